@@ -1,0 +1,116 @@
+/*
+ * CPU ORACLE -- test infrastructure only.
+ *
+ * A plain, serial, FP64 implementation of what the GPU solver computes, used
+ * to check it.  Only the tests, the smoke check and the benchmark's CPU
+ * baseline leg may load it; the product path never does.  It shares no code
+ * with the GPU library: its own storage (block CSR), its own generic IKJ
+ * ILU(0), its own Krylov drivers.
+ *
+ * What each routine follows:
+ *  - operations y = A x, <x,y>, ||x||: the paper's "Algebraic Operations"
+ *    subsection (distributed matrices and vectors);
+ *  - ILU: "LU x = b <=> L y = b, U x = y" solved row by row (Preconditioners,
+ *    Restricted Additive Schwarz subsection), with ILU(0) as the default local
+ *    solver (RAS default-parameter figure); the factorisation is the textbook
+ *    IKJ ILU(0) (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed.,
+ *    sec. 10.3) with 3x3 blocks, divides replaced by right-multiplication by
+ *    the pivot block's inverse;
+ *  - RAS: restricted additive Schwarz of Cai & Sarkis (1999), the paper's
+ *    [DDM] citation, overlap 1 by default;
+ *  - GMRES(m): Saad & Schultz (1986), right preconditioned, classical
+ *    Gram-Schmidt applied twice, Givens rotations;
+ *  - BiCGSTAB: van der Vorst (1992), right preconditioned;
+ *  - FGMRES: Saad (1993), with a fallback preconditioner.
+ * Parity status of each routine is recorded in the tests that pin it.
+ */
+#ifndef RSV_ORACLE_H
+#define RSV_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORC_OK = 0,
+    ORC_NOT_CONVERGED = 1,
+    ORC_BREAKDOWN = 2,
+    ORC_ERR_ARG = -1,
+    ORC_ERR_OOM = -2,
+    ORC_ERR_ZERO_PIVOT = -4,
+    ORC_ERR_NAN = -5,
+    ORC_ERR_PATTERN = -6,
+};
+
+/* Block CSR, 3x3 blocks stored row-major, columns ascending in each row. */
+typedef struct orc_bcsr {
+    int64_t n;        /* block rows */
+    int64_t nnzb;
+    int64_t *rowptr;  /* n+1 */
+    int64_t *col;     /* nnzb */
+    double  *val;     /* 9*nnzb */
+} orc_bcsr;
+
+typedef int (*orc_apply_fn)(void *ctx, const double *in, double *out);
+
+typedef struct orc_stats {
+    int64_t its;         /* Arnoldi steps (GMRES/FGMRES) or iterations (BiCGSTAB) */
+    int64_t restarts;    /* completed GMRES cycles */
+    int64_t fallbacks;   /* FGMRES columns recomputed with the fallback */
+    double  final_relres;/* recomputed ||b - A x|| / ||b|| */
+    int64_t bad_cell;    /* block row of a zero pivot, else -1 */
+} orc_stats;
+
+/* ---- storage ---- */
+int  orc_bcsr_from_stencil(int32_t nx, int32_t ny, int32_t nz, const double *blocks, orc_bcsr **out);
+int  orc_bcsr_from_dense_pattern(int64_t n, const int64_t *rowptr, const int64_t *col, const double *val, orc_bcsr **out);
+void orc_bcsr_free(orc_bcsr *A);
+int64_t orc_bcsr_nnzb(const orc_bcsr *A);
+/* copy out rowptr/col/val (sizes n+1, nnzb, 9*nnzb) */
+void orc_bcsr_export(const orc_bcsr *A, int64_t *rowptr, int64_t *col, double *val);
+
+/* ---- algebraic operations ---- */
+void   orc_spmv(const orc_bcsr *A, const double *x, double *y);            /* y = A x */
+double orc_dot(int64_t n, const double *x, const double *y);
+double orc_nrm2(int64_t n, const double *x);
+
+/* ---- ILU(0) ---- */
+typedef struct orc_ilu orc_ilu;
+int  orc_ilu0(const orc_bcsr *A, orc_ilu **out, int64_t *bad_cell);
+void orc_ilu_free(orc_ilu *F);
+const orc_bcsr *orc_ilu_factors(const orc_ilu *F);   /* strict lower = L, upper incl. diagonal = U */
+int  orc_ilu_apply(void *F, const double *r, double *z);    /* z = (LU)^{-1} r */
+int  orc_ilu_apply_f32(void *F, const double *r, double *z);/* FP32 factors + FP32 sweeps */
+
+/* ---- RAS ---- */
+typedef struct orc_ras orc_ras;
+int  orc_ras_setup(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
+                   int32_t px, int32_t py, int32_t pz, int32_t overlap,
+                   orc_ras **out, int64_t *bad_cell);
+void orc_ras_free(orc_ras *R);
+int  orc_ras_apply(void *R, const double *r, double *z);
+int64_t orc_ras_nsub(const orc_ras *R);
+int64_t orc_ras_sub_size(const orc_ras *R, int64_t s);           /* |Omega_s| */
+void orc_ras_sub_cells(const orc_ras *R, int64_t s, int64_t *cells); /* ascending */
+void orc_ras_owner(const orc_ras *R, int64_t *owner);            /* per cell */
+
+/* ---- Krylov ---- */
+int orc_gmres(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
+              const double *b, double *x, int32_t m, double tol, int64_t maxit,
+              orc_stats *st, double *hist /* nullable, length maxit+1 */);
+int orc_bicgstab(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
+                 const double *b, double *x, double tol, int64_t maxit,
+                 orc_stats *st, double *hist);
+int orc_fgmres(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
+               orc_apply_fn fb, void *fb_ctx, double theta,
+               const double *b, double *x, int32_t m, double tol, int64_t maxit,
+               orc_stats *st, double *hist);
+
+/* plain dense 3x3 helpers exposed for the pins */
+int orc_inv3(const double *a, double *ainv);  /* LU with partial pivoting; 0 ok, -4 singular */
+
+#ifdef __cplusplus
+}
+#endif
+#endif
