@@ -1,0 +1,230 @@
+#!/usr/bin/env python
+"""Benchmark: time-to-solve of the 3x3-block 7-point reservoir Jacobian on one
+MI355X, with the dominant kernel's achieved HBM bandwidth against the roofline
+and the CPU oracle timed beside it.
+
+Workload (default C2): 128x128x64 cells (3,145,728 unknowns), layered
+log-normal permeability (layer mean ~ N(0,1.5), cell noise ~ N(0,2)), four
+source cells, b = A x_true, x0 = 0, tol 1e-8 on the recomputed FP64 relative
+residual.  One step = assemble the block matrix, then for each solver form:
+preconditioner setup + solve.  Forms: BiCGSTAB + BILU0 (the headline
+time-to-solve), GMRES(30) + RAS(4x4x4 subdomains, overlap 1, ILU(0)),
+GMRES(30) + BILU0 with FP64 factors, GMRES(30) + BILU0 with FP32 factors,
+and FGMRES(30) + the learned U-Net preconditioner when a trained network
+is given (--net).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(nx, ny, nz):
+    """Bytes each kernel must move per launch (stored blocks only, no padding,
+    no re-reads), FP64."""
+    c = nx * ny * nz
+    N = 3 * c
+    nl = (nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1)   # lower (= upper) neighbour pairs
+    nnzb = 2 * nl + c
+    return {
+        "nnzb": nnzb,
+        "spmv": 72 * nnzb + 24 * N,            # A, x, y, plus the fused epilogue operand (b, rhat or s)
+        "ilu_fwd": 72 * nl + 16 * N,            # L blocks, r in, y out
+        "ilu_bwd": 72 * (nl + c) + 16 * N,      # U blocks + D^-1, y in, z out
+        "ilu_apply": 72 * nnzb + 32 * N,
+        "spmv_plain": 72 * nnzb + 16 * N,
+    }
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="bicgstab_bilu0,gmres_ras64,gmres_bilu0,gmres_bilu0_fp32")
+    ap.add_argument("--net", default=None, help="trained U-Net weights for the learned form")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1602_05901_amd import inputs as I
+    from paper_1602_05901_amd import rsv
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cfg = I.preset(args.workload, seed=args.seed)
+    t0 = time.time()
+    lnk = I.lnk(cfg)
+    B = I.blocks(cfg, lnk)
+    xt = I.x_true(cfg)
+    log(f"generated {args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} in {time.time() - t0:.1f}s")
+    Bd = torch.from_numpy(B).to(dev)
+    xtd = torch.from_numpy(xt).to(dev)
+    ctx = rsv.Context(0)
+    g = rsv.Grid(ctx, cfg.nx, cfg.ny, cfg.nz)
+    A = rsv.Matrix(g, Bd)
+    b = torch.zeros_like(xtd)
+    A.spmv(xtd, b)          # manufactured right-hand side, on the GPU
+    torch.cuda.synchronize()
+
+    forms_all = {
+        "bicgstab_bilu0": (rsv.BICGSTAB, dict(type=rsv.PC_BILU0)),
+        "gmres_ras64": (rsv.GMRES, dict(type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1)),
+        "gmres_bilu0": (rsv.GMRES, dict(type=rsv.PC_BILU0)),
+        "gmres_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_BILU0, precision=rsv.FP32)),
+    }
+    forms = [f for f in args.forms.split(",") if f]
+    net = None
+    lnk32 = None
+    if args.net:
+        net = rsv.Net(ctx)
+        net.load(args.net)
+        lnk32 = torch.from_numpy(lnk.astype(np.float32)).to(dev)
+        forms_all["fgmres_learned"] = (rsv.FGMRES, dict(type=rsv.PC_LEARNED, net=net, lnk=lnk32))
+        forms.append("fgmres_learned")
+
+    def step(profile_headline=False):
+        out = {}
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        A.update(Bd)
+        torch.cuda.synchronize()
+        out["assemble_s"] = time.perf_counter() - ta
+        for name in forms:
+            method, pkw = forms_all[name]
+            prof = profile_headline and name == forms[0]
+            t1 = time.perf_counter()
+            M = rsv.Precond(A, **pkw)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            x = torch.zeros_like(b)
+            if prof:
+                ctx.profile(True)
+            st = rsv.solve(A, M, b, x, method=method, restart=30, tol=1e-8, maxit=10000)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if prof:
+                out["kernels"] = ctx.profile_read()
+                ctx.profile(False)
+            err = float(torch.linalg.norm(x - xtd) / torch.linalg.norm(xtd))
+            out[name] = {"setup_s": t2 - t1, "solve_s": t3 - t2, "its": st["its"], "relres": st["final_relres"],
+                         "status": st["status"], "err_vs_xtrue": err, "fallbacks": st["fallbacks"]}
+            M.close()
+            assert st["status"] == rsv.OK and st["final_relres"] <= 1e-8, (name, st)
+        return out
+
+    for w in range(args.warmup):
+        r = step()
+        log(f"warmup {w}: " + ", ".join(f"{k} {r[k]['solve_s'] * 1e3:.1f}ms/{r[k]['its']}its" for k in forms))
+    torch.cuda.synchronize()
+    res = []
+    tt = time.perf_counter()
+    for s in range(args.steps):
+        r = step(profile_headline=True)
+        res.append(r)
+        log(f"step {s}: " + ", ".join(f"{k} {r[k]['solve_s'] * 1e3:.1f}ms/{r[k]['its']}its" for k in forms))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - tt
+
+    def med(key, sub):
+        return float(np.median([r[key][sub] for r in res]))
+
+    head = forms[0]
+    summary = {f: {"solve_s": med(f, "solve_s"), "setup_s": med(f, "setup_s"), "its": res[-1][f]["its"],
+                   "relres": res[-1][f]["relres"], "err_vs_xtrue": res[-1][f]["err_vs_xtrue"],
+                   "fallbacks": res[-1][f]["fallbacks"]} for f in forms}
+    # live kernel timing (HIP events on the solver stream) over the headline solves
+    kms = {k: sum(r["kernels"][k][0] for r in res) for k in rsv.K_NAMES}
+    kcnt = {k: sum(r["kernels"][k][1] for r in res) for k in rsv.K_NAMES}
+    ab = algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz)
+    cand = [k for k in ("spmv", "ilu_fwd", "ilu_bwd") if kcnt[k] > 0]
+    dom = max(cand, key=lambda k: kms[k])
+    avg_ms = kms[dom] / kcnt[dom]
+    achieved = ab[dom] / (avg_ms * 1e-3) / 1e9
+    kernels = {k: {"avg_us": 1e3 * kms[k] / kcnt[k], "launches": kcnt[k],
+                   "GBps": (ab[k] / (kms[k] / kcnt[k] * 1e-3) / 1e9) if k in ab else None}
+               for k in rsv.K_NAMES if kcnt[k] > 0}
+    ilu_ms = (kms["ilu_fwd"] + kms["ilu_bwd"]) / max(kcnt["ilu_fwd"], 1)
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        try:
+            tj = json.load(open(tpath))
+            if tj.get("kernel") == dom and tj.get("workload") == args.workload:
+                traffic = tj.get("bytes_per_launch")
+        except Exception:  # noqa: BLE001
+            traffic = None
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": ab[dom], "avg_launch_us": round(avg_ms * 1e3, 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        os.environ.setdefault("OMP_NUM_THREADS", "1")
+        t0 = time.perf_counter()
+        Ao = O.BCSR.from_stencil(cfg.nx, cfg.ny, cfg.nz, B)
+        bo = Ao.spmv(xt)
+        t1 = time.perf_counter()
+        F = O.ILU(Ao)
+        ro = O.bicgstab(Ao, bo, pc=F, tol=1e-8, maxit=10000)
+        t2 = time.perf_counter()
+        cpu = {"value": round(t2 - t1, 3), "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"full {args.workload} BiCGSTAB+BILU0 solve (ILU(0) setup + {ro['its']} iterations, "
+                         f"relres {ro['relres']:.2e}), serial FP64 C on one host thread"}
+        log(f"oracle: {t2 - t1:.2f}s ({ro['its']} its)")
+
+    value = summary[head]["solve_s"]
+    line = {
+        "metric": "time-to-solve to 1e-8 FP64 rel. residual (s), SpMV/ILU HBM GB/s; learned/FP32 vs plain",
+        "value": round(value, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} 3x3-block 7-point, "
+                               f"headline {head}, tol 1e-8", "unknowns": 3 * cfg.ncell,
+                   "forms": forms, "seed": args.seed},
+        "solves": summary,
+        "ilu_apply_GBps": round(ab["ilu_apply"] / (ilu_ms * 1e-3) / 1e9, 1) if kcnt["ilu_fwd"] else None,
+        "spmv_GBps": kernels.get("spmv", {}).get("GBps"),
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "device_bytes": A.device_bytes,
+    }
+    print(json.dumps(line), flush=True)
+    A.close(); g.close(); ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,246 @@
+/*
+ * rsv -- preconditioned Krylov solver for 3x3-block, 7-point-stencil
+ * reservoir Jacobians on one MI355X (gfx950).  C ABI.
+ *
+ * The calls follow the paper's problem statement (arxiv 1602.05901):
+ * a structured grid nx*ny*nz (Grid section), a cell -> row map (MAP section),
+ * an assembled block matrix (Distributed Matrices and Vectors section), a
+ * preconditioner with setup / apply / destroy hooks (Preconditioners section,
+ * SOLVER_PC and PC_TYPE figures) and a solver with rtol / maxit / restart
+ * (Solvers section, SOLVER figure).
+ *
+ * Conventions (every call):
+ *  - Every call returns an rsv_status.  RSV_OK = 0; positive values are
+ *    warnings whose outputs are still filled; negative values are errors.
+ *    No C++ exception crosses this boundary.
+ *  - The caller owns every buffer it passes.  Handles own their device
+ *    memory until the matching *_destroy.  Destroy in the order
+ *    precond -> matrix -> grid -> net -> ctx.
+ *  - Vectors are FP64, contiguous, length 3*ncell, in block-row order with
+ *    the three unknowns of a cell interleaved (row = 3*block_row + comp).
+ *    Vector pointers are DEVICE pointers unless a call says otherwise.
+ *  - All device work is enqueued on the context's stream (rsv_set_stream);
+ *    calls that return scalars synchronise that stream before returning.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef RSV_H
+#define RSV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rsv_status;
+enum {
+    RSV_OK = 0,
+    RSV_NOT_CONVERGED = 1,   /* maxit reached: x holds the last iterate, stats filled */
+    RSV_BREAKDOWN = 2,       /* BiCGSTAB rho = 0 or omega = 0: x holds the current iterate */
+    RSV_ERR_ARG = -1,        /* invalid argument (null handle, bad size, bad enum) */
+    RSV_ERR_OOM = -2,        /* device or host allocation failed */
+    RSV_ERR_HIP = -3,        /* a HIP runtime call failed (rsv_last_error has the text) */
+    RSV_ERR_ZERO_PIVOT = -4, /* singular or near-singular 3x3 pivot; stats.bad_cell names it */
+    RSV_ERR_NAN = -5,        /* NaN/Inf in the right-hand side, x0 or a recurrence */
+    RSV_ERR_PATTERN = -6,    /* nonzero block in a stencil slot whose neighbour is outside the grid */
+    RSV_ERR_TIMEOUT = -7     /* a wavefront kernel's bounded wait expired (should not happen) */
+};
+
+typedef enum {
+    RSV_BOTTOM_UP = 0,   /* block_row = nx*ny*k + nx*j + i (Grid section, default numbering) */
+    RSV_TOP_DOWN = 1     /* block_row = nx*ny*(nz-1-k) + nx*j + i (the top-to-bottom numbering,
+                            read with nz-1-k so that rows stay in [0, ncell)) */
+} rsv_ordering;
+
+typedef enum { RSV_MEM_HOST = 0, RSV_MEM_DEVICE = 1 } rsv_mem;
+
+/* Preconditioner kinds; mirrors the paper's PC_TYPE (RAS, ..., USER, NON). */
+typedef enum {
+    RSV_PC_NONE = 0,
+    RSV_PC_BILU0 = 1,    /* global block ILU(0) in natural (bottom-up) order */
+    RSV_PC_RAS = 2,      /* restricted additive Schwarz, local block ILU(0) */
+    RSV_PC_LEARNED = 3   /* user-type preconditioner: the U-Net, BILU0 fallback (FGMRES only) */
+} rsv_pc_type;
+
+typedef enum { RSV_FP64 = 0, RSV_FP32 = 1 } rsv_precision;
+
+typedef enum { RSV_GMRES = 0, RSV_BICGSTAB = 1, RSV_FGMRES = 2 } rsv_method;
+
+typedef struct rsv_ctx rsv_ctx;
+typedef struct rsv_grid rsv_grid;
+typedef struct rsv_matrix rsv_matrix;
+typedef struct rsv_precond rsv_precond;
+typedef struct rsv_net rsv_net;
+
+/* Preconditioner parameters.  Defaults (rsv_pc_params_default) follow the
+ * paper's RAS default-parameter figure: overlap 1, ILU level 0. */
+typedef struct rsv_pc_params {
+    int32_t type;        /* rsv_pc_type */
+    int32_t precision;   /* rsv_precision of the stored factors and triangular sweeps */
+    int32_t ras_px, ras_py, ras_pz;  /* RAS: subdomain boxes per axis (default 4,4,4) */
+    int32_t ras_overlap; /* RAS: matrix-graph overlap distance (default 1) */
+    int32_t iluk_level;  /* must be 0 (ILU(0)); kept to mirror RAS_PARS */
+    int32_t pipelined;   /* 1 (default): sync-free tiled wavefront sweeps; 0: one launch per hyperplane */
+    rsv_net *net;        /* LEARNED: trained network (not owned) */
+    const float *lnk;    /* LEARNED: DEVICE pointer, ln k per cell in block-row order (not copied; must outlive the precond) */
+    double theta;        /* LEARNED: fallback when a step's residual estimate exceeds theta * previous (default 0.99) */
+    int32_t reserved[8];
+} rsv_pc_params;
+
+/* Solver parameters; mirrors SOLVER (rtol, atol, maxit, restart). */
+typedef struct rsv_solver_params {
+    int32_t method;      /* rsv_method */
+    int32_t restart;     /* GMRES/FGMRES cycle length m (default 30, max 60) */
+    double tol;          /* stop when the recomputed ||b - A x||_2 / ||b||_2 <= tol (default 1e-8) */
+    int64_t maxit;       /* Arnoldi steps (GMRES/FGMRES) or iterations (BiCGSTAB); default 10000 */
+    double rtol;         /* optional, 0 = off: stop when ||r|| <= rtol * ||r0|| */
+    double atol;         /* optional, 0 = off: stop when ||r|| <= atol */
+    int32_t record_history;  /* 1: keep per-step residual estimates (rsv_solve_history) */
+    int32_t reserved[7];
+} rsv_solver_params;
+
+typedef struct rsv_stats {
+    int64_t its;          /* Arnoldi steps or BiCGSTAB iterations performed */
+    int64_t restarts;     /* completed GMRES cycles */
+    int64_t fallbacks;    /* FGMRES columns computed with the fallback preconditioner */
+    double final_relres;  /* recomputed ||b - A x|| / ||b|| at exit */
+    double solve_ms;      /* wall time of the call (host clock, after the final sync) */
+    int64_t bad_cell;     /* block row of a zero pivot, else -1 */
+    int32_t status;       /* same as the return value */
+    int32_t reserved;
+} rsv_stats;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device_ordinal`; work goes to the null
+ * stream until rsv_set_stream.  Errors: RSV_ERR_ARG (bad ordinal), RSV_ERR_HIP. */
+rsv_status rsv_create(int32_t device_ordinal, rsv_ctx **out);
+/* Enqueue all later work on `hip_stream` (a hipStream_t, e.g. torch's
+ * current_stream().cuda_stream); NULL selects the null stream. */
+rsv_status rsv_set_stream(rsv_ctx *ctx, void *hip_stream);
+void rsv_destroy(rsv_ctx *ctx);
+const char *rsv_status_str(rsv_status s);
+/* Text of the last error recorded on ctx (empty string if none; ctx may be NULL). */
+const char *rsv_last_error(const rsv_ctx *ctx);
+/* ABI version: major*10000 + minor*100 + patch. */
+int32_t rsv_version(void);
+
+/* ---------------------------------------------------------------- grid and MAP */
+
+/* Structured grid nx*ny*nz (Grid section); nx, ny, nz >= 1 and
+ * nx*ny*nz*3 < 2^31.  Errors: RSV_ERR_ARG. */
+rsv_status rsv_grid_create(rsv_ctx *ctx, int32_t nx, int32_t ny, int32_t nz,
+                           int32_t ordering /* rsv_ordering */, rsv_grid **out);
+void rsv_grid_destroy(rsv_grid *g);
+int64_t rsv_grid_ncell(const rsv_grid *g);
+/* Cell -> block row under the grid's ordering (MAP section); the scalar row of
+ * component c is 3*block_row + c.  Errors: RSV_ERR_ARG (out of range). */
+rsv_status rsv_cell_to_row(const rsv_grid *g, int32_t i, int32_t j, int32_t k, int64_t *block_row);
+rsv_status rsv_row_to_cell(const rsv_grid *g, int64_t block_row, int32_t *i, int32_t *j, int32_t *k);
+
+/* ---------------------------------------------------------------- matrix */
+
+/* Assemble the block matrix (Distributed Matrices section) from
+ * blocks[ncell][7][3][3] (row-major 3x3), rows in block-row order, slots by
+ * direction: 0:-z 1:-y 2:-x 3:diagonal 4:+x 5:+y 6:+z.  `where` says whether
+ * `blocks` is a host or a device pointer.  The library copies the values.
+ * Errors: RSV_ERR_ARG, RSV_ERR_OOM, RSV_ERR_PATTERN (nonzero block toward a
+ * missing neighbour), RSV_ERR_NAN, RSV_ERR_HIP. */
+rsv_status rsv_matrix_assemble(rsv_grid *g, const double *blocks, int32_t where, rsv_matrix **out);
+/* New values, same grid (next Newton step).  Preconditioners built on the
+ * old values must be set up again.  Errors as for assemble. */
+rsv_status rsv_matrix_update(rsv_matrix *A, const double *blocks, int32_t where);
+void rsv_matrix_destroy(rsv_matrix *A);
+/* y = alpha*A*x + beta*y (Algebraic Operations: y = alpha A x + beta y);
+ * x, y device vectors of length 3*ncell (must not alias). */
+rsv_status rsv_spmv(rsv_matrix *A, double alpha, const double *x, double beta, double *y);
+/* Device bytes held by the matrix and everything built on it (diagnostics). */
+int64_t rsv_matrix_device_bytes(const rsv_matrix *A);
+
+/* ---------------------------------------------------------------- preconditioner */
+
+void rsv_pc_params_default(rsv_pc_params *p);
+/* Build the preconditioner (SOLVER_PC assemble hook): BILU0 factorisation,
+ * RAS subdomains + local factorisations, or the learned network plus its
+ * BILU0 fallback.  Errors: RSV_ERR_ARG, RSV_ERR_OOM, RSV_ERR_ZERO_PIVOT
+ * (the offending block row is written to *bad_cell if non-NULL), RSV_ERR_HIP. */
+rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond **out, int64_t *bad_cell);
+/* z = M^{-1} r (SOLVER_PC solve hook); r, z device vectors, may not alias.
+ * For LEARNED this applies the network (no fallback). */
+rsv_status rsv_precond_apply(rsv_precond *M, const double *r, double *z);
+void rsv_precond_destroy(rsv_precond *M);
+
+/* ---------------------------------------------------------------- solver */
+
+void rsv_solver_params_default(rsv_solver_params *p);
+/* Solve A x = b (Linear System section).  b: device, length 3*ncell.
+ * x: device, in: x0, out: the solution or last iterate.  M may be NULL
+ * (no preconditioner).  Returns RSV_OK when the recomputed FP64 relative
+ * residual meets tol (or rtol/atol), RSV_NOT_CONVERGED after maxit,
+ * RSV_BREAKDOWN, or an error.  `st` may be NULL. */
+rsv_status rsv_solve(rsv_matrix *A, rsv_precond *M, const rsv_solver_params *p,
+                     const double *b, double *x, rsv_stats *st);
+/* Residual estimates per step of the last solve with record_history = 1:
+ * hist[0] = initial relative residual, hist[s] after step s.  Writes at most
+ * cap values to the HOST array hist; returns how many exist. */
+int64_t rsv_solve_history(const rsv_matrix *A, double *hist, int64_t cap);
+
+/* ---------------------------------------------------------------- learned preconditioner */
+
+/* U-Net architecture: 3 levels, channels c0/c1/c2 (default 16/32/64),
+ * 3x3x3 kernels, 4 input channels (3 residual components + ln k), 3 outputs. */
+typedef struct rsv_net_arch {
+    int32_t levels;      /* must be 3 */
+    int32_t c0, c1, c2;  /* channels per level */
+    int32_t reserved[4];
+} rsv_net_arch;
+
+/* Create a network with seeded random weights.  Errors: RSV_ERR_ARG, RSV_ERR_OOM. */
+rsv_status rsv_net_create(rsv_ctx *ctx, const rsv_net_arch *arch, uint64_t seed, rsv_net **out);
+void rsv_net_destroy(rsv_net *net);
+/* Number of parameters and FP32 master copies of them (HOST arrays). */
+int64_t rsv_net_num_params(const rsv_net *net);
+rsv_status rsv_net_get_params(rsv_net *net, float *host_out, int64_t n);
+rsv_status rsv_net_set_params(rsv_net *net, const float *host_in, int64_t n);
+rsv_status rsv_net_save(rsv_net *net, const char *path);
+rsv_status rsv_net_load(rsv_net *net, const char *path);
+/* Inference z = ||r||_rms * N(r / ||r||_rms, lnk) on grid g.  r, z: device
+ * FP64 vectors (block-row order); lnk: device FP32 per cell (standardised
+ * inside).  Errors: RSV_ERR_ARG (grid dims not multiples of 4). */
+rsv_status rsv_net_forward(rsv_net *net, rsv_grid *g, const double *r, const float *lnk, double *z);
+/* One Adam step on a batch of `nb` samples on grid g: inputs r[nb][3*ncell]
+ * (device FP64), targets e[nb][3*ncell] (device FP64), lnk[nb][ncell]
+ * (device FP32).  Loss = mean_b ||N(r_b/s_b) - e_b/s_b||^2 / ||e_b/s_b||^2
+ * with s_b = rms(r_b).  The loss is written to *loss_out (host). */
+rsv_status rsv_net_train_step(rsv_net *net, rsv_grid *g, int32_t nb, const double *r, const double *e,
+                              const float *lnk, float lr, float *loss_out);
+/* Forward + backward without the update: loss and the gradient of every
+ * parameter (HOST array of rsv_net_num_params floats).  For gradient checks. */
+rsv_status rsv_net_loss_grad(rsv_net *net, rsv_grid *g, int32_t nb, const double *r, const double *e,
+                             const float *lnk, float *loss_out, float *grad_out);
+
+/* ---------------------------------------------------------------- kernel timing (diagnostics) */
+
+/* Kernel classes timed with HIP events recorded on the context stream
+ * around each launch while profiling is enabled. */
+enum {
+    RSV_K_SPMV = 0,      /* block SpMV (all fused epilogues) */
+    RSV_K_ILU_FWD = 1,   /* BILU0 forward sweep */
+    RSV_K_ILU_BWD = 2,   /* BILU0 backward sweep */
+    RSV_K_RAS = 3,       /* RAS apply (both sweeps of every subdomain) */
+    RSV_K_ORTHO = 4,     /* CGS2 multi-dot / update / normalise kernels */
+    RSV_K_VEC = 5,       /* other vector kernels (BiCGSTAB updates, copies, reductions) */
+    RSV_K_FACTOR = 6,    /* factorisations */
+    RSV_K_NET = 7,       /* U-Net kernels */
+    RSV_K_COUNT = 8
+};
+/* on = 1 starts (and zeroes) the per-class totals, on = 0 stops recording. */
+rsv_status rsv_profile_enable(rsv_ctx *ctx, int32_t on);
+/* Synchronises the stream and writes per-class total milliseconds and launch
+ * counts (HOST arrays of RSV_K_COUNT entries; either may be NULL). */
+rsv_status rsv_profile_read(rsv_ctx *ctx, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSV_H */

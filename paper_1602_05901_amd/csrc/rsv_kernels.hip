@@ -1,0 +1,555 @@
+// Bandwidth-bound kernels on the tile-lane layout: block SpMV with fused
+// epilogues, layout permutes, assembly, and the vector operations of the
+// Krylov drivers (Algebraic Operations: y = aAx + by, y = ax + by, <x,y>,
+// ||x||) with deterministic two-stage reductions.
+#include "rsv_internal.h"
+
+#include <algorithm>
+
+namespace {
+
+constexpr int BS = 256;          // threads per block for streaming kernels
+constexpr int RED_T = 1024;      // threads of the final reduction
+
+// Sum of v over the block (deterministic butterfly + fixed-order LDS pass);
+// result valid in thread 0.
+__device__ inline double block_sum(double v, double *lds)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < nw; ++q) s += lds[q];
+    return s;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(BS) void k_spmv(Geo g, const double *__restrict__ A, const double *__restrict__ x,
+                                             double *__restrict__ y, const double *__restrict__ aux1,
+                                             double alpha, double beta, double *__restrict__ partials)
+{
+    __shared__ double lds[16];
+    const int64_t slot = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const bool valid = slot < g.nslot;
+    int gx = 0, gy = 0, k = 0;
+    const bool real = valid && cell_of(g, slot, gx, gy, k);
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    if (real) {
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+            int di, dj, dk;
+            dir_off(s, di, dj, dk);
+            const int ax = gx + di, ay = gy + dj, az = k + dk;
+            double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+            if (ax >= 0 && ax < g.nx && ay >= 0 && ay < g.ny && az >= 0 && az < g.nz) {
+                const int64_t ns = (s == 3) ? slot : slot_of(g, ax, ay, az);
+                x0 = x[vidx(ns, 0)];
+                x1 = x[vidx(ns, 1)];
+                x2 = x[vidx(ns, 2)];
+            }
+            const double *a = A + aidx(slot, s * 9);
+            acc0 += a[0 * 64] * x0 + a[1 * 64] * x1 + a[2 * 64] * x2;
+            acc1 += a[3 * 64] * x0 + a[4 * 64] * x1 + a[5 * 64] * x2;
+            acc2 += a[6 * 64] * x0 + a[7 * 64] * x1 + a[8 * 64] * x2;
+        }
+    }
+    double r0 = 0.0, r1 = 0.0;
+    if (valid) {
+        double o0 = acc0, o1 = acc1, o2 = acc2;
+        const int64_t i0 = vidx(slot, 0), i1 = vidx(slot, 1), i2 = vidx(slot, 2);
+        if (MODE == SPMV_AXPBY) {
+            o0 *= alpha; o1 *= alpha; o2 *= alpha;
+            if (beta != 0.0) { o0 += beta * y[i0]; o1 += beta * y[i1]; o2 += beta * y[i2]; }
+        } else if (MODE == SPMV_RESID) {
+            o0 = aux1[i0] - acc0; o1 = aux1[i1] - acc1; o2 = aux1[i2] - acc2;
+        }
+        y[i0] = o0; y[i1] = o1; y[i2] = o2;
+        if (MODE == SPMV_RESID || MODE == SPMV_NORM) r0 = o0 * o0 + o1 * o1 + o2 * o2;
+        if (MODE == SPMV_DOT1 || MODE == SPMV_DOT2) r0 = aux1[i0] * o0 + aux1[i1] * o1 + aux1[i2] * o2;
+        if (MODE == SPMV_DOT2) r1 = o0 * o0 + o1 * o1 + o2 * o2;
+    }
+    if (MODE >= SPMV_RESID) {
+        const int K = (MODE == SPMV_DOT2) ? 2 : 1;
+        double s0 = block_sum(r0, lds);
+        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * K] = s0;
+        if (MODE == SPMV_DOT2) {
+            double s1 = block_sum(r1, lds);
+            if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * K + 1] = s1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(RED_T) void k_reduce(const double *__restrict__ partials, int nb, int K,
+                                                 double *__restrict__ out)
+{
+    __shared__ double lds[16];
+    for (int kk = 0; kk < K; ++kk) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += RED_T) s += partials[(int64_t)b * K + kk];
+        s = block_sum(s, lds);
+        if (threadIdx.x == 0) out[kk] = s;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_nat_to_tl(Geo g, const double *__restrict__ nat, double *__restrict__ tl)
+{
+    const int64_t slot = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (slot >= g.nslot) return;
+    int gx, gy, k;
+    const bool real = cell_of(g, slot, gx, gy, k);
+    const int64_t row = real ? row_of(g, gx, gy, k) : 0;
+    for (int p = 0; p < 3; ++p) tl[vidx(slot, p)] = real ? nat[3 * row + p] : 0.0;
+}
+
+__global__ __launch_bounds__(BS) void k_tl_to_nat(Geo g, const double *__restrict__ tl, double *__restrict__ nat,
+                                                  double alpha, double beta)
+{
+    const int64_t slot = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (slot >= g.nslot) return;
+    int gx, gy, k;
+    if (!cell_of(g, slot, gx, gy, k)) return;
+    const int64_t row = row_of(g, gx, gy, k);
+    for (int p = 0; p < 3; ++p) {
+        double v = alpha * tl[vidx(slot, p)];
+        if (beta != 0.0) v += beta * nat[3 * row + p];
+        nat[3 * row + p] = v;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_assemble(Geo g, const double *__restrict__ blocks, double *__restrict__ A,
+                                                 int32_t *flags)
+{
+    const int64_t slot = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (slot >= g.nslot) return;
+    int gx, gy, k;
+    const bool real = cell_of(g, slot, gx, gy, k);
+    const int64_t row = real ? row_of(g, gx, gy, k) : 0;
+    int bad = 0;
+    for (int s = 0; s < 7; ++s) {
+        int di, dj, dk;
+        dir_off(s, di, dj, dk);
+        const bool exists = real && gx + di >= 0 && gx + di < g.nx && gy + dj >= 0 && gy + dj < g.ny &&
+                            k + dk >= 0 && k + dk < g.nz;
+        for (int e = 0; e < 9; ++e) {
+            const double v = real ? blocks[row * 63 + s * 9 + e] : 0.0;
+            if (!isfinite(v)) bad |= FLAG_NAN;
+            if (real && !exists && v != 0.0) bad |= FLAG_PATTERN;
+            A[aidx(slot, s * 9 + e)] = exists ? v : 0.0;
+        }
+    }
+    if (bad) atomicOr(&flags[0], bad);
+}
+
+// ---------------------------------------------------------------- vector ops
+
+__global__ __launch_bounds__(BS) void k_dot(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                                            double *__restrict__ partials)
+{
+    __shared__ double lds[16];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) s += x[e] * y[e];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_nonfinite(int64_t n, const double *__restrict__ x, double *__restrict__ partials)
+{
+    __shared__ double lds[16];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS)
+        s += isfinite(x[e]) ? 0.0 : 1.0;
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_copy(int64_t n, const double *__restrict__ x, double *__restrict__ y)
+{
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) y[e] = x[e];
+}
+
+__global__ __launch_bounds__(BS) void k_scale_dev(int64_t n, double *__restrict__ x, const double *__restrict__ sc)
+{
+    const double nn = sc[0];
+    const double f = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) x[e] *= f;
+}
+
+__global__ __launch_bounds__(BS) void k_axpby(int64_t n, double a, const double *__restrict__ x, double b,
+                                              double *__restrict__ y)
+{
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS)
+        y[e] = (b == 0.0) ? a * x[e] : a * x[e] + b * y[e];
+}
+
+constexpr int KMAX = 64;   // max vectors in a multi-dot (GMRES restart <= 60)
+
+// partial dots V_i . w for i < K (+ w.w when ww)
+template <int KB>
+__global__ __launch_bounds__(BS) void k_mdot(int64_t n, const double *__restrict__ V, int64_t ldv, int K,
+                                             const double *__restrict__ w, double *__restrict__ partials)
+{
+    __shared__ double lds[16];
+    double acc[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) acc[i] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
+        const double we = w[e];
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+            if (i < K) acc[i] += V[i * ldv + e] * we;
+    }
+    for (int i = 0; i < K; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < KB; ++q)
+            if (q == i) s = acc[q];
+        s = block_sum(s, lds);
+        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * K + i] = s;
+    }
+}
+
+// w -= sum_i c_i V_i (c_i = sc[kc+i], ascending i); then partial V_i . w (MODE 0) or w.w (MODE 1)
+template <int KB, int MODE>
+__global__ __launch_bounds__(BS) void k_upd(int64_t n, const double *__restrict__ V, int64_t ldv, int K,
+                                            double *__restrict__ w, const double *__restrict__ c,
+                                            double *__restrict__ partials)
+{
+    __shared__ double lds[16];
+    double coef[KB];
+    double acc[MODE == 0 ? KB : 1];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) coef[i] = (i < K) ? c[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < (MODE == 0 ? KB : 1); ++i) acc[i] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
+        double v[KB];
+        double we = w[e];
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+            if (i < K) {
+                v[i] = V[i * ldv + e];
+                we -= coef[i] * v[i];
+            }
+        w[e] = we;
+        if (MODE == 0) {
+#pragma unroll
+            for (int i = 0; i < KB; ++i)
+                if (i < K) acc[i] += v[i] * we;
+        } else {
+            acc[0] += we * we;
+        }
+    }
+    const int nout = (MODE == 0) ? K : 1;
+    for (int i = 0; i < nout; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < (MODE == 0 ? KB : 1); ++q)
+            if (q == i) s = acc[q];
+        s = block_sum(s, lds);
+        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * nout + i] = s;
+    }
+}
+
+template <int KB>
+__global__ __launch_bounds__(BS) void k_combine(int64_t n, const double *__restrict__ V, int64_t ldv, int K,
+                                                const double *__restrict__ y, double *__restrict__ u, int accumulate)
+{
+    double coef[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) coef[i] = (i < K) ? y[i] : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
+        double s = accumulate ? u[e] : 0.0;
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+            if (i < K) s += coef[i] * V[i * ldv + e];
+        u[e] = s;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_bicg_p(int64_t n, const double *__restrict__ r, const double *__restrict__ v,
+                                               double beta, double omega, double *__restrict__ p)
+{
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS)
+        p[e] = r[e] + beta * (p[e] - omega * v[e]);
+}
+
+__global__ __launch_bounds__(BS) void k_bicg_s(int64_t n, const double *__restrict__ r, const double *__restrict__ v,
+                                               double *__restrict__ s, const double *__restrict__ sc, int knum,
+                                               int kden, double *__restrict__ partials)
+{
+    __shared__ double lds[16];
+    const double alpha = sc[knum] / sc[kden];
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
+        const double se = r[e] - alpha * v[e];
+        s[e] = se;
+        acc += se * se;
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// omega = sc[SC_TS] / sc[SC_TT] (0 when tt = 0); x += alpha ph + omega sh; r = s - omega t
+__global__ __launch_bounds__(BS) void k_bicg_xr(int64_t n, double alpha, const double *__restrict__ sc,
+                                                const double *__restrict__ ph, const double *__restrict__ sh,
+                                                const double *__restrict__ s, const double *__restrict__ t,
+                                                const double *__restrict__ rh, double *__restrict__ x,
+                                                double *__restrict__ r, double *__restrict__ partials)
+{
+    __shared__ double lds[16];
+    const double tt = sc[SC_TT];
+    const double omega = (tt > 0.0) ? sc[SC_TS] / tt : 0.0;
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
+        x[e] += alpha * ph[e] + omega * sh[e];
+        const double re = s[e] - omega * t[e];
+        r[e] = re;
+        a0 += re * re;
+        a1 += rh[e] * re;
+    }
+    a0 = block_sum(a0, lds);
+    if (threadIdx.x == 0) partials[2 * blockIdx.x] = a0;
+    a1 = block_sum(a1, lds);
+    if (threadIdx.x == 0) partials[2 * blockIdx.x + 1] = a1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+rsv_status partials_reserve(rsv_ctx *c, int64_t nd)
+{
+    if (nd <= c->partials_cap) return RSV_OK;
+    // the stream may still read the old buffer
+    RSV_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->d_partials) dev_free(c->d_partials);
+    c->d_partials = nullptr;
+    c->partials_cap = 0;
+    rsv_status s = dev_alloc(c, (void **)&c->d_partials, (size_t)nd * sizeof(double));
+    if (s != RSV_OK) return s;
+    c->partials_cap = nd;
+    return RSV_OK;
+}
+
+int spmv_blocks(const Geo &g) { return (int)((g.nslot + BS - 1) / BS); }
+int vec_blocks(int64_t n)
+{
+    int64_t b = (n + BS - 1) / BS;
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 2048);
+}
+
+rsv_status launch_reduce(rsv_ctx *c, int nblocks, int K, int k0)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_T), 0, c->stream, c->d_partials, nblocks, K, c->d_scal + k0);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+rsv_status launch_spmv(rsv_ctx *c, const Geo &g, const double *A, int mode, const double *x, double *y,
+                       const double *aux1, double alpha, double beta, int k0)
+{
+    const int nb = spmv_blocks(g);
+    if (mode >= SPMV_RESID) {
+        rsv_status s = partials_reserve(c, (int64_t)nb * 2);
+        if (s != RSV_OK) return s;
+    }
+    dim3 grid(nb), block(BS);
+    double *P = c->d_partials;
+    const int tok = prof_begin(c, RSV_K_SPMV);
+    switch (mode) {
+    case SPMV_Y: hipLaunchKernelGGL(k_spmv<SPMV_Y>, grid, block, 0, c->stream, g, A, x, y, aux1, alpha, beta, P); break;
+    case SPMV_AXPBY: hipLaunchKernelGGL(k_spmv<SPMV_AXPBY>, grid, block, 0, c->stream, g, A, x, y, aux1, alpha, beta, P); break;
+    case SPMV_RESID: hipLaunchKernelGGL(k_spmv<SPMV_RESID>, grid, block, 0, c->stream, g, A, x, y, aux1, alpha, beta, P); break;
+    case SPMV_NORM: hipLaunchKernelGGL(k_spmv<SPMV_NORM>, grid, block, 0, c->stream, g, A, x, y, aux1, alpha, beta, P); break;
+    case SPMV_DOT1: hipLaunchKernelGGL(k_spmv<SPMV_DOT1>, grid, block, 0, c->stream, g, A, x, y, aux1, alpha, beta, P); break;
+    case SPMV_DOT2: hipLaunchKernelGGL(k_spmv<SPMV_DOT2>, grid, block, 0, c->stream, g, A, x, y, aux1, alpha, beta, P); break;
+    default: return set_err(c, RSV_ERR_ARG, "bad spmv mode");
+    }
+    prof_end(c, tok);
+    RSV_LAUNCH(c);
+    if (mode >= SPMV_RESID) return launch_reduce(c, nb, mode == SPMV_DOT2 ? 2 : 1, k0);
+    return RSV_OK;
+}
+
+rsv_status launch_nat_to_tl(rsv_ctx *c, const Geo &g, const double *nat, double *tl)
+{
+    hipLaunchKernelGGL(k_nat_to_tl, dim3(spmv_blocks(g)), dim3(BS), 0, c->stream, g, nat, tl);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+rsv_status launch_tl_to_nat(rsv_ctx *c, const Geo &g, const double *tl, double *nat, double alpha, double beta)
+{
+    hipLaunchKernelGGL(k_tl_to_nat, dim3(spmv_blocks(g)), dim3(BS), 0, c->stream, g, tl, nat, alpha, beta);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+rsv_status launch_assemble(rsv_ctx *c, const Geo &g, const double *blocks, double *A)
+{
+    hipLaunchKernelGGL(k_assemble, dim3(spmv_blocks(g)), dim3(BS), 0, c->stream, g, blocks, A, c->d_flags);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+rsv_status launch_dot(rsv_ctx *c, int64_t n, const double *x, const double *y, int k0)
+{
+    const int nb = vec_blocks(n);
+    rsv_status s = partials_reserve(c, nb);
+    if (s != RSV_OK) return s;
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(BS), 0, c->stream, n, x, y, c->d_partials);
+    RSV_LAUNCH(c);
+    return launch_reduce(c, nb, 1, k0);
+}
+
+rsv_status launch_nonfinite(rsv_ctx *c, int64_t n, const double *x, int k0)
+{
+    const int nb = vec_blocks(n);
+    rsv_status s = partials_reserve(c, nb);
+    if (s != RSV_OK) return s;
+    hipLaunchKernelGGL(k_nonfinite, dim3(nb), dim3(BS), 0, c->stream, n, x, c->d_partials);
+    RSV_LAUNCH(c);
+    return launch_reduce(c, nb, 1, k0);
+}
+
+rsv_status launch_copy(rsv_ctx *c, int64_t n, const double *x, double *y)
+{
+    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(BS), 0, c->stream, n, x, y);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+rsv_status launch_scale_dev(rsv_ctx *c, int64_t n, double *x, int k)
+{
+    ProfScope ps(c, RSV_K_ORTHO);
+    hipLaunchKernelGGL(k_scale_dev, dim3(vec_blocks(n)), dim3(BS), 0, c->stream, n, x, c->d_scal + k);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+rsv_status launch_axpby(rsv_ctx *c, int64_t n, double a, const double *x, double b, double *y)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(vec_blocks(n)), dim3(BS), 0, c->stream, n, a, x, b, y);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+#define KB_DISPATCH(K, MACRO) \
+    if ((K) <= 4) { MACRO(4); } else if ((K) <= 8) { MACRO(8); } else if ((K) <= 16) { MACRO(16); } \
+    else if ((K) <= 32) { MACRO(32); } else { MACRO(64); }
+
+rsv_status launch_mdot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, const double *w, int k0)
+{
+    if (K < 1 || K > KMAX) return set_err(c, RSV_ERR_ARG, "mdot K");
+    const int nb = vec_blocks(n);
+    rsv_status s = partials_reserve(c, (int64_t)nb * K);
+    if (s != RSV_OK) return s;
+#define L_MDOT(KB) hipLaunchKernelGGL(k_mdot<KB>, dim3(nb), dim3(BS), 0, c->stream, n, V, ldv, K, w, c->d_partials)
+    {
+        ProfScope ps(c, RSV_K_ORTHO);
+        KB_DISPATCH(K, L_MDOT)
+    }
+#undef L_MDOT
+    RSV_LAUNCH(c);
+    return launch_reduce(c, nb, K, k0);
+}
+
+rsv_status launch_upd_dot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0)
+{
+    if (K < 1 || K > KMAX) return set_err(c, RSV_ERR_ARG, "upd K");
+    const int nb = vec_blocks(n);
+    rsv_status s = partials_reserve(c, (int64_t)nb * K);
+    if (s != RSV_OK) return s;
+#define L_UPD(KB) hipLaunchKernelGGL((k_upd<KB, 0>), dim3(nb), dim3(BS), 0, c->stream, n, V, ldv, K, w, c->d_scal + kc, c->d_partials)
+    {
+        ProfScope ps(c, RSV_K_ORTHO);
+        KB_DISPATCH(K, L_UPD)
+    }
+#undef L_UPD
+    RSV_LAUNCH(c);
+    return launch_reduce(c, nb, K, k0);
+}
+
+rsv_status launch_upd_norm(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0)
+{
+    if (K < 1 || K > KMAX) return set_err(c, RSV_ERR_ARG, "upd K");
+    const int nb = vec_blocks(n);
+    rsv_status s = partials_reserve(c, nb);
+    if (s != RSV_OK) return s;
+#define L_UPDN(KB) hipLaunchKernelGGL((k_upd<KB, 1>), dim3(nb), dim3(BS), 0, c->stream, n, V, ldv, K, w, c->d_scal + kc, c->d_partials)
+    {
+        ProfScope ps(c, RSV_K_ORTHO);
+        KB_DISPATCH(K, L_UPDN)
+    }
+#undef L_UPDN
+    RSV_LAUNCH(c);
+    return launch_reduce(c, nb, 1, k0);
+}
+
+rsv_status launch_combine(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, int ky, double *u, int accumulate)
+{
+    if (K < 1 || K > KMAX) return set_err(c, RSV_ERR_ARG, "combine K");
+    const int nb = vec_blocks(n);
+#define L_CMB(KB) hipLaunchKernelGGL(k_combine<KB>, dim3(nb), dim3(BS), 0, c->stream, n, V, ldv, K, c->d_scal + ky, u, accumulate)
+    {
+        ProfScope ps(c, RSV_K_ORTHO);
+        KB_DISPATCH(K, L_CMB)
+    }
+#undef L_CMB
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+rsv_status launch_bicg_p(rsv_ctx *c, int64_t n, const double *r, const double *v, double beta, double omega, double *p)
+{
+    ProfScope ps(c, RSV_K_VEC);
+    hipLaunchKernelGGL(k_bicg_p, dim3(vec_blocks(n)), dim3(BS), 0, c->stream, n, r, v, beta, omega, p);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+rsv_status launch_bicg_s(rsv_ctx *c, int64_t n, const double *r, const double *v, double *s, int knum, int kden, int k0)
+{
+    const int nb = vec_blocks(n);
+    rsv_status st = partials_reserve(c, nb);
+    if (st != RSV_OK) return st;
+    ProfScope ps(c, RSV_K_VEC);
+    hipLaunchKernelGGL(k_bicg_s, dim3(nb), dim3(BS), 0, c->stream, n, r, v, s, c->d_scal, knum, kden, c->d_partials);
+    RSV_LAUNCH(c);
+    return launch_reduce(c, nb, 1, k0);
+}
+
+rsv_status launch_bicg_xr(rsv_ctx *c, int64_t n, double alpha, double /*omega_unused*/, const double *ph, const double *sh,
+                          const double *s, const double *t, const double *rh, double *x, double *r, int k0)
+{
+    const int nb = vec_blocks(n);
+    rsv_status st = partials_reserve(c, (int64_t)nb * 2);
+    if (st != RSV_OK) return st;
+    ProfScope ps(c, RSV_K_VEC);
+    hipLaunchKernelGGL(k_bicg_xr, dim3(nb), dim3(BS), 0, c->stream, n, alpha, c->d_scal, ph, sh, s, t, rh, x, r,
+                       c->d_partials);
+    RSV_LAUNCH(c);
+    return launch_reduce(c, nb, 2, k0);
+}
+
+rsv_status scal_to_host(rsv_ctx *c, int k0, int n)
+{
+    RSV_HIP(c, hipMemcpyAsync(c->h_scal + k0, c->d_scal + k0, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    RSV_HIP(c, hipStreamSynchronize(c->stream));
+    return RSV_OK;
+}
+
+rsv_status scal_set(rsv_ctx *c, int k0, const double *vals, int n)
+{
+    // staged through the pinned buffer so the copy is truly asynchronous
+    for (int i = 0; i < n; ++i) c->h_scal[k0 + i] = vals[i];
+    RSV_HIP(c, hipMemcpyAsync(c->d_scal + k0, c->h_scal + k0, (size_t)n * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+    // the pinned slots may be overwritten by the next scal_to_host; make the copy complete first
+    RSV_HIP(c, hipStreamSynchronize(c->stream));
+    return RSV_OK;
+}

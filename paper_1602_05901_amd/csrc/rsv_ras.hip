@@ -1,0 +1,380 @@
+// Restricted additive Schwarz (Cai & Sarkis; the paper's RAS subsection and
+// its RAS_DATA / default-parameter figures): the grid is cut into px*py*pz
+// boxes; subdomain s is its box plus every cell within matrix-graph distance
+// `overlap`; the local matrix (A restricted to Omega_s, couplings leaving it
+// dropped) gets a block ILU(0) in ascending global order; the apply restricts
+// r to Omega_s, solves with the local factors and writes back only the cells
+// s owns (restricted prolongation, no atomics, no averaging).
+//
+// GPU mapping: one workgroup per subdomain.  Omega_s's cells are listed by
+// hyperplane i+j+k (ascending global index inside a plane); all local lower
+// neighbours of a cell lie on the previous hyperplane, so a workgroup walks
+// the planes with one barrier between planes.  Factors are stored
+// structure-of-arrays over the concatenated local cell lists so that each
+// plane's loads are coalesced.
+#include "rsv_internal.h"
+
+#include <algorithm>
+#include <new>
+
+namespace {
+
+constexpr int RB = 1024;   // threads per subdomain workgroup
+
+struct RasDev {
+    int64_t n;                  // total local cells (sum |Omega_s|)
+    const int32_t *slot;        // [n] tile-lane slot of the cell
+    const int32_t *nb;          // [6][n] local index of neighbour -z,-y,-x,+x,+y,+z in Omega_s, or -1
+    const uint8_t *owned;       // [n]
+    const int64_t *pp;          // plane pointers (global offsets into the local arrays)
+    const int32_t *sub_pp0;     // [nsub] first entry of subdomain s in pp
+    const int32_t *sub_np;      // [nsub] number of planes
+};
+
+__global__ __launch_bounds__(RB) void k_ras_factor(RasDev R, const double *__restrict__ A, double *__restrict__ Lf,
+                                                   double *__restrict__ Dinv, double *__restrict__ U,
+                                                   int32_t *flags, Geo g)
+{
+    const int s = blockIdx.x;
+    const int64_t n = R.n;
+    const int np = R.sub_np[s];
+    const int64_t *pp = R.pp + R.sub_pp0[s];
+    for (int p = 0; p < np; ++p) {
+        for (int64_t c = pp[p] + threadIdx.x; c < pp[p + 1]; c += RB) {
+            const int64_t slot = R.slot[c];
+            double D[9];
+            for (int e = 0; e < 9; ++e) D[e] = A[aidx(slot, 27 + e)];
+            for (int q = 0; q < 3; ++q) {   // -z, -y, -x
+                const int32_t m = R.nb[q * n + c];
+                double L[9];
+                if (m >= 0) {
+                    const int64_t ms = R.slot[m];
+                    double Ack[9], Dk[9], Akc[9];
+                    for (int e = 0; e < 9; ++e) {
+                        Ack[e] = A[aidx(slot, q * 9 + e)];
+                        Dk[e] = Dinv[e * n + m];
+                        Akc[e] = A[aidx(ms, (6 - q) * 9 + e)];
+                    }
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b)
+                            L[3 * a + b] = Ack[3 * a] * Dk[b] + Ack[3 * a + 1] * Dk[3 + b] + Ack[3 * a + 2] * Dk[6 + b];
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b)
+                            D[3 * a + b] -= L[3 * a] * Akc[b] + L[3 * a + 1] * Akc[3 + b] + L[3 * a + 2] * Akc[6 + b];
+                } else {
+                    for (int e = 0; e < 9; ++e) L[e] = 0.0;
+                }
+                for (int e = 0; e < 9; ++e) Lf[(q * 9 + e) * n + c] = L[e];
+            }
+            for (int q = 0; q < 3; ++q) {   // +x, +y, +z: A's blocks if the neighbour is in Omega_s
+                const int32_t m = R.nb[(3 + q) * n + c];
+                for (int e = 0; e < 9; ++e) U[(q * 9 + e) * n + c] = (m >= 0) ? A[aidx(slot, (4 + q) * 9 + e)] : 0.0;
+            }
+            double Di[9];
+            if (!inv3(D, Di)) {
+                int gx, gy, k;
+                cell_of(g, slot, gx, gy, k);
+                atomicOr(&flags[0], FLAG_PIVOT);
+                atomicMin(&flags[1], (int32_t)row_of(g, gx, gy, k));
+                for (int e = 0; e < 9; ++e) Di[e] = 0.0;
+            }
+            for (int e = 0; e < 9; ++e) Dinv[e * n + c] = Di[e];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_ras_apply(RasDev R, const T *__restrict__ Lf, const T *__restrict__ Dinv,
+                                                  const T *__restrict__ U, const double *__restrict__ r,
+                                                  T *__restrict__ yl, T *__restrict__ zl, double *__restrict__ z)
+{
+    const int s = blockIdx.x;
+    const int64_t n = R.n;
+    const int np = R.sub_np[s];
+    const int64_t *pp = R.pp + R.sub_pp0[s];
+    for (int p = 0; p < np; ++p) {
+        for (int64_t c = pp[p] + threadIdx.x; c < pp[p + 1]; c += RB) {
+            const int64_t slot = R.slot[c];
+            T acc[3] = {0, 0, 0};
+            for (int q = 0; q < 3; ++q) {
+                const int32_t m = R.nb[q * n + c];
+                if (m >= 0) {
+                    const T y0 = yl[m], y1 = yl[n + m], y2 = yl[2 * n + m];
+                    for (int a = 0; a < 3; ++a)
+                        acc[a] += Lf[(q * 9 + 3 * a) * n + c] * y0 + Lf[(q * 9 + 3 * a + 1) * n + c] * y1 +
+                                  Lf[(q * 9 + 3 * a + 2) * n + c] * y2;
+                }
+            }
+            for (int a = 0; a < 3; ++a) yl[a * n + c] = (T)r[vidx(slot, a)] - acc[a];
+        }
+        __syncthreads();
+    }
+    for (int p = np - 1; p >= 0; --p) {
+        for (int64_t c = pp[p] + threadIdx.x; c < pp[p + 1]; c += RB) {
+            const int64_t slot = R.slot[c];
+            T acc[3] = {0, 0, 0};
+            for (int q = 0; q < 3; ++q) {
+                const int32_t m = R.nb[(3 + q) * n + c];
+                if (m >= 0) {
+                    const T z0 = zl[m], z1 = zl[n + m], z2 = zl[2 * n + m];
+                    for (int a = 0; a < 3; ++a)
+                        acc[a] += U[(q * 9 + 3 * a) * n + c] * z0 + U[(q * 9 + 3 * a + 1) * n + c] * z1 +
+                                  U[(q * 9 + 3 * a + 2) * n + c] * z2;
+                }
+            }
+            T tv[3];
+            for (int a = 0; a < 3; ++a) tv[a] = yl[a * n + c] - acc[a];
+            T out[3];
+            for (int a = 0; a < 3; ++a)
+                out[a] = Dinv[(3 * a) * n + c] * tv[0] + Dinv[(3 * a + 1) * n + c] * tv[1] + Dinv[(3 * a + 2) * n + c] * tv[2];
+            for (int a = 0; a < 3; ++a) zl[a * n + c] = out[a];
+            if (R.owned[c])
+                for (int a = 0; a < 3; ++a) z[vidx(slot, a)] = (double)out[a];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_cvt(int64_t n, const double *__restrict__ a, float *__restrict__ b)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) b[e] = (float)a[e];
+}
+
+static int64_t split_index(int64_t v, int64_t len, int64_t p)
+{
+    const int64_t base = len / p, rem = len % p, big = rem * (base + 1);
+    if (v < big) return v / (base + 1);
+    return rem + (v - big) / base;
+}
+static int64_t split_start(int64_t b, int64_t len, int64_t p)
+{
+    const int64_t base = len / p, rem = len % p;
+    return b * base + std::min(b, rem);
+}
+
+struct Ras : PcImpl {
+    rsv_matrix *M = nullptr;
+    rsv_ctx *c = nullptr;
+    bool fp32 = false;
+    int nsub = 0;
+    int64_t n = 0;
+    int32_t *slot = nullptr, *nb = nullptr, *sub_pp0 = nullptr, *sub_np = nullptr;
+    uint8_t *owned = nullptr;
+    int64_t *pp = nullptr;
+    double *Lf = nullptr, *Dinv = nullptr, *U = nullptr;
+    float *Lf32 = nullptr, *Dinv32 = nullptr, *U32 = nullptr;
+    void *yl = nullptr, *zl = nullptr;
+    int64_t nbytes = 0;
+
+    ~Ras() override
+    {
+        dev_free(slot); dev_free(nb); dev_free(sub_pp0); dev_free(sub_np); dev_free(owned); dev_free(pp);
+        dev_free(Lf); dev_free(Dinv); dev_free(U); dev_free(Lf32); dev_free(Dinv32); dev_free(U32);
+        dev_free(yl); dev_free(zl);
+    }
+    int64_t bytes() const override { return nbytes; }
+
+    rsv_status alloc(void **p, size_t b)
+    {
+        rsv_status s = dev_alloc(c, p, b);
+        if (s == RSV_OK) nbytes += (int64_t)b;
+        return s;
+    }
+    template <typename V>
+    rsv_status upload(V **p, const std::vector<V> &h)
+    {
+        rsv_status s = alloc((void **)p, h.size() * sizeof(V));
+        if (s != RSV_OK) return s;
+        RSV_HIP(c, hipMemcpy(*p, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+        return RSV_OK;
+    }
+
+    RasDev dev() const { return RasDev{n, slot, nb, owned, pp, sub_pp0, sub_np}; }
+
+    rsv_status setup(const rsv_pc_params *p, int64_t *bad_cell)
+    {
+        const Geo &g = M->g->geo;
+        const int px = p->ras_px, py = p->ras_py, pz = p->ras_pz, ov = p->ras_overlap;
+        if (px < 1 || py < 1 || pz < 1 || px > g.nx || py > g.ny || pz > g.nz || ov < 0)
+            return set_err(c, RSV_ERR_ARG, "bad RAS partition");
+        nsub = px * py * pz;
+        const int64_t ncell = M->g->ncell;
+        auto cid = [&](int i, int j, int k) { return ((int64_t)k * g.ny + j) * g.nx + i; };
+        std::vector<int32_t> stamp(ncell, -1), dist(ncell, 0);
+        std::vector<int32_t> h_slot, h_nb6;   // nb filled after sizes are known
+        std::vector<uint8_t> h_owned;
+        std::vector<int64_t> h_pp;
+        std::vector<int32_t> h_pp0(nsub), h_np(nsub);
+        std::vector<std::vector<int64_t>> lists(nsub);
+        std::vector<int64_t> queue;
+        for (int s = 0; s < nsub; ++s) {
+            const int sx = s % px, sy = (s / px) % py, sz = s / (px * py);
+            const int x0 = (int)split_start(sx, g.nx, px), x1 = (int)split_start(sx + 1, g.nx, px);
+            const int y0 = (int)split_start(sy, g.ny, py), y1 = (int)split_start(sy + 1, g.ny, py);
+            const int z0 = (int)split_start(sz, g.nz, pz), z1 = (int)split_start(sz + 1, g.nz, pz);
+            queue.clear();
+            for (int k = z0; k < z1; ++k)
+                for (int j = y0; j < y1; ++j)
+                    for (int i = x0; i < x1; ++i) {
+                        const int64_t C = cid(i, j, k);
+                        stamp[C] = s;
+                        dist[C] = 0;
+                        queue.push_back(C);
+                    }
+            // breadth-first search over the stencil graph up to distance `ov`
+            for (size_t h = 0; h < queue.size(); ++h) {
+                const int64_t C = queue[h];
+                if (dist[C] >= ov) continue;
+                const int i = (int)(C % g.nx), j = (int)((C / g.nx) % g.ny), k = (int)(C / ((int64_t)g.nx * g.ny));
+                for (int d = 0; d < 7; ++d) {
+                    if (d == 3) continue;
+                    int di, dj, dk;
+                    dir_off(d, di, dj, dk);
+                    const int a = i + di, b = j + dj, e = k + dk;
+                    if (a < 0 || a >= g.nx || b < 0 || b >= g.ny || e < 0 || e >= g.nz) continue;
+                    const int64_t N = cid(a, b, e);
+                    if (stamp[N] == s) continue;
+                    stamp[N] = s;
+                    dist[N] = dist[C] + 1;
+                    queue.push_back(N);
+                }
+            }
+            // order: hyperplane, then ascending global index
+            std::vector<int64_t> &lst = lists[s];
+            lst = queue;
+            std::sort(lst.begin(), lst.end(), [&](int64_t a, int64_t b) {
+                const int64_t pa = a % g.nx + (a / g.nx) % g.ny + a / ((int64_t)g.nx * g.ny);
+                const int64_t pb = b % g.nx + (b / g.nx) % g.ny + b / ((int64_t)g.nx * g.ny);
+                return pa != pb ? pa < pb : a < b;
+            });
+        }
+        int64_t total = 0;
+        for (int s = 0; s < nsub; ++s) total += (int64_t)lists[s].size();
+        if (total >= ((int64_t)1 << 31)) return set_err(c, RSV_ERR_ARG, "RAS local size exceeds int32");
+        n = total;
+        h_slot.resize(n);
+        h_owned.resize(n);
+        h_nb6.assign(6 * n, -1);
+        std::vector<int32_t> loc(ncell, -1);
+        int64_t off = 0;
+        for (int s = 0; s < nsub; ++s) {
+            const std::vector<int64_t> &lst = lists[s];
+            for (size_t q = 0; q < lst.size(); ++q) loc[lst[q]] = (int32_t)(off + q);
+            h_pp0[s] = (int32_t)h_pp.size();
+            int64_t prev_plane = -1;
+            int nplanes = 0;
+            for (size_t q = 0; q < lst.size(); ++q) {
+                const int64_t C = lst[q];
+                const int i = (int)(C % g.nx), j = (int)((C / g.nx) % g.ny), k = (int)(C / ((int64_t)g.nx * g.ny));
+                const int64_t pl = i + j + k;
+                if (pl != prev_plane) {
+                    // planes are contiguous (every plane between first and last is non-empty
+                    // for a face-connected set); record empty planes too for safety
+                    if (prev_plane >= 0)
+                        for (int64_t e = prev_plane + 1; e < pl; ++e) { h_pp.push_back(off + (int64_t)q); ++nplanes; }
+                    h_pp.push_back(off + (int64_t)q);
+                    ++nplanes;
+                    prev_plane = pl;
+                }
+                const int64_t L = off + (int64_t)q;
+                h_slot[L] = (int32_t)slot_of(g, i, j, k);
+                const int sx = (int)split_index(i, g.nx, px), sy = (int)split_index(j, g.ny, py),
+                          sz = (int)split_index(k, g.nz, pz);
+                h_owned[L] = ((sz * py + sy) * px + sx) == s;
+            }
+            h_pp.push_back(off + (int64_t)lst.size());
+            h_np[s] = nplanes;
+            // local neighbour indices
+            const int dirs[6] = {0, 1, 2, 4, 5, 6};
+            for (size_t q = 0; q < lst.size(); ++q) {
+                const int64_t C = lst[q];
+                const int i = (int)(C % g.nx), j = (int)((C / g.nx) % g.ny), k = (int)(C / ((int64_t)g.nx * g.ny));
+                for (int d6 = 0; d6 < 6; ++d6) {
+                    int di, dj, dk;
+                    dir_off(dirs[d6], di, dj, dk);
+                    const int a = i + di, b = j + dj, e = k + dk;
+                    if (a < 0 || a >= g.nx || b < 0 || b >= g.ny || e < 0 || e >= g.nz) continue;
+                    const int32_t m = loc[cid(a, b, e)];
+                    h_nb6[(int64_t)d6 * n + off + (int64_t)q] = m;
+                }
+            }
+            for (size_t q = 0; q < lst.size(); ++q) loc[lst[q]] = -1;
+            off += (int64_t)lst.size();
+        }
+        rsv_status st = upload(&slot, h_slot);
+        if (st == RSV_OK) st = upload(&nb, h_nb6);
+        if (st == RSV_OK) st = upload(&owned, h_owned);
+        if (st == RSV_OK) st = upload(&pp, h_pp);
+        if (st == RSV_OK) st = upload(&sub_pp0, h_pp0);
+        if (st == RSV_OK) st = upload(&sub_np, h_np);
+        if (st == RSV_OK) st = alloc((void **)&Lf, (size_t)n * 27 * sizeof(double));
+        if (st == RSV_OK) st = alloc((void **)&Dinv, (size_t)n * 9 * sizeof(double));
+        if (st == RSV_OK) st = alloc((void **)&U, (size_t)n * 27 * sizeof(double));
+        if (st != RSV_OK) return st;
+        st = flags_reset(c);
+        if (st != RSV_OK) return st;
+        {
+            ProfScope ps(c, RSV_K_FACTOR);
+            hipLaunchKernelGGL(k_ras_factor, dim3(nsub), dim3(RB), 0, c->stream, dev(), M->d_A, Lf, Dinv, U, c->d_flags, g);
+        }
+        RSV_LAUNCH(c);
+        st = flags_check(c, bad_cell);
+        if (st != RSV_OK) return st;
+        if (fp32) {
+            st = alloc((void **)&Lf32, (size_t)n * 27 * sizeof(float));
+            if (st == RSV_OK) st = alloc((void **)&Dinv32, (size_t)n * 9 * sizeof(float));
+            if (st == RSV_OK) st = alloc((void **)&U32, (size_t)n * 27 * sizeof(float));
+            if (st == RSV_OK) st = alloc(&yl, (size_t)n * 3 * sizeof(float));
+            if (st == RSV_OK) st = alloc(&zl, (size_t)n * 3 * sizeof(float));
+            if (st != RSV_OK) return st;
+            hipLaunchKernelGGL(k_cvt, dim3(2048), dim3(256), 0, c->stream, n * 27, Lf, Lf32);
+            hipLaunchKernelGGL(k_cvt, dim3(2048), dim3(256), 0, c->stream, n * 9, Dinv, Dinv32);
+            hipLaunchKernelGGL(k_cvt, dim3(2048), dim3(256), 0, c->stream, n * 27, U, U32);
+            RSV_LAUNCH(c);
+            RSV_HIP(c, hipStreamSynchronize(c->stream));
+            dev_free(Lf); Lf = nullptr;
+            dev_free(Dinv); Dinv = nullptr;
+            dev_free(U); U = nullptr;
+            nbytes -= n * 63 * (int64_t)sizeof(double);
+        } else {
+            st = alloc(&yl, (size_t)n * 3 * sizeof(double));
+            if (st == RSV_OK) st = alloc(&zl, (size_t)n * 3 * sizeof(double));
+            if (st != RSV_OK) return st;
+        }
+        RSV_HIP(c, hipStreamSynchronize(c->stream));
+        return RSV_OK;
+    }
+
+    rsv_status apply(const double *r, double *z) override
+    {
+        ProfScope ps(c, RSV_K_RAS);
+        if (fp32)
+            hipLaunchKernelGGL(k_ras_apply<float>, dim3(nsub), dim3(RB), 0, c->stream, dev(), Lf32, Dinv32, U32, r,
+                               (float *)yl, (float *)zl, z);
+        else
+            hipLaunchKernelGGL(k_ras_apply<double>, dim3(nsub), dim3(RB), 0, c->stream, dev(), Lf, Dinv, U, r,
+                               (double *)yl, (double *)zl, z);
+        RSV_LAUNCH(c);
+        return RSV_OK;
+    }
+};
+
+}  // namespace
+
+rsv_status ras_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell)
+{
+    rsv_ctx *c = A->g->ctx;
+    Ras *R = new (std::nothrow) Ras();
+    if (!R) return set_err(c, RSV_ERR_OOM, "ras");
+    R->M = A;
+    R->c = c;
+    R->fp32 = (p->precision == RSV_FP32);
+    rsv_status s = R->setup(p, bad_cell);
+    if (s != RSV_OK) {
+        delete R;
+        return s;
+    }
+    *out = R;
+    return RSV_OK;
+}

@@ -1,0 +1,326 @@
+"""Thin Python binding of the rsv C ABI (include/rsv.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library
+librsv.so.  PyTorch supplies device memory (tensor.data_ptr()) and the HIP
+stream (torch.cuda.current_stream().cuda_stream).  If the library is missing
+this module raises on use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsv.so")
+
+OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+ERR_ARG, ERR_OOM, ERR_HIP, ERR_ZERO_PIVOT, ERR_NAN, ERR_PATTERN, ERR_TIMEOUT = -1, -2, -3, -4, -5, -6, -7
+BOTTOM_UP, TOP_DOWN = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+PC_NONE, PC_BILU0, PC_RAS, PC_LEARNED = 0, 1, 2, 3
+FP64, FP32 = 0, 1
+GMRES, BICGSTAB, FGMRES = 0, 1, 2
+
+vp, i32, i64, dbl, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+
+
+class PcParams(ctypes.Structure):
+    _fields_ = [("type", i32), ("precision", i32), ("ras_px", i32), ("ras_py", i32), ("ras_pz", i32),
+                ("ras_overlap", i32), ("iluk_level", i32), ("pipelined", i32), ("net", vp), ("lnk", vp),
+                ("theta", dbl), ("reserved", i32 * 8)]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("method", i32), ("restart", i32), ("tol", dbl), ("maxit", i64), ("rtol", dbl), ("atol", dbl),
+                ("record_history", i32), ("reserved", i32 * 7)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("its", i64), ("restarts", i64), ("fallbacks", i64), ("final_relres", dbl), ("solve_ms", dbl),
+                ("bad_cell", i64), ("status", i32), ("reserved", i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class NetArch(ctypes.Structure):
+    _fields_ = [("levels", i32), ("c0", i32), ("c1", i32), ("c2", i32), ("reserved", i32 * 4)]
+
+
+_P = ctypes.POINTER
+_SIGS = {
+    "rsv_version": ([], i32),
+    "rsv_status_str": ([i32], ctypes.c_char_p),
+    "rsv_last_error": ([vp], ctypes.c_char_p),
+    "rsv_create": ([i32, _P(vp)], i32),
+    "rsv_set_stream": ([vp, vp], i32),
+    "rsv_destroy": ([vp], None),
+    "rsv_grid_create": ([vp, i32, i32, i32, i32, _P(vp)], i32),
+    "rsv_grid_destroy": ([vp], None),
+    "rsv_grid_ncell": ([vp], i64),
+    "rsv_cell_to_row": ([vp, i32, i32, i32, _P(i64)], i32),
+    "rsv_row_to_cell": ([vp, i64, _P(i32), _P(i32), _P(i32)], i32),
+    "rsv_matrix_assemble": ([vp, vp, i32, _P(vp)], i32),
+    "rsv_matrix_update": ([vp, vp, i32], i32),
+    "rsv_matrix_destroy": ([vp], None),
+    "rsv_spmv": ([vp, dbl, vp, dbl, vp], i32),
+    "rsv_matrix_device_bytes": ([vp], i64),
+    "rsv_pc_params_default": ([_P(PcParams)], None),
+    "rsv_precond_setup": ([vp, _P(PcParams), _P(vp), _P(i64)], i32),
+    "rsv_precond_apply": ([vp, vp, vp], i32),
+    "rsv_precond_destroy": ([vp], None),
+    "rsv_solver_params_default": ([_P(SolverParams)], None),
+    "rsv_solve": ([vp, vp, _P(SolverParams), vp, vp, _P(Stats)], i32),
+    "rsv_solve_history": ([vp, vp, i64], i64),
+    "rsv_net_create": ([vp, _P(NetArch), u64, _P(vp)], i32),
+    "rsv_net_destroy": ([vp], None),
+    "rsv_net_num_params": ([vp], i64),
+    "rsv_net_get_params": ([vp, vp, i64], i32),
+    "rsv_net_set_params": ([vp, vp, i64], i32),
+    "rsv_net_save": ([vp, ctypes.c_char_p], i32),
+    "rsv_net_load": ([vp, ctypes.c_char_p], i32),
+    "rsv_net_forward": ([vp, vp, vp, vp, vp], i32),
+    "rsv_net_train_step": ([vp, vp, i32, vp, vp, vp, ctypes.c_float, _P(ctypes.c_float)], i32),
+    "rsv_net_loss_grad": ([vp, vp, i32, vp, vp, vp, _P(ctypes.c_float), vp], i32),
+    "rsv_profile_enable": ([vp, i32], i32),
+    "rsv_profile_read": ([vp, vp, vp], i32),
+}
+K_NAMES = ["spmv", "ilu_fwd", "ilu_bwd", "ras", "ortho", "vec", "factor", "net"]
+
+_lib = None
+
+
+def lib():
+    """Load librsv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} -- run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+class RsvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{lib().rsv_status_str(status).decode()}: {msg}")
+        self.status = status
+
+
+def _check(ctx, status, allow=(OK,)):
+    if status not in allow:
+        msg = lib().rsv_last_error(ctx.h if ctx is not None else None).decode(errors="replace")
+        raise RsvError(status, msg)
+    return status
+
+
+def _ptr(t):
+    """Device (or host) address of a torch tensor / numpy array / int."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+class Context:
+    def __init__(self, device=0, stream=None):
+        h = vp()
+        _check(None, lib().rsv_create(device, ctypes.byref(h)))
+        self.h = h
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        _check(self, lib().rsv_set_stream(self.h, stream))
+
+    def profile(self, on=True):
+        _check(self, lib().rsv_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        import numpy as np
+        ms = np.zeros(len(K_NAMES))
+        cnt = np.zeros(len(K_NAMES), np.int64)
+        _check(self, lib().rsv_profile_read(self.h, ms.ctypes.data, cnt.ctypes.data))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(K_NAMES)}
+
+    def close(self):
+        if self.h:
+            lib().rsv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Grid:
+    def __init__(self, ctx: Context, nx, ny, nz, ordering=BOTTOM_UP):
+        h = vp()
+        _check(ctx, lib().rsv_grid_create(ctx.h, nx, ny, nz, ordering, ctypes.byref(h)))
+        self.ctx, self.h, self.dims = ctx, h, (nx, ny, nz)
+
+    @property
+    def ncell(self):
+        return lib().rsv_grid_ncell(self.h)
+
+    def cell_to_row(self, i, j, k):
+        r = i64()
+        _check(self.ctx, lib().rsv_cell_to_row(self.h, i, j, k, ctypes.byref(r)))
+        return r.value
+
+    def row_to_cell(self, row):
+        i, j, k = i32(), i32(), i32()
+        _check(self.ctx, lib().rsv_row_to_cell(self.h, row, ctypes.byref(i), ctypes.byref(j), ctypes.byref(k)))
+        return i.value, j.value, k.value
+
+    def close(self):
+        if self.h:
+            lib().rsv_grid_destroy(self.h)
+            self.h = None
+
+
+class Matrix:
+    def __init__(self, grid: Grid, blocks, where=None):
+        """blocks: [ncell,7,3,3] float64, numpy (host) or torch (host or device)."""
+        if where is None:
+            where = MEM_DEVICE if (hasattr(blocks, "is_cuda") and blocks.is_cuda) else MEM_HOST
+        h = vp()
+        _check(grid.ctx, lib().rsv_matrix_assemble(grid.h, _ptr(blocks), where, ctypes.byref(h)))
+        self.grid, self.ctx, self.h = grid, grid.ctx, h
+
+    def update(self, blocks, where=None):
+        if where is None:
+            where = MEM_DEVICE if (hasattr(blocks, "is_cuda") and blocks.is_cuda) else MEM_HOST
+        _check(self.ctx, lib().rsv_matrix_update(self.h, _ptr(blocks), where))
+
+    def spmv(self, x, y, alpha=1.0, beta=0.0):
+        _check(self.ctx, lib().rsv_spmv(self.h, alpha, _ptr(x), beta, _ptr(y)))
+        return y
+
+    @property
+    def device_bytes(self):
+        return lib().rsv_matrix_device_bytes(self.h)
+
+    def close(self):
+        if self.h:
+            lib().rsv_matrix_destroy(self.h)
+            self.h = None
+
+
+def pc_params(**kw) -> PcParams:
+    p = PcParams()
+    lib().rsv_pc_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k in ("net", "lnk"):
+            v = _ptr(v) if not isinstance(v, Net) else v.h.value
+        setattr(p, k, v)
+    return p
+
+
+def solver_params(**kw) -> SolverParams:
+    p = SolverParams()
+    lib().rsv_solver_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Precond:
+    def __init__(self, A: Matrix, **kw):
+        p = pc_params(**kw)
+        h = vp()
+        bad = i64(-1)
+        st = lib().rsv_precond_setup(A.h, ctypes.byref(p), ctypes.byref(h), ctypes.byref(bad))
+        if st != OK:
+            e = RsvError(st, lib().rsv_last_error(A.ctx.h).decode(errors="replace"))
+            e.bad_cell = bad.value
+            raise e
+        self.A, self.ctx, self.h, self.params = A, A.ctx, h, p
+        self._keep = kw
+
+    def apply(self, r, z):
+        _check(self.ctx, lib().rsv_precond_apply(self.h, _ptr(r), _ptr(z)))
+        return z
+
+    def close(self):
+        if self.h:
+            lib().rsv_precond_destroy(self.h)
+            self.h = None
+
+
+def solve(A: Matrix, M: Precond | None, b, x, allow=(OK, NOT_CONVERGED, BREAKDOWN), **kw):
+    """x (device tensor) holds x0 on entry and the result on exit; returns stats dict."""
+    p = solver_params(**kw)
+    st = Stats()
+    status = lib().rsv_solve(A.h, M.h if M is not None else None, ctypes.byref(p), _ptr(b), _ptr(x),
+                             ctypes.byref(st))
+    _check(A.ctx, status, allow)
+    d = st.as_dict()
+    d["status"] = status
+    if p.record_history:
+        n = lib().rsv_solve_history(A.h, None, 0)
+        import numpy as np
+        h = np.zeros(n)
+        lib().rsv_solve_history(A.h, h.ctypes.data, n)
+        d["hist"] = h
+    return d
+
+
+class Net:
+    def __init__(self, ctx: Context, c0=16, c1=32, c2=64, seed=0):
+        arch = NetArch(3, c0, c1, c2)
+        h = vp()
+        _check(ctx, lib().rsv_net_create(ctx.h, ctypes.byref(arch), seed, ctypes.byref(h)))
+        self.ctx, self.h = ctx, h
+
+    @property
+    def num_params(self):
+        return lib().rsv_net_num_params(self.h)
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.num_params, np.float32)
+        _check(self.ctx, lib().rsv_net_get_params(self.h, out.ctypes.data, out.size))
+        return out
+
+    def set_params(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(self.ctx, lib().rsv_net_set_params(self.h, w.ctypes.data, w.size))
+
+    def save(self, path):
+        _check(self.ctx, lib().rsv_net_save(self.h, path.encode()))
+
+    def load(self, path):
+        _check(self.ctx, lib().rsv_net_load(self.h, path.encode()))
+
+    def forward(self, grid: Grid, r, lnk, z):
+        _check(self.ctx, lib().rsv_net_forward(self.h, grid.h, _ptr(r), _ptr(lnk), _ptr(z)))
+        return z
+
+    def train_step(self, grid: Grid, nb, r, e, lnk, lr):
+        loss = ctypes.c_float()
+        _check(self.ctx, lib().rsv_net_train_step(self.h, grid.h, nb, _ptr(r), _ptr(e), _ptr(lnk), lr,
+                                                  ctypes.byref(loss)))
+        return loss.value
+
+    def loss_grad(self, grid: Grid, nb, r, e, lnk):
+        import numpy as np
+        loss = ctypes.c_float()
+        g = np.zeros(self.num_params, np.float32)
+        _check(self.ctx, lib().rsv_net_loss_grad(self.h, grid.h, nb, _ptr(r), _ptr(e), _ptr(lnk),
+                                                 ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def close(self):
+        if self.h:
+            lib().rsv_net_destroy(self.h)
+            self.h = None
