@@ -221,6 +221,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "device_bytes": A.device_bytes,
+        "device": ctx.device_info(),
     }
     print(json.dumps(line), flush=True)
     A.close(); g.close(); ctx.close()

@@ -124,6 +124,11 @@ const char *rsv_status_str(rsv_status s);
 const char *rsv_last_error(const rsv_ctx *ctx);
 /* ABI version: major*10000 + minor*100 + patch. */
 int32_t rsv_version(void);
+/* Device facts the solver sizes itself by, written to the HOST array info:
+ * [0] compute units, [1] LDS bytes a workgroup may use, [2] LDS bytes per CU,
+ * [3] ring depth of the forward FP64 sweep, [4] of the backward FP64 sweep.
+ * Writes min(n, 5) entries.  Errors: RSV_ERR_ARG. */
+rsv_status rsv_device_info(const rsv_ctx *ctx, int64_t *info, int32_t n);
 
 /* ---------------------------------------------------------------- grid and MAP */
 

@@ -122,6 +122,14 @@ rsv_status rsv_profile_read(rsv_ctx *c, double *ms, int64_t *cnt)
 
 int32_t rsv_version(void) { return RSV_VERSION; }
 
+rsv_status rsv_device_info(const rsv_ctx *c, int64_t *info, int32_t n)
+{
+    if (!c || !info || n < 0) return set_err(nullptr, RSV_ERR_ARG, "NULL argument");
+    const int64_t v[5] = {c->num_cu, c->lds_max, c->lds_per_cu, sweep_ring_depth(c, 0, 0), sweep_ring_depth(c, 1, 0)};
+    for (int i = 0; i < n && i < 5; ++i) info[i] = v[i];
+    return RSV_OK;
+}
+
 const char *rsv_status_str(rsv_status s)
 {
     switch (s) {
@@ -158,7 +166,15 @@ rsv_status rsv_create(int32_t dev, rsv_ctx **out)
     if (!c) return set_err(nullptr, RSV_ERR_OOM, "ctx");
     c->device = dev;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        c->num_cu = prop.multiProcessorCount;
+        size_t lds = prop.sharedMemPerBlock;
+        if (prop.sharedMemPerBlockOptin > lds) lds = prop.sharedMemPerBlockOptin;
+        if (prop.maxSharedMemoryPerMultiProcessor > 0 && prop.maxSharedMemoryPerMultiProcessor < lds)
+            lds = prop.maxSharedMemoryPerMultiProcessor;
+        c->lds_max = (int)lds;
+        c->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+    }
     rsv_status s = RSV_OK;
     if (hipHostMalloc((void **)&c->h_scal, SC_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) s = RSV_ERR_OOM;
     if (s == RSV_OK) s = dev_alloc(c, (void **)&c->d_scal, SC_COUNT * sizeof(double));

@@ -24,6 +24,8 @@
 #include "rsv_internal.h"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <new>
 
 namespace {
@@ -36,15 +38,22 @@ __device__ inline int64_t fidx(int64_t slot, int e, int ne) { return ((slot >> 6
 // Per-cell arithmetic shared by the per-hyperplane and the pipelined sweeps,
 // so that both executions produce bitwise-identical results.
 // forward: out = r - (L_-z vz + L_-y vy + L_-x vx)   (ascending column order)
+// explicit fused multiply-adds: the same operation sequence in every kernel
+// that inlines these helpers, whatever the contraction choices around them
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <typename T>
+__device__ __forceinline__ T dot3(const T *m, const T *v) { return fma_t(m[2], v[2], fma_t(m[1], v[1], m[0] * v[0])); }
+
+// forward: out = r - (L_-z vz + L_-y vy + L_-x vx); the three block products
+// are independent chains summed at the end (short dependency path per step)
 template <typename T>
 __device__ __forceinline__ void fwd_cell(const T *l, const T *vz, const T *vy, const T *vx, const T *rr, T *out)
 {
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        T acc = l[3 * p] * vz[0] + l[3 * p + 1] * vz[1] + l[3 * p + 2] * vz[2];
-        acc += l[9 + 3 * p] * vy[0] + l[9 + 3 * p + 1] * vy[1] + l[9 + 3 * p + 2] * vy[2];
-        acc += l[18 + 3 * p] * vx[0] + l[18 + 3 * p + 1] * vx[1] + l[18 + 3 * p + 2] * vx[2];
-        out[p] = rr[p] - acc;
+        const T az = dot3(l + 3 * p, vz), ay = dot3(l + 9 + 3 * p, vy), ax = dot3(l + 18 + 3 * p, vx);
+        out[p] = rr[p] - ((az + ay) + ax);
     }
 }
 // backward: out = Dinv (y - (U_+x vx + U_+y vy + U_+z vz))
@@ -55,13 +64,11 @@ __device__ __forceinline__ void bwd_cell(const T *u, const T *dd, const T *vx, c
     T tv[3];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        T acc = u[3 * p] * vx[0] + u[3 * p + 1] * vx[1] + u[3 * p + 2] * vx[2];
-        acc += u[9 + 3 * p] * vy[0] + u[9 + 3 * p + 1] * vy[1] + u[9 + 3 * p + 2] * vy[2];
-        acc += u[18 + 3 * p] * vz[0] + u[18 + 3 * p + 1] * vz[1] + u[18 + 3 * p + 2] * vz[2];
-        tv[p] = yy[p] - acc;
+        const T ax = dot3(u + 3 * p, vx), ay = dot3(u + 9 + 3 * p, vy), az = dot3(u + 18 + 3 * p, vz);
+        tv[p] = yy[p] - ((ax + ay) + az);
     }
 #pragma unroll
-    for (int p = 0; p < 3; ++p) out[p] = dd[3 * p] * tv[0] + dd[3 * p + 1] * tv[1] + dd[3 * p + 2] * tv[2];
+    for (int p = 0; p < 3; ++p) out[p] = dot3(dd + 3 * p, tv);
 }
 
 // ---------------------------------------------------------------- factorisation (one launch per hyperplane)
@@ -185,298 +192,401 @@ __global__ __launch_bounds__(BS) void k_bwd_plane(Geo g, const int32_t *__restri
 }
 
 // ---------------------------------------------------------------- pipelined tile-lane sweeps
+//
+// One workgroup per tile at a time: wave 0 computes, waves 1..NL stream the
+// tile's per-step data into a ring of D slots in LDS (warp specialisation).
+// A wavefront can keep at most 63 memory operations outstanding and retires
+// them in order, so one wave alone cannot hide HBM latency for the ~30 loads
+// each step needs; each loader wave owns every NL-th step and brings its own
+// outstanding-load budget.
+//
+// Step t of a tile: lane (i,j) of the compute wave handles cell k = t - (i+j)
+// (forward) or k = nz-1-(t-(14-i-j)) (backward); the cell's data sit in row
+// (t mod nz) (forward) or ((nz+13-t) mod nz) (backward) of the tile, so every
+// load is one coalesced 64-lane row.
+//
+// Face exchange between neighbouring tiles: face row s of a tile holds the
+// eight boundary values (three components each) that the neighbouring tile
+// needs at its local step s; the producing lane computes them at its own step
+// s + 7.  FP64 values are split into 32-bit halves, each stored with the
+// 32-bit call epoch in the upper half of a 64-bit word (FP32 values: one
+// word), so a word is valid exactly when its tag equals the current epoch --
+// no fences between tiles, no clearing between calls.  The loader of step t
+// reads the row (one word per lane), waits until every needed word carries
+// the epoch, and writes the values into the slot.  Tiles are handed out by an
+// atomic ticket in topological order, so a tile only waits on tiles held by
+// running workgroups; every wait is bounded by a wall-clock limit that raises
+// an error flag and makes all other waits give up at once.
 
-// Face words: FP64 values are split into two 32-bit halves, each stored with
-// the 32-bit epoch in the upper half of a 64-bit word; FP32 values take one word.
 template <typename T> struct FaceW;
 template <> struct FaceW<double> { static constexpr int W = 2; };
 template <> struct FaceW<float> { static constexpr int W = 1; };
 
-__device__ inline void face_put(uint64_t *p, double v, uint32_t ep)
-{
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    __hip_atomic_store(p, ((uint64_t)ep << 32) | (b & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(p + 1, ((uint64_t)ep << 32) | (b >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void face_put(uint64_t *p, float v, uint32_t ep)
-{
-    __hip_atomic_store(p, ((uint64_t)ep << 32) | (uint64_t)__float_as_uint(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ inline uint64_t face_ld(const uint64_t *p)
 {
     return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline double face_val(const uint64_t *w, double) { return __longlong_as_double((long long)((w[0] & 0xffffffffull) | (w[1] << 32))); }
-__device__ inline float face_val(const uint64_t *w, float) { return __uint_as_float((uint32_t)w[0]); }
-
-template <typename T>
-struct FaceSet {
-    uint64_t w[3 * FaceW<T>::W];
-};
-
-template <typename T>
-__device__ inline void face_load3(FaceSet<T> &f, const uint64_t *p)
+__device__ inline void face_st(uint64_t *p, uint64_t v)
 {
-#pragma unroll
-    for (int q = 0; q < 3 * FaceW<T>::W; ++q) f.w[q] = face_ld(p + q);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-template <typename T>
-__device__ inline bool face_ok(const FaceSet<T> &f, uint32_t ep)
+__device__ inline void face_put(uint64_t *p, double v, uint32_t ep)
 {
-    bool ok = true;
-#pragma unroll
-    for (int q = 0; q < 3 * FaceW<T>::W; ++q) ok = ok && ((uint32_t)(f.w[q] >> 32) == ep);
-    return ok;
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    face_st(p, ((uint64_t)ep << 32) | (b & 0xffffffffull));
+    face_st(p + 1, ((uint64_t)ep << 32) | (b >> 32));
 }
-
-// Wait (bounded) until the three values at p carry epoch ep; returns them.
-template <typename T>
-__device__ inline void face_wait(FaceSet<T> &f, const uint64_t *p, uint32_t ep, int32_t *flags, T *out)
+__device__ inline void face_put(uint64_t *p, float v, uint32_t ep)
 {
-    if (!face_ok(f, ep)) {
-        const uint64_t t0 = wall_clock64();
-        for (;;) {
-            face_load3(f, p);
-            if (face_ok(f, ep)) break;
-            // give up at the bound, or at once if another wait already timed out
-            const int32_t fl = __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((fl & FLAG_TIMEOUT) || wall_clock64() - t0 > SPIN_LIMIT_TICKS) {
-                atomicOr(&flags[0], FLAG_TIMEOUT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    const int W = FaceW<T>::W;
-#pragma unroll
-    for (int p3 = 0; p3 < 3; ++p3) out[p3] = face_val(&f.w[p3 * W], T());
+    face_st(p, ((uint64_t)ep << 32) | (uint64_t)__float_as_uint(v));
 }
 
 __device__ inline double shfl_d(double v, int src) { return __shfl(v, src, 64); }
 __device__ inline float shfl_d(float v, int src) { return __shfl(v, src, 64); }
+
+// Spin-loop guard: checks the clock and the shared error flag only every 256th
+// call (the flag read is a device-scope load, which waits for every memory
+// operation the wave still has in flight).
+__device__ inline bool spin_guard(int32_t *flags, uint64_t t0, uint32_t &n)
+{
+    if ((++n & 255u) != 0u) return false;
+    const int32_t fl = __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (fl & FLAG_TIMEOUT) return true;
+    if (wall_clock64() - t0 > SPIN_LIMIT_TICKS) {
+        atomicOr(&flags[0], FLAG_TIMEOUT);
+        return true;
+    }
+    return false;
+}
+
+__device__ inline bool timed_out(int32_t *flags, uint64_t t0)
+{
+    const int32_t fl = __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (fl & FLAG_TIMEOUT) return true;
+    if (wall_clock64() - t0 > SPIN_LIMIT_TICKS) {
+        atomicOr(&flags[0], FLAG_TIMEOUT);
+        return true;
+    }
+    return false;
+}
 
 struct SweepArgs {
     Geo g;
     const int32_t *tile_order;   // tiles in topological (anti-diagonal) order
     uint64_t *ticket;
     uint64_t ticket_base;
-    uint64_t *faceX;             // [NT][nz][8][3][W]
+    uint64_t *faceX;             // [NT][nz+7][24*W] words
     uint64_t *faceY;
     uint32_t epoch;
     int32_t *flags;
+    int D;                       // LDS ring slots
+    uint64_t *trace;             // optional: per tile [start, step 8 reached, end, steps that waited for data]
 };
 
-// Forward sweep y = L^{-1} r.  NE = 27 factor entries per cell.
-template <typename T, int PD>
-__global__ __launch_bounds__(64) void k_sweep_fwd(SweepArgs a, const T *__restrict__ Lf,
-                                                 const double *__restrict__ r, T *__restrict__ y)
+// per-step operands streamed by the loaders; all rows are [entries][64 lanes]
+template <typename T>
+struct SweepSrc {
+    const T *p0; int64_t s0, o0;                  // factor blocks (27): L (fwd) or U (bwd)
+    const T *p1; int64_t s1, o1;                  // D^{-1} (bwd only, 9)
+    const double *v64; const T *vT;               // 3-vector input: r (FP64, fwd) or y (T, bwd)
+};
+
+// NLOAD loader waves per workgroup (each keeps two steps in flight)
+template <int DIR, typename T, int NLOAD>
+__global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSrc<T> src, T *__restrict__ yout,
+                                                           double *__restrict__ zout)
 {
     constexpr int W = FaceW<T>::W;
+    constexpr int RW = 24 * W;                   // face words per row
+    extern __shared__ __align__(16) unsigned char smem[];
     const Geo &g = a.g;
-    const int L = threadIdx.x;
+    const int nz = g.nz, NT = g.ntx * g.nty, nsteps = nz + 14;
+    const int D = a.D;
+    constexpr int NE = DIR == 0 ? 30 : 39;       // T entries per lane per step (27 blocks [+9 D^-1] + 3 vector)
+    constexpr int slot_elems = NE * 64 + 48;     // + x and y faces (8 entries x 3 components each)
+    T *ring = (T *)smem;
+    int32_t *tags = (int32_t *)(smem + (size_t)D * slot_elems * sizeof(T));
+    int32_t *consumed = tags + D;
+    int32_t *tile_sh = consumed + 1;
+    const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
     int li, lj;
     lane_ij(L, li, lj);
-    const int d = li + lj;
-    const int lx = (li > 0) ? ij_lane(li - 1, lj) : L;
-    const int ly = (lj > 0) ? ij_lane(li, lj - 1) : L;
-    const int NT = g.ntx * g.nty;
-    const int nz = g.nz;
-    const int nsteps = nz + 14;
+    const int64_t frow = (int64_t)(nz + 7) * RW;
+    if (threadIdx.x == 0) *consumed = 0;
+    for (int s = threadIdx.x; s < D; s += blockDim.x) tags[s] = 0;
+    __syncthreads();
+    int gstep = 0;   // running step count across tiles (tags are gstep + 1)
     for (;;) {
-        uint64_t tk = 0;
-        if (L == 0) tk = atomicAdd((unsigned long long *)a.ticket, 1ull);
-        tk = __shfl(tk, 0, 64) - a.ticket_base;
-        if (tk >= (uint64_t)NT) break;
-        const int T_ = a.tile_order[tk];
+        if (threadIdx.x == 0) {
+            const uint64_t tk = atomicAdd((unsigned long long *)a.ticket, 1ull) - a.ticket_base;
+            *tile_sh = (tk >= (uint64_t)NT) ? -1 : a.tile_order[DIR == 0 ? (int)tk : NT - 1 - (int)tk];
+        }
+        __syncthreads();
+        const int T_ = *tile_sh;
+        __syncthreads();
+        if (T_ < 0) break;
         const int tx = T_ % g.ntx, ty = T_ / g.ntx;
         const int64_t rowbase = (int64_t)T_ * nz;
-        const bool cx = (li == 0 && tx > 0), cy = (lj == 0 && ty > 0);
-        const bool px = (li == 7 && tx < g.ntx - 1), py = (lj == 7 && ty < g.nty - 1);
-        const uint64_t *fxin = a.faceX + ((int64_t)(T_ - 1) * nz * 8 * 3 * W);
-        const uint64_t *fyin = a.faceY + ((int64_t)(T_ - g.ntx) * nz * 8 * 3 * W);
-        uint64_t *fxout = a.faceX + ((int64_t)T_ * nz * 8 * 3 * W);
-        uint64_t *fyout = a.faceY + ((int64_t)T_ * nz * 8 * 3 * W);
-
-        T ring_l[PD][27];
-        double ring_r[PD][3];
-        FaceSet<T> ring_fx[PD], ring_fy[PD];
-        auto issue = [&](int u, int t) {
-            const int k = t - d;
-            if (t < nsteps && k >= 0 && k < nz) {
-                const int row = wrap_nz(t, nz);
-                const T *lp = Lf + ((rowbase + row) * 27) * 64 + L;
+        const bool hasx = DIR == 0 ? tx > 0 : tx < g.ntx - 1;
+        const bool hasy = DIR == 0 ? ty > 0 : ty < g.nty - 1;
+        if (wave > 0) {
+            // ------------------------------------------------ loader waves
+            const uint64_t *xin = a.faceX + (int64_t)(DIR == 0 ? T_ - 1 : T_ + 1) * frow;
+            const uint64_t *yin = a.faceY + (int64_t)(DIR == 0 ? T_ - g.ntx : T_ + g.ntx) * frow;
+            const int eq = L / (3 * W);   // face entry of this lane's word
+            constexpr int nv = DIR == 0 ? 27 : 36;
+            struct Regs {
+                T v[nv + 3];
+                uint64_t wx, wy;   // face words of the same step
+            };
+            // face words: always two loads per lane (a tile without that neighbour
+            // reads its own face buffer, an in-range dummy); validity is decided later
+            const uint64_t *xsrc = hasx ? xin : a.faceX + (int64_t)T_ * frow;
+            const uint64_t *ysrc = hasy ? yin : a.faceY + (int64_t)T_ * frow;
+            const int lq = L < RW ? L : RW - 1;
+            // loads are issued unconditionally (out-of-range steps re-read a valid
+            // row) so that the outstanding-load count is static and the compiler
+            // can wait for exactly the buffer it needs
+            // Lanes are ordered by anti-diagonal, so the lanes whose cell is in range
+            // at step t are one contiguous range [lo, hi]; an out-of-range lane reads
+            // the slot of the nearest in-range lane instead of its own, so a step
+            // touches only the cache lines its in-range lanes need (the wrapped
+            // layout would otherwise re-read rows at the start and end of a column).
+            auto issue_lane = [&](int tc) {
+                const int dmin = DIR == 0 ? (tc - nz + 1 > 0 ? tc - nz + 1 : 0) : (14 - tc > 0 ? 14 - tc : 0);
+                const int dmax = DIR == 0 ? (tc < 14 ? tc : 14) : (13 - tc + nz < 14 ? 13 - tc + nz : 14);
+                const int lo = lane_first(dmin), hi = lane_first(dmax + 1) - 1;
+                return L < lo ? lo : (L > hi ? hi : L);
+            };
+            auto issue_data = [&](Regs &R, int t) {
+                const int tc = t < nsteps ? t : nsteps - 1;
+                const int row = DIR == 0 ? wrap_nz(tc, nz) : wrap_nz(nz + 13 - tc, nz);
+                const int64_t rb = rowbase + row;
+                const int Ls = issue_lane(tc);
+                const T *q0 = src.p0 + rb * src.s0 + src.o0 + Ls;
 #pragma unroll
-                for (int e = 0; e < 27; ++e) ring_l[u][e] = lp[e * 64];
-                const double *rp = r + (rowbase + row) * 192 + L;
+                for (int e = 0; e < 27; ++e) R.v[e] = q0[e * 64];
+                if constexpr (DIR == 1) {
+                    const T *q1 = src.p1 + rb * src.s1 + src.o1 + Ls;
 #pragma unroll
-                for (int p = 0; p < 3; ++p) ring_r[u][p] = rp[p * 64];
-                if (cx) face_load3(ring_fx[u], fxin + ((int64_t)k * 8 + lj) * 3 * W);
-                if (cy) face_load3(ring_fy[u], fyin + ((int64_t)k * 8 + li) * 3 * W);
-            }
-        };
+                    for (int e = 0; e < 9; ++e) R.v[27 + e] = q1[e * 64];
+                }
+                if constexpr (DIR == 0) {
+                    const double *q2 = src.v64 + rb * 192 + Ls;
 #pragma unroll
-        for (int u = 0; u < PD; ++u) issue(u, u);
-        T last[3] = {0, 0, 0};
-        for (int t0 = 0; t0 < nsteps; t0 += PD) {
+                    for (int p = 0; p < 3; ++p) R.v[nv + p] = (T)q2[p * 64];
+                } else {
+                    const T *q2 = src.vT + rb * 192 + Ls;
 #pragma unroll
-            for (int u = 0; u < PD; ++u) {
-                const int t = t0 + u;
-                if (t < nsteps) {
-                    const int k = t - d;
-                    const bool act = (k >= 0 && k < nz);
-                    T vx[3], vy[3], vz[3];
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) {
-                        vx[p] = shfl_d(last[p], lx);
-                        vy[p] = shfl_d(last[p], ly);
-                        vz[p] = last[p];
+                    for (int p = 0; p < 3; ++p) R.v[nv + p] = q2[p * 64];
+                }
+                // face words of the same step, issued with its data (they may still
+                // be stale when the step is delivered; then they are polled again)
+                const int tr = t < nz + 7 ? t : nz + 6;
+                R.wx = face_ld(xsrc + (int64_t)tr * RW + lq);
+                R.wy = face_ld(ysrc + (int64_t)tr * RW + lq);
+            };
+            // face words of step t (entries whose cell exists)
+            auto face_need = [&](int t) {
+                const int kk = DIR == 0 ? t - eq : t - 7 + eq;
+                return L < RW && kk >= 0 && kk < nz;
+            };
+            auto finish = [&](const Regs &R, int t) {
+                uint64_t wx = R.wx, wy = R.wy;
+                const int G = gstep + t;
+                const int slot = G % D;
+                T *sl = ring + (size_t)slot * slot_elems;
+                // wait for the compute wave to release this slot (step G - D)
+                if (__hip_atomic_load(consumed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G - D + 1) {
+                    const uint64_t t0 = wall_clock64();
+                    uint32_t n = 0;
+                    while (__hip_atomic_load(consumed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G - D + 1) {
+                        if (spin_guard(a.flags, t0, n)) break;
+                        __builtin_amdgcn_s_sleep(1);
                     }
-                    T out[3] = {0, 0, 0};
-                    if (act) {
-                        if (li == 0) {
-                            if (cx) face_wait(ring_fx[u], fxin + ((int64_t)k * 8 + lj) * 3 * W, a.epoch, a.flags, vx);
-                            else vx[0] = vx[1] = vx[2] = 0;
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+                for (int e = 0; e < nv + 3; ++e) sl[e * 64 + L] = R.v[e];
+                const bool need = face_need(t);
+                const bool okx = !hasx || !need || (uint32_t)(wx >> 32) == a.epoch;
+                const bool oky = !hasy || !need || (uint32_t)(wy >> 32) == a.epoch;
+                if (!(okx && oky)) {
+                    // Slow path.  Rows become valid in step order, so first wait (in
+                    // LDS) until the previous step has been delivered; then only the
+                    // loader of the oldest pending step polls device memory, with
+                    // exponential backoff, instead of every waiting wave at once.
+                    const uint64_t t0 = wall_clock64();
+                    uint32_t n = 0;
+                    if (t > 0)
+                        while (__hip_atomic_load(&tags[(G - 1) % D], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G) {
+                            if (spin_guard(a.flags, t0, n)) break;
+                            __builtin_amdgcn_s_sleep(2);
                         }
-                        if (lj == 0) {
-                            if (cy) face_wait(ring_fy[u], fyin + ((int64_t)k * 8 + li) * 3 * W, a.epoch, a.flags, vy);
-                            else vy[0] = vy[1] = vy[2] = 0;
-                        }
-                        if (k == 0) vz[0] = vz[1] = vz[2] = 0;
-                        T rr[3] = {(T)ring_r[u][0], (T)ring_r[u][1], (T)ring_r[u][2]};
-                        fwd_cell(ring_l[u], vz, vy, vx, rr, out);
-                        const int row = wrap_nz(t, nz);
-                        T *yp = y + (rowbase + row) * 192 + L;
+                    int backoff = 1;
+                    for (;;) {
+                        if (hasx) wx = face_ld(xin + (int64_t)t * RW + L);
+                        if (hasy) wy = face_ld(yin + (int64_t)t * RW + L);
+                        const bool ok = (!hasx || !need || (uint32_t)(wx >> 32) == a.epoch) &&
+                                        (!hasy || !need || (uint32_t)(wy >> 32) == a.epoch);
+                        if (__ballot(!ok) == 0ull) break;
+                        if (spin_guard(a.flags, t0, n)) break;
+                        for (int q = 0; q < backoff; ++q) __builtin_amdgcn_s_sleep(8);
+                        backoff = backoff < 16 ? 2 * backoff : 16;
+                    }
+                }
+                // the low 32 bits of word q are 32-bit half q of the row's values
+                uint32_t *fs = (uint32_t *)(sl + NE * 64);
+                if (L < RW) {
+                    fs[L] = (uint32_t)wx;
+                    fs[RW + L] = (uint32_t)wy;
+                }
+                // the slot's LDS writes complete before its tag is published
+                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __hip_atomic_store(&tags[slot], G + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            };
+            // two steps in flight per loader: the next step's loads are issued
+            // before the current one is delivered
+            Regs A, B;
+            int t = wave - 1;
+            issue_data(A, t);
+            for (; t < nsteps; t += 2 * NLOAD) {
+                issue_data(B, t + NLOAD);
+                finish(A, t);
+                if (t + NLOAD >= nsteps) break;
+                issue_data(A, t + 2 * NLOAD);
+                finish(B, t + NLOAD);
+            }
+        } else {
+            // ------------------------------------------------ compute wave
+            const int d = li + lj;
+            const int e_ = 14 - d;
+            const int lx = DIR == 0 ? (li > 0 ? ij_lane(li - 1, lj) : L) : (li < 7 ? ij_lane(li + 1, lj) : L);
+            const int ly = DIR == 0 ? (lj > 0 ? ij_lane(li, lj - 1) : L) : (lj < 7 ? ij_lane(li, lj + 1) : L);
+            const bool cx = DIR == 0 ? li == 0 : li == 7, cy = DIR == 0 ? lj == 0 : lj == 7;
+            const bool px = DIR == 0 ? (li == 7 && tx < g.ntx - 1) : (li == 0 && tx > 0);
+            const bool py = DIR == 0 ? (lj == 7 && ty < g.nty - 1) : (lj == 0 && ty > 0);
+            uint64_t *fxo = a.faceX + (int64_t)T_ * frow;
+            uint64_t *fyo = a.faceY + (int64_t)T_ * frow;
+            T last[3] = {0, 0, 0};
+            uint32_t waited = 0;
+            if (a.trace && L == 0) a.trace[4 * T_ + 0] = wall_clock64();
+            // operands of a step: slot data for this lane plus the face values of
+            // the boundary lanes, read from LDS one step ahead into one of two
+            // register sets (the loop is unrolled by two, so nothing is copied)
+            auto fetch = [&](T *nf, T *nfx, T *nfy, int t) {
+                const int G = gstep + t;
+                const int slot = G % D;
+                const T *sl = ring + (size_t)slot * slot_elems;
+                if (__hip_atomic_load(&tags[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != G + 1) {
+                    ++waited;
+                    const uint64_t t0 = wall_clock64();
+                    uint32_t n = 0;
+                    while (__hip_atomic_load(&tags[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != G + 1) {
+                        if (spin_guard(a.flags, t0, n)) break;
+                        __builtin_amdgcn_s_sleep(0);
+                    }
+                }
+                // LDS only: the slot's data were written before the tag (see the loader)
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+                for (int e = 0; e < NE; ++e) nf[e] = sl[e * 64 + L];
+                const T *fsv = sl + NE * 64;   // x face: entries [8][3], then y face
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    nfx[p] = fsv[lj * 3 + p];
+                    nfy[p] = fsv[24 + li * 3 + p];
+                }
+            };
+            // the slot of step t is in registers: hand it back to the loaders
+            auto release = [&](int t) {
+                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); global stores stay in flight
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                if (L == 0) __hip_atomic_store(consumed, gstep + t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            };
+            const T zx = hasx ? (T)1 : (T)0, zy = hasy ? (T)1 : (T)0;
+            auto step = [&](const T *f, const T *fx, const T *fy, int t) {
+                const int kk = DIR == 0 ? t - d : t - e_;
+                const bool act = kk >= 0 && kk < nz;
+                T vx[3], vy[3], vz[3];
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    vx[p] = shfl_d(last[p], lx);
+                    vy[p] = shfl_d(last[p], ly);
+                    vz[p] = last[p];
+                }
+                if (cx)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) vx[p] = zx * fx[p];
+                if (cy)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) vy[p] = zy * fy[p];
+                if (act) {
+                    if (kk == 0) vz[0] = vz[1] = vz[2] = 0;
+                    T out[3];
+                    if (DIR == 0) {
+                        fwd_cell(f, vz, vy, vx, f + 27, out);
+                    } else {
+                        bwd_cell(f, f + 27, vx, vy, vz, f + 36, out);
+                    }
+                    const int row = DIR == 0 ? wrap_nz(t, nz) : wrap_nz(nz + 13 - t, nz);
+                    if (DIR == 0) {
+                        T *yp = yout + (rowbase + row) * 192 + L;
 #pragma unroll
                         for (int p = 0; p < 3; ++p) yp[p * 64] = out[p];
-                        if (px) {
-                            uint64_t *f = fxout + ((int64_t)k * 8 + lj) * 3 * W;
+                    } else {
+                        double *zp = zout + (rowbase + row) * 192 + L;
 #pragma unroll
-                            for (int p = 0; p < 3; ++p) face_put(f + p * W, out[p], a.epoch);
-                        }
-                        if (py) {
-                            uint64_t *f = fyout + ((int64_t)k * 8 + li) * 3 * W;
+                        for (int p = 0; p < 3; ++p) zp[p * 64] = (double)out[p];
+                    }
+                    if (px) {
+                        uint64_t *fp = fxo + (int64_t)(t - 7) * RW + lj * 3 * W;
 #pragma unroll
-                            for (int p = 0; p < 3; ++p) face_put(f + p * W, out[p], a.epoch);
-                        }
+                        for (int p = 0; p < 3; ++p) face_put(fp + p * W, out[p], a.epoch);
+                    }
+                    if (py) {
+                        uint64_t *fp = fyo + (int64_t)(t - 7) * RW + li * 3 * W;
+#pragma unroll
+                        for (int p = 0; p < 3; ++p) face_put(fp + p * W, out[p], a.epoch);
                     }
 #pragma unroll
                     for (int p = 0; p < 3; ++p) last[p] = out[p];
-                    issue(u, t + PD);
+                } else {
+                    last[0] = last[1] = last[2] = 0;
                 }
+            };
+            T fa[NE], fxa[3], fya[3], fb[NE], fxb[3], fyb[3];
+            fetch(fa, fxa, fya, 0);
+            for (int t = 0; t < nsteps; t += 2) {
+                if (a.trace && L == 0 && t == 8) a.trace[4 * T_ + 1] = wall_clock64();
+                release(t);
+                if (t + 1 < nsteps) fetch(fb, fxb, fyb, t + 1);
+                step(fa, fxa, fya, t);
+                if (t + 1 >= nsteps) break;
+                release(t + 1);
+                if (t + 2 < nsteps) fetch(fa, fxa, fya, t + 2);
+                step(fb, fxb, fyb, t + 1);
+            }
+            if (a.trace && L == 0) {
+                a.trace[4 * T_ + 2] = wall_clock64();
+                a.trace[4 * T_ + 3] = waited;
             }
         }
+        gstep += nsteps;
+        __syncthreads();
     }
 }
 
-// Backward sweep z = U^{-1} y.  Upper blocks are read at U + row*u_stride +
-// u_off: the FP32 copy [row][27][64], or the FP64 matrix A itself (offset 36*64).
-template <typename T, int PD>
-__global__ __launch_bounds__(64) void k_sweep_bwd(SweepArgs a, const T *__restrict__ Dinv,
-                                                 const T *__restrict__ U, int64_t u_stride, int64_t u_off,
-                                                 const T *__restrict__ y, double *__restrict__ z)
-{
-    constexpr int W = FaceW<T>::W;
-    const Geo &g = a.g;
-    const int L = threadIdx.x;
-    int li, lj;
-    lane_ij(L, li, lj);
-    const int e_ = 14 - (li + lj);
-    const int lx = (li < 7) ? ij_lane(li + 1, lj) : L;
-    const int ly = (lj < 7) ? ij_lane(li, lj + 1) : L;
-    const int NT = g.ntx * g.nty;
-    const int nz = g.nz;
-    const int nsteps = nz + 14;
-    for (;;) {
-        uint64_t tk = 0;
-        if (L == 0) tk = atomicAdd((unsigned long long *)a.ticket, 1ull);
-        tk = __shfl(tk, 0, 64) - a.ticket_base;
-        if (tk >= (uint64_t)NT) break;
-        const int T_ = a.tile_order[NT - 1 - (int)tk];
-        const int tx = T_ % g.ntx, ty = T_ / g.ntx;
-        const int64_t rowbase = (int64_t)T_ * nz;
-        const bool cx = (li == 7 && tx < g.ntx - 1), cy = (lj == 7 && ty < g.nty - 1);
-        const bool px = (li == 0 && tx > 0), py = (lj == 0 && ty > 0);
-        const uint64_t *fxin = a.faceX + ((int64_t)(T_ + 1) * nz * 8 * 3 * W);
-        const uint64_t *fyin = a.faceY + ((int64_t)(T_ + g.ntx) * nz * 8 * 3 * W);
-        uint64_t *fxout = a.faceX + ((int64_t)T_ * nz * 8 * 3 * W);
-        uint64_t *fyout = a.faceY + ((int64_t)T_ * nz * 8 * 3 * W);
+// loader waves: 7, except the FP64 backward sweep whose 39-entry double
+// buffers need the 512-register budget of a 4-wave workgroup
+template <int DIR, typename T> struct NLoad { static constexpr int v = (DIR == 1 && sizeof(T) == 8) ? 3 : 7; };
 
-        T ring_u[PD][27];
-        T ring_d[PD][9];
-        T ring_y[PD][3];
-        FaceSet<T> ring_fx[PD], ring_fy[PD];
-        auto issue = [&](int u, int t) {
-            const int kk = t - e_;
-            if (t < nsteps && kk >= 0 && kk < nz) {
-                const int k = nz - 1 - kk;
-                const int row = wrap_nz(nz + 13 - t, nz);
-                const T *up = U + (rowbase + row) * u_stride + u_off + L;
-#pragma unroll
-                for (int e = 0; e < 27; ++e) ring_u[u][e] = up[e * 64];
-                const T *dp = Dinv + ((rowbase + row) * 9) * 64 + L;
-#pragma unroll
-                for (int e = 0; e < 9; ++e) ring_d[u][e] = dp[e * 64];
-                const T *yp = y + (rowbase + row) * 192 + L;
-#pragma unroll
-                for (int p = 0; p < 3; ++p) ring_y[u][p] = yp[p * 64];
-                if (cx) face_load3(ring_fx[u], fxin + ((int64_t)k * 8 + lj) * 3 * W);
-                if (cy) face_load3(ring_fy[u], fyin + ((int64_t)k * 8 + li) * 3 * W);
-            }
-        };
-#pragma unroll
-        for (int u = 0; u < PD; ++u) issue(u, u);
-        T last[3] = {0, 0, 0};
-        for (int t0 = 0; t0 < nsteps; t0 += PD) {
-#pragma unroll
-            for (int u = 0; u < PD; ++u) {
-                const int t = t0 + u;
-                if (t < nsteps) {
-                    const int kk = t - e_;
-                    const bool act = (kk >= 0 && kk < nz);
-                    const int k = nz - 1 - kk;
-                    T vx[3], vy[3], vz[3];
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) {
-                        vx[p] = shfl_d(last[p], lx);
-                        vy[p] = shfl_d(last[p], ly);
-                        vz[p] = last[p];
-                    }
-                    T out[3] = {0, 0, 0};
-                    if (act) {
-                        if (li == 7) {
-                            if (cx) face_wait(ring_fx[u], fxin + ((int64_t)k * 8 + lj) * 3 * W, a.epoch, a.flags, vx);
-                            else vx[0] = vx[1] = vx[2] = 0;
-                        }
-                        if (lj == 7) {
-                            if (cy) face_wait(ring_fy[u], fyin + ((int64_t)k * 8 + li) * 3 * W, a.epoch, a.flags, vy);
-                            else vy[0] = vy[1] = vy[2] = 0;
-                        }
-                        if (kk == 0) vz[0] = vz[1] = vz[2] = 0;
-                        bwd_cell(ring_u[u], ring_d[u], vx, vy, vz, ring_y[u], out);
-                        const int row = wrap_nz(nz + 13 - t, nz);
-                        double *zp = z + (rowbase + row) * 192 + L;
-#pragma unroll
-                        for (int p = 0; p < 3; ++p) zp[p * 64] = (double)out[p];
-                        if (px) {
-                            uint64_t *f = fxout + ((int64_t)k * 8 + lj) * 3 * W;
-#pragma unroll
-                            for (int p = 0; p < 3; ++p) face_put(f + p * W, out[p], a.epoch);
-                        }
-                        if (py) {
-                            uint64_t *f = fyout + ((int64_t)k * 8 + li) * 3 * W;
-#pragma unroll
-                            for (int p = 0; p < 3; ++p) face_put(f + p * W, out[p], a.epoch);
-                        }
-                    }
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) last[p] = out[p];
-                    issue(u, t + PD);
-                }
-            }
-        }
-    }
+template <typename T>
+inline size_t sweep_slot_bytes(int dir)
+{
+    const int NE = (dir == 0) ? 30 : 39;
+    return (size_t)(NE * 64 + 48) * sizeof(T);
 }
 
 // ---------------------------------------------------------------- the preconditioner object
@@ -499,6 +609,7 @@ struct Bilu0 : PcImpl {
     {
         dev_free(Lf); dev_free(Dinv); dev_free(Lf32); dev_free(Dinv32); dev_free(U32);
         dev_free(ybuf); dev_free(zt32); dev_free(zt64); dev_free(faceX); dev_free(faceY); dev_free(tile_order);
+        dev_free(trace);
     }
     int64_t bytes() const override { return nbytes; }
 
@@ -557,7 +668,12 @@ struct Bilu0 : PcImpl {
         }
         if (pipelined) {
             const int W = fp32 ? 1 : 2;
-            const size_t fb = (size_t)NT * g.nz * 8 * 3 * W * sizeof(uint64_t);
+            const size_t fb = (size_t)NT * (g.nz + 7) * 24 * W * sizeof(uint64_t);
+            // the sweeps keep a multi-slot ring in LDS: allow the full LDS per workgroup
+            RSV_HIP(c, hipFuncSetAttribute((const void *)k_sweep<0, double, NLoad<0, double>::v>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max));
+            RSV_HIP(c, hipFuncSetAttribute((const void *)k_sweep<1, double, NLoad<1, double>::v>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max));
+            RSV_HIP(c, hipFuncSetAttribute((const void *)k_sweep<0, float, NLoad<0, float>::v>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max));
+            RSV_HIP(c, hipFuncSetAttribute((const void *)k_sweep<1, float, NLoad<1, float>::v>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max));
             s = alloc((void **)&faceX, fb);
             if (s == RSV_OK) s = alloc((void **)&faceY, fb);
             if (s == RSV_OK) s = alloc((void **)&tile_order, (size_t)NT * sizeof(int32_t));
@@ -596,6 +712,8 @@ struct Bilu0 : PcImpl {
         return RSV_OK;
     }
 
+    uint64_t *trace = nullptr;   // RSV_SWEEP_TRACE=<file>: per-tile timestamps of every pipelined sweep
+
     SweepArgs sweep_args(uint64_t nwaves)
     {
         const Geo &g = M->g->geo;
@@ -609,54 +727,104 @@ struct Bilu0 : PcImpl {
         a.epoch = c->epoch++;
         if (c->epoch == 0) c->epoch = 1;
         a.flags = c->d_flags;
+        a.trace = trace;
         c->ticket_base[0] += (uint64_t)(g.ntx * g.nty) + nwaves;
         return a;
     }
 
+    // workgroups of the pipelined sweeps: one per CU (each holds a large LDS ring)
     int nwaves() const
     {
         const int NT = M->g->geo.ntx * M->g->geo.nty;
-        return std::max(1, std::min(NT, c->num_cu * 4));
+        return std::max(1, std::min(NT, c->num_cu));
+    }
+
+    void dump_trace(int dir)
+    {
+        const char *path = getenv("RSV_SWEEP_TRACE");
+        if (!path || !trace) return;
+        const int NT = M->g->geo.ntx * M->g->geo.nty;
+        std::vector<uint64_t> h((size_t)NT * 4);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return;
+        if (hipMemcpy(h.data(), trace, h.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess) return;
+        FILE *fp = fopen(path, "a");
+        if (!fp) return;
+        fprintf(fp, "sweep dir=%d ntx=%d nty=%d nz=%d\n", dir, M->g->geo.ntx, M->g->geo.nty, M->g->geo.nz);
+        for (int t = 0; t < NT; ++t)
+            fprintf(fp, "%d %llu %llu %llu %llu\n", t, (unsigned long long)h[4 * t], (unsigned long long)h[4 * t + 1],
+                    (unsigned long long)h[4 * t + 2], (unsigned long long)h[4 * t + 3]);
+        fclose(fp);
     }
 
     rsv_status apply(const double *r, double *z) override
     {
+        if (pipelined && getenv("RSV_SWEEP_TRACE") && !trace) {
+            const int NT = M->g->geo.ntx * M->g->geo.nty;
+            rsv_status s = alloc((void **)&trace, (size_t)NT * 4 * sizeof(uint64_t));
+            if (s != RSV_OK) return s;
+        }
         if (!pipelined) {
             ProfScope ps(c, RSV_K_ILU_FWD);
             if (fp32) return apply_plane<float>(r, z, Lf32, Dinv32, U32, zt32);
             return apply_plane<double>(r, z, Lf, Dinv, nullptr, zt64);
         }
+        const Geo &g = M->g->geo;
         const int nw = nwaves();
         if (fp32) {
             SweepArgs a = sweep_args(nw);
+            a.D = (int)sweep_ring_depth(c, 0, 1);
+            SweepSrc<float> s0{Lf32, (int64_t)27 * 64, 0, nullptr, 0, 0, r, nullptr};
+            size_t sh = (size_t)a.D * sweep_slot_bytes<float>(0) + 64 * sizeof(int32_t);
             int t1 = prof_begin(c, RSV_K_ILU_FWD);
-            hipLaunchKernelGGL((k_sweep_fwd<float, 4>), dim3(nw), dim3(64), 0, c->stream, a, Lf32, r, (float *)ybuf);
+            hipLaunchKernelGGL((k_sweep<0, float, NLoad<0, float>::v>), dim3(nw), dim3(64 * (1 + NLoad<0, float>::v)), sh, c->stream, a, s0,
+                               (float *)ybuf, (double *)nullptr);
             prof_end(c, t1);
             RSV_LAUNCH(c);
             SweepArgs b = sweep_args(nw);
+            b.D = (int)sweep_ring_depth(c, 1, 1);
+            SweepSrc<float> s1{U32, (int64_t)27 * 64, 0, Dinv32, (int64_t)9 * 64, 0, nullptr, (const float *)ybuf};
+            sh = (size_t)b.D * sweep_slot_bytes<float>(1) + 64 * sizeof(int32_t);
             int t2 = prof_begin(c, RSV_K_ILU_BWD);
-            hipLaunchKernelGGL((k_sweep_bwd<float, 4>), dim3(nw), dim3(64), 0, c->stream, b, Dinv32, U32,
-                               (int64_t)27 * 64, (int64_t)0, (const float *)ybuf, z);
+            hipLaunchKernelGGL((k_sweep<1, float, NLoad<1, float>::v>), dim3(nw), dim3(64 * (1 + NLoad<1, float>::v)), sh, c->stream, b, s1,
+                               (float *)nullptr, z);
             prof_end(c, t2);
             RSV_LAUNCH(c);
         } else {
             SweepArgs a = sweep_args(nw);
+            a.D = (int)sweep_ring_depth(c, 0, 0);
+            SweepSrc<double> s0{Lf, (int64_t)27 * 64, 0, nullptr, 0, 0, r, nullptr};
+            size_t sh = (size_t)a.D * sweep_slot_bytes<double>(0) + 64 * sizeof(int32_t);
             int t1 = prof_begin(c, RSV_K_ILU_FWD);
-            hipLaunchKernelGGL((k_sweep_fwd<double, 3>), dim3(nw), dim3(64), 0, c->stream, a, Lf, r, (double *)ybuf);
+            hipLaunchKernelGGL((k_sweep<0, double, NLoad<0, double>::v>), dim3(nw), dim3(64 * (1 + NLoad<0, double>::v)), sh, c->stream, a, s0,
+                               (double *)ybuf, (double *)nullptr);
             prof_end(c, t1);
             RSV_LAUNCH(c);
+            dump_trace(0);
             SweepArgs b = sweep_args(nw);
+            b.D = (int)sweep_ring_depth(c, 1, 0);
+            SweepSrc<double> s1{M->d_A, (int64_t)63 * 64, (int64_t)36 * 64, Dinv, (int64_t)9 * 64, 0, nullptr,
+                                (const double *)ybuf};
+            sh = (size_t)b.D * sweep_slot_bytes<double>(1) + 64 * sizeof(int32_t);
             int t2 = prof_begin(c, RSV_K_ILU_BWD);
-            hipLaunchKernelGGL((k_sweep_bwd<double, 3>), dim3(nw), dim3(64), 0, c->stream, b, Dinv, M->d_A,
-                               (int64_t)63 * 64, (int64_t)36 * 64, (const double *)ybuf, z);
+            hipLaunchKernelGGL((k_sweep<1, double, NLoad<1, double>::v>), dim3(nw), dim3(64 * (1 + NLoad<1, double>::v)), sh, c->stream, b, s1,
+                               (double *)nullptr, z);
             prof_end(c, t2);
             RSV_LAUNCH(c);
+            dump_trace(1);
         }
+        (void)g;
         return RSV_OK;
     }
 };
 
 }  // namespace
+
+int64_t sweep_ring_depth(const rsv_ctx *c, int dir, int fp32)
+{
+    const size_t cap = (size_t)c->lds_max - 1024;
+    const size_t sb = fp32 ? sweep_slot_bytes<float>(dir) : sweep_slot_bytes<double>(dir);
+    return (int64_t)std::max<size_t>(2, std::min<size_t>(12, cap / sb));
+}
 
 rsv_status bilu0_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell)
 {

@@ -131,6 +131,8 @@ struct rsv_ctx {
     uint64_t ticket_base[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int32_t *d_flags = nullptr;   // [0] error flags, [1] bad cell (min)
     int num_cu = 256;
+    int lds_max = 65536;               // dynamic LDS bytes a workgroup may use
+    int lds_per_cu = 0;
     // kernel timing
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;   // pairs
@@ -246,6 +248,8 @@ rsv_status scal_set(rsv_ctx *c, int k0, const double *vals, int n);
 rsv_status bilu0_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
 rsv_status ras_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
 rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out);
+// LDS ring depth (slots) of the pipelined BILU0 sweeps for this device
+int64_t sweep_ring_depth(const rsv_ctx *c, int dir, int fp32);
 
 // pinned host error flag read (after sync); flags: bit0 timeout, bit1 zero pivot, bit2 pattern, bit3 nan
 rsv_status flags_check(rsv_ctx *c, int64_t *bad_cell);

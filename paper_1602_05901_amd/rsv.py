@@ -84,6 +84,7 @@ _SIGS = {
     "rsv_net_loss_grad": ([vp, vp, i32, vp, vp, vp, _P(ctypes.c_float), vp], i32),
     "rsv_profile_enable": ([vp, i32], i32),
     "rsv_profile_read": ([vp, vp, vp], i32),
+    "rsv_device_info": ([vp, vp, i32], i32),
 }
 K_NAMES = ["spmv", "ilu_fwd", "ilu_bwd", "ras", "ortho", "vec", "factor", "net"]
 
@@ -138,6 +139,13 @@ class Context:
             import torch
             stream = torch.cuda.current_stream(device).cuda_stream
         _check(self, lib().rsv_set_stream(self.h, stream))
+
+    def device_info(self):
+        import numpy as np
+        v = np.zeros(5, np.int64)
+        _check(self, lib().rsv_device_info(self.h, v.ctypes.data, 5))
+        return {"num_cu": int(v[0]), "lds_per_workgroup": int(v[1]), "lds_per_cu": int(v[2]),
+                "sweep_ring_fwd": int(v[3]), "sweep_ring_bwd": int(v[4])}
 
     def profile(self, on=True):
         _check(self, lib().rsv_profile_enable(self.h, 1 if on else 0))
