@@ -107,6 +107,20 @@ int orc_fgmres(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
                const double *b, double *x, int32_t m, double tol, int64_t maxit,
                orc_stats *st, double *hist);
 
+/* ---- learned preconditioner network (unet.c) ---- */
+double  orc_bf16(double x);      /* round to the nearest BF16 value (ties to even) */
+void    orc_conv3d_fwd(int nx, int ny, int nz, int cin, int cout, const double *x, const double *w,
+                       const double *b, double *y);
+void    orc_conv3d_bwd(int nx, int ny, int nz, int cin, int cout, const double *x, const double *w,
+                       const double *dy, double *dx, double *dw, double *db);
+int64_t orc_unet_nparams(int c0, int c1, int c2);
+int     orc_unet_forward(int c0, int c1, int c2, int nx, int ny, int nz, const double *params,
+                         const double *x0, double *y, int emulate_bf16);
+int     orc_unet_loss_grad(int c0, int c1, int c2, int nx, int ny, int nz, const double *params,
+                           const double *x0, const double *target, double *grad, double *loss, int emulate_bf16);
+double  orc_unet_prepare(int nx, int ny, int nz, const double *r, const double *lnk, double *x0);
+void    orc_adam(int64_t n, double *p, const double *g, double *m, double *v, int64_t t, double lr);
+
 /* plain dense 3x3 helpers exposed for the pins */
 int orc_inv3(const double *a, double *ainv);  /* LU with partial pivoting; 0 ok, -4 singular */
 

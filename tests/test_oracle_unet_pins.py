@@ -1,0 +1,134 @@
+"""Pins for the FP64 U-Net oracle: a library routine for single-channel
+convolutions, adjoint (dot-product) identities for every backward map,
+central finite differences for the whole network's gradient, the BF16
+rounding rule, and Adam's first step in closed form.  CPU only."""
+import numpy as np
+import pytest
+import scipy.ndimage as nd
+
+import oracle as O
+from oracle import unet as U
+from paper_1602_05901_amd import inputs as I
+
+O.lib()
+
+
+def rnd(n, seed):
+    return I.uniform(seed, 6, n, -1.0, 1.0)
+
+
+def test_conv_single_channel_is_library_correlation():
+    dims = (6, 5, 4)
+    nx, ny, nz = dims
+    x = rnd(nx * ny * nz, 1)
+    w = rnd(27, 2)
+    y = U.conv3d(dims, 1, 1, x, w, np.array([0.25]))
+    xa = x.reshape(nz, ny, nx)
+    ka = w.reshape(3, 3, 3)              # [dk][dj][di]
+    ref = nd.correlate(xa, ka, mode="constant", cval=0.0) + 0.25
+    assert np.allclose(y.reshape(nz, ny, nx), ref, rtol=0, atol=1e-13)
+
+
+def test_conv_multichannel_is_sum_of_channel_correlations():
+    dims = (5, 4, 3)
+    nx, ny, nz = dims
+    cin, cout = 3, 2
+    x = rnd(nx * ny * nz * cin, 3).reshape(-1, cin)
+    w = rnd(27 * cin * cout, 4).reshape(27, cin, cout)
+    y = U.conv3d(dims, cin, cout, x, w).reshape(-1, cout)
+    for co in range(cout):
+        ref = sum(nd.correlate(x[:, ci].reshape(nz, ny, nx), w[:, ci, co].reshape(3, 3, 3), mode="constant")
+                  for ci in range(cin))
+        assert np.allclose(y[:, co].reshape(nz, ny, nx), ref, atol=1e-13)
+
+
+def test_conv_backward_adjoint_identities():
+    dims = (4, 5, 3)
+    cin, cout = 3, 4
+    V = 60
+    x = rnd(V * cin, 5)
+    w = rnd(27 * cin * cout, 6)
+    dy = rnd(V * cout, 7)
+    dx, dw, db = U.conv3d_bwd(dims, cin, cout, x, w, dy)
+    # <conv(x), dy> = <x, dx>  (data adjoint)
+    assert np.dot(U.conv3d(dims, cin, cout, x, w), dy) == pytest.approx(np.dot(x, dx), rel=1e-12)
+    # conv is linear in w: <conv(x; w2), dy> = <w2, dw>
+    w2 = rnd(27 * cin * cout, 8)
+    assert np.dot(U.conv3d(dims, cin, cout, x, w2), dy) == pytest.approx(np.dot(w2, dw), rel=1e-12)
+    # bias: <1_b, dy> = db
+    b = rnd(cout, 9)
+    yb = U.conv3d(dims, cin, cout, np.zeros(V * cin), np.zeros(27 * cin * cout), b)
+    assert np.dot(yb, dy) == pytest.approx(np.dot(b, db), rel=1e-12)
+
+
+def test_network_gradient_finite_differences():
+    dims, ch = (8, 8, 4), (2, 3, 4)
+    P = U.nparams(*ch)
+    params = rnd(P, 10) * 0.5
+    x0 = rnd(8 * 8 * 4 * 4, 11)
+    target = rnd(8 * 8 * 4 * 3, 12)
+    loss, g = U.loss_grad(params, x0, target, dims, ch, emulate=False)
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([rng.choice(P, 60, replace=False), np.arange(P - 40, P)])
+    h = 1e-6
+    fd = []
+    for q in idx:
+        pp, pm = params.copy(), params.copy()
+        pp[q] += h
+        pm[q] -= h
+        lp, _ = U.loss_grad(pp, x0, target, dims, ch)
+        lm, _ = U.loss_grad(pm, x0, target, dims, ch)
+        fd.append((lp - lm) / (2 * h))
+    fd = np.array(fd)
+    assert np.linalg.norm(fd - g[idx]) <= 1e-6 * np.linalg.norm(fd)
+    # the loss itself: ||y - t||^2 / ||t||^2
+    y = U.forward(params, x0, dims, ch)
+    assert loss == pytest.approx(np.sum((y - target) ** 2) / np.sum(target ** 2), rel=1e-13)
+
+
+def test_network_structure_special_cases():
+    """Zero weights: output = final bias everywhere.  With only the final layer
+    active the network is a per-voxel linear map of the last ReLU features."""
+    dims, ch = (8, 4, 4), (2, 3, 4)
+    P = U.nparams(*ch)
+    params = np.zeros(P)
+    params[-3:] = [0.5, -1.0, 2.0]
+    y = U.forward(params, rnd(8 * 4 * 4 * 4, 13), dims, ch).reshape(-1, 3)
+    assert np.all(y == np.array([0.5, -1.0, 2.0]))
+    assert P == U.nparams(*ch)
+    # parameter count of the default architecture (~3.2e5)
+    assert U.nparams(16, 32, 64) == (27 * (4 * 16 + 16 * 16 + 16 * 32 + 32 * 32 + 32 * 64 + 64 * 64 + 64 * 32 + 32 * 32
+                                           + 32 * 16 + 16 * 16) + (16 + 16 + 32 + 32 + 64 + 64 + 32 + 32 + 16 + 16)
+                                     + 16 * 3 + 3)
+
+
+def test_bf16_rounding_rule():
+    # representable values are fixed points; halfway cases go to even
+    for v in [1.0, -2.5, 0.0, 3.140625]:
+        assert U.bf16(v) == v
+    one_plus = 1.0 + 2.0 ** -8          # halfway between 1 and 1 + 2^-7: ties to even -> 1
+    assert U.bf16(one_plus) == 1.0
+    assert U.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6    # halfway, odd below -> rounds up
+    x = rnd(1000, 14) * 100
+    assert np.array_equal(U.bf16_array(x), np.array([U.bf16(v) for v in x]))
+    assert np.max(np.abs(U.bf16_array(x) - x) / np.abs(x)) <= 2.0 ** -8
+
+
+def test_prepare_normalisation():
+    dims = (4, 4, 4)
+    r = rnd(3 * 64, 15) * 7.0
+    lnk = rnd(64, 16) * 3 + 1
+    x0, s = U.prepare(r, lnk, dims)
+    x0 = x0.reshape(-1, 4)
+    assert s == pytest.approx(np.sqrt(np.mean(r ** 2)))
+    assert np.sqrt(np.mean(x0[:, :3] ** 2)) == pytest.approx(1.0)
+    assert np.mean(x0[:, 3]) == pytest.approx(0.0, abs=1e-12) and np.std(x0[:, 3]) == pytest.approx(1.0)
+
+
+def test_adam_first_step_closed_form():
+    g = rnd(50, 17)
+    p0 = rnd(50, 18)
+    p1, m, v = U.adam(p0, g, np.zeros(50), np.zeros(50), 1, 1e-3)
+    # bias-corrected first step: p -= lr * g / (|g| + eps)
+    assert np.allclose(p1, p0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
