@@ -211,7 +211,10 @@ rsv_status rsv_net_save(rsv_net *net, const char *path);
 rsv_status rsv_net_load(rsv_net *net, const char *path);
 /* Inference z = ||r||_rms * N(r / ||r||_rms, lnk) on grid g.  r, z: device
  * FP64 vectors (block-row order); lnk: device FP32 per cell (standardised
- * inside).  Errors: RSV_ERR_ARG (grid dims not multiples of 4). */
+ * inside).  Errors: RSV_ERR_ARG (grid dims not multiples of 4).  A network
+ * keeps one set of activation buffers, sized for the last grid it ran on:
+ * calls on one network (inference, training, applies of preconditioners
+ * built on it) must not overlap in time. */
 rsv_status rsv_net_forward(rsv_net *net, rsv_grid *g, const double *r, const float *lnk, double *z);
 /* One Adam step on a batch of `nb` samples on grid g: inputs r[nb][3*ncell]
  * (device FP64), targets e[nb][3*ncell] (device FP64), lnk[nb][ncell]
@@ -223,6 +226,23 @@ rsv_status rsv_net_train_step(rsv_net *net, rsv_grid *g, int32_t nb, const doubl
  * parameter (HOST array of rsv_net_num_params floats).  For gradient checks. */
 rsv_status rsv_net_loss_grad(rsv_net *net, rsv_grid *g, int32_t nb, const double *r, const double *e,
                              const float *lnk, float *loss_out, float *grad_out);
+
+/* One 3x3x3 convolution layer of the network (zero padding, stride 1), the
+ * building block the network's forward and training passes are made of;
+ * exposed so each can be checked on its own.  Voxel v = i + nx*(j + ny*k);
+ * tensors are channels-last [v][c].  x: DEVICE BF16 bit patterns [V][cin];
+ * w: DEVICE FP32 [27][cin][cout] with tap (dk+1)*9 + (dj+1)*3 + (di+1)
+ * (rounded to BF16 inside); b: DEVICE FP32 [cout] or NULL; y: DEVICE FP32
+ * [V][cout] = b + sum_tap sum_ci w x(shifted).  cin a multiple of 4 up to
+ * 64, cout 16, 32 or 64; otherwise RSV_ERR_ARG.  Synchronous. */
+rsv_status rsv_conv3d(rsv_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t cin, int32_t cout,
+                      const uint16_t *x, const float *w, const float *b, float *y);
+/* Its gradients for an output gradient dy (DEVICE BF16 [V][cout]): dx =
+ * the adjoint convolution (DEVICE FP32 [V][cin], needs cin 16/32/64),
+ * dw (DEVICE FP32 [27][cin][cout]), db (DEVICE FP32 [cout]); any of the
+ * three may be NULL.  Synchronous. */
+rsv_status rsv_conv3d_bwd(rsv_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int32_t cin, int32_t cout,
+                          const uint16_t *x, const float *w, const uint16_t *dy, float *dx, float *dw, float *db);
 
 /* ---------------------------------------------------------------- kernel timing (diagnostics) */
 

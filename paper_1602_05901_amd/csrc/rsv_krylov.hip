@@ -413,7 +413,7 @@ rsv_status rsv_solve(rsv_matrix *A, rsv_precond *P, const rsv_solver_params *p, 
     if (s == RSV_OK) s = launch_nat_to_tl(c, A->g->geo, x, xt);
     if (s == RSV_OK) s = launch_nonfinite(c, n, bt, SC_MISC);
     if (s == RSV_OK) s = launch_dot(c, n, bt, bt, SC_BB);
-    if (s == RSV_OK) s = scal_to_host(c, 0, SC_BB + 1);
+    if (s == RSV_OK) s = scal_to_host(c, 0, SC_MISC + 1);   // slots SC_BB and SC_MISC
     if (s != RSV_OK) return st->status = s;
     double bad = c->h_scal[SC_MISC];
     s = launch_nonfinite(c, n, xt, SC_MISC);

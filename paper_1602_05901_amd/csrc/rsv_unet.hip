@@ -1,20 +1,1099 @@
-// Learned preconditioner (U-Net) -- placeholder until the network kernels land.
+// Learned preconditioner: a 3-level 3-D U-Net residual -> correction map used
+// inside flexible GMRES, with block ILU(0) as the fallback (the paper's
+// user-defined preconditioner hook, PC_USER with assemble / solve / destroy).
+//
+// Network (channels c0/c1/c2, default 16/32/64, 3x3x3 kernels, zero padding):
+//   x0 = [r/s (3 channels), standardised ln k]           s = rms(r)
+//   a1 = relu(conv0(x0)),  s1 = relu(conv1(a1))           full resolution
+//   a2 = relu(conv2(pool(s1))), s2 = relu(conv3(a2))     1/2
+//   a3 = relu(conv4(pool(s2))), b3 = relu(conv5(a3))     1/4
+//   d2a = relu(conv6(up(b3)) + s2), d2 = relu(conv7(d2a))
+//   d1a = relu(conv8(up(d2)) + s1), d1 = relu(conv9(d1a))
+//   y = conv10(d1)  (1x1x1 linear to 3 channels),  z = s * y
+// pool = 2x2x2 average, up = nearest-neighbour x2.  Activations and weights
+// are BF16; every convolution is an implicit GEMM on the CDNA matrix cores
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation).  Training: the backward
+// data pass is the same kernel on transposed, tap-flipped weights; the weight
+// gradient is a split-K MFMA GEMM over voxels with a fixed-order reduction;
+// Adam keeps FP32 master weights.
 #include "rsv_internal.h"
 
-rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *, PcImpl **)
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __host__ inline uint16_t f2bf(float f)
 {
-    return set_err(A->g->ctx, RSV_ERR_ARG, "learned preconditioner not available in this build");
+#ifdef __HIP_DEVICE_COMPILE__
+    uint32_t u = __float_as_uint(f);
+#else
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+#endif
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+constexpr int NL = 11;   // layers (10 convolutions 3x3x3 + final 1x1x1)
+
+struct Arch {
+    int c[3];
+    int cin[NL], cout[NL];
+    int64_t woff[NL], boff[NL], np;
+    void init(int c0, int c1, int c2)
+    {
+        c[0] = c0; c[1] = c1; c[2] = c2;
+        const int ci[NL] = {4, c0, c0, c1, c1, c2, c2, c1, c1, c0, c0};
+        const int co[NL] = {c0, c0, c1, c1, c2, c2, c1, c1, c0, c0, 3};
+        int64_t off = 0;
+        for (int l = 0; l < NL; ++l) {
+            cin[l] = ci[l];
+            cout[l] = co[l];
+            woff[l] = off;
+            off += (int64_t)(l < 10 ? 27 : 1) * ci[l] * co[l];
+            boff[l] = off;
+            off += co[l];
+        }
+        np = off;
+    }
+    int kb(int l) const { return (27 * cin[l] + 15) / 16; }        // K blocks, forward
+    int kbt(int l) const { return (27 * cout[l] + 15) / 16; }      // K blocks, backward data
+};
+
+struct ConvGeo {
+    int nx, ny, nz;   // output resolution
+    int up;           // input is the half-resolution tensor, read nearest-up-sampled
+    int cin, cout;
+    int64_t V;
+};
+
+__device__ inline int64_t src_voxel(const ConvGeo &g, int x, int y, int z, int dx, int dy, int dz)
+{
+    const int a = x + dx, b = y + dy, c = z + dz;
+    if (a < 0 || a >= g.nx || b < 0 || b >= g.ny || c < 0 || c >= g.nz) return -1;
+    if (g.up) {
+        const int hx = g.nx >> 1, hy = g.ny >> 1;
+        return (a >> 1) + (int64_t)hx * ((b >> 1) + (int64_t)hy * (c >> 1));
+    }
+    return a + (int64_t)g.nx * (b + (int64_t)g.ny * c);
+}
+
+// ---------------------------------------------------------------- convolution as implicit GEMM
+// One wavefront: 16 output voxels x (16*NB) output channels.  GEMM row m = voxel,
+// column n = output channel, k = tap*cin + ci.  Operand fragments of
+// v_mfma_f32_16x16x16_bf16: lane l holds A[m = l%16][k = 4*(l/16) .. +3] and
+// B[k = 4*(l/16) .. +3][n = l%16]; the result holds D[m = 4*(l/16) + i][n = l%16].
+// Weights are pre-packed so that B fragments are one 8-byte load per lane.
+template <int NB, bool OUT_BF16>
+__global__ __launch_bounds__(256) void k_conv(ConvGeo g, const uint16_t *__restrict__ X, const v4s *__restrict__ Wf,
+                                              int KB, const float *__restrict__ bias,
+                                              const uint16_t *__restrict__ skip, int relu, void *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t v0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    if (v0 >= g.V) return;
+    const int m = lane & 15, kq = 4 * (lane >> 4);
+    const int64_t v = v0 + m;
+    const bool live = v < g.V;   // the last tile of a level may be partial
+    const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
+    v4f acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int K = 27 * g.cin;
+    for (int kb = 0; kb < KB; ++kb) {
+        const int k = kb * 16 + kq;
+        v4s a = v4s{0, 0, 0, 0};
+        if (k < K && live) {
+            const int tap = k / g.cin, ci = k - tap * g.cin;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int64_t u = src_voxel(g, x, y, z, dx, dy, dz);
+            if (u >= 0) a = *(const v4s *)(X + u * g.cin + ci);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const v4s b = Wf[((int64_t)kb * NB + nb) * 64 + lane];
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nb], 0, 0, 0);
+        }
+    }
+    const int n = lane & 15, mr = 4 * (lane >> 4);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 16 + n;
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t vo = v0 + mr + i;
+            if (vo >= g.V) continue;
+            float val = acc[nb][i] + bb;
+            if (skip) val += bf2f(skip[vo * g.cout + co]);
+            if (relu) val = val > 0.f ? val : 0.f;
+            if (OUT_BF16) ((uint16_t *)out)[vo * g.cout + co] = f2bf(val);
+            else ((float *)out)[vo * g.cout + co] = val;
+        }
+    }
+}
+
+// Weight gradient dW[tap][ci][co] = sum_v X[v + off(tap)][ci] * G[v][co] as an
+// MFMA GEMM with k = voxel: rows m = ci, columns n = co.  grid.x = tile
+// (tap, ci block, co block), grid.y = voxel chunk (split K); one partial per
+// chunk, summed in chunk order afterwards.
+__global__ __launch_bounds__(256) void k_conv_dw(ConvGeo g, const uint16_t *__restrict__ X,
+                                                 const uint16_t *__restrict__ G, int nvb_chunk,
+                                                 float *__restrict__ partials)
+{
+    __shared__ float red[4][16][16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cib_n = (g.cin + 15) / 16, cob_n = g.cout / 16;
+    const int tile = blockIdx.x;
+    const int tap = tile / (cib_n * cob_n), cib = (tile / cob_n) % cib_n, cob = tile % cob_n;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int ci = cib * 16 + (lane & 15), co = cob * 16 + (lane & 15);
+    const int kq = 4 * (lane >> 4);
+    const int64_t nvb = (g.V + 15) / 16;
+    const int64_t vb_begin = (int64_t)blockIdx.y * nvb_chunk;
+    const int64_t vb_end = vb_begin + nvb_chunk < nvb ? vb_begin + nvb_chunk : nvb;
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int64_t vb = vb_begin + wave; vb < vb_end; vb += 4) {
+        v4s a, b;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t v = vb * 16 + kq + i;
+            a[i] = 0;
+            b[i] = 0;
+            if (v < g.V) {
+                const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
+                const int64_t u = src_voxel(g, x, y, z, dx, dy, dz);
+                if (u >= 0 && ci < g.cin) a[i] = (short)X[u * g.cin + ci];
+                b[i] = (short)G[v * g.cout + co];
+            }
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[wave][4 * (lane >> 4) + i][lane & 15] = acc[i];
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+        const float s = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
+        const int cir = cib * 16 + r, coc = cob * 16 + c;
+        if (cir < g.cin)
+            partials[(int64_t)blockIdx.y * 27 * g.cin * g.cout + ((int64_t)tap * g.cin + cir) * g.cout + coc] = s;
+    }
+}
+
+// sum over chunks (fixed order), added to the gradient
+__global__ void k_sum_chunks(const float *__restrict__ partials, int nchunk, int64_t n, float scale,
+                             float *__restrict__ grad)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        float s = 0.f;
+        for (int c = 0; c < nchunk; ++c) s += partials[(int64_t)c * n + e];
+        grad[e] += scale * s;
+    }
+}
+
+// per-channel column sums of a [V][C] tensor (bias gradients), fixed order
+__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t *__restrict__ G, int64_t V, int C,
+                                                     float scale, float *__restrict__ grad)
+{
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float s = 0.f;
+    for (int64_t v = threadIdx.x; v < V; v += 256) s += bf2f(G[v * C + c]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[c] += scale * red[0];
+}
+
+// ---------------------------------------------------------------- elementwise pieces
+
+__global__ void k_pool(int nx, int ny, int nz, int C, const uint16_t *__restrict__ x, uint16_t *__restrict__ y)
+{
+    const int mx = nx / 2, my = ny / 2;
+    const int64_t n = (int64_t)mx * my * (nz / 2) * C;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int c = (int)(e % C);
+        const int64_t u = e / C;
+        const int i = (int)(u % mx), j = (int)((u / mx) % my), k = (int)(u / ((int64_t)mx * my));
+        float s = 0.f;
+        for (int q = 0; q < 8; ++q) {
+            const int ii = 2 * i + (q & 1), jj = 2 * j + ((q >> 1) & 1), kk = 2 * k + (q >> 2);
+            s += bf2f(x[(ii + (int64_t)nx * (jj + (int64_t)ny * kk)) * C + c]);
+        }
+        y[e] = f2bf(0.125f * s);
+    }
+}
+
+// adjoint of the average pool (fine grid nx,ny,nz): dx += dy(parent) / 8
+__global__ void k_pool_bwd(int nx, int ny, int nz, int C, const float *__restrict__ dy, float *__restrict__ dx)
+{
+    const int mx = nx / 2, my = ny / 2;
+    const int64_t n = (int64_t)nx * ny * nz * C;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int c = (int)(e % C);
+        const int64_t v = e / C;
+        const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((int64_t)nx * ny));
+        dx[e] += 0.125f * dy[((i / 2) + (int64_t)mx * ((j / 2) + (int64_t)my * (k / 2))) * C + c];
+    }
+}
+
+// adjoint of nearest up-sampling (fine grid nx,ny,nz): parent = sum of 8 children
+__global__ void k_up_bwd(int nx, int ny, int nz, int C, const float *__restrict__ dyf, float *__restrict__ dx)
+{
+    const int mx = nx / 2, my = ny / 2;
+    const int64_t n = (int64_t)mx * my * (nz / 2) * C;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int c = (int)(e % C);
+        const int64_t u = e / C;
+        const int i = (int)(u % mx), j = (int)((u / mx) % my), k = (int)(u / ((int64_t)mx * my));
+        float s = 0.f;
+        for (int q = 0; q < 8; ++q) {
+            const int ii = 2 * i + (q & 1), jj = 2 * j + ((q >> 1) & 1), kk = 2 * k + (q >> 2);
+            s += dyf[(ii + (int64_t)nx * (jj + (int64_t)ny * kk)) * C + c];
+        }
+        dx[e] = s;
+    }
+}
+
+// G = bf16(g * [y > 0]); optional FP32 copy of the masked gradient (skip paths)
+__global__ void k_mask(int64_t n, const float *__restrict__ g, const uint16_t *__restrict__ y,
+                       uint16_t *__restrict__ G, float *__restrict__ gm)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const float v = bf2f(y[e]) > 0.f ? g[e] : 0.f;
+        G[e] = f2bf(v);
+        if (gm) gm[e] = v;
+    }
+}
+
+__global__ void k_add(int64_t n, const float *__restrict__ a, float *__restrict__ b)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) b[e] += a[e];
+}
+
+__global__ void k_f2bf(int64_t n, const float *__restrict__ a, uint16_t *__restrict__ b)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) b[e] = f2bf(a[e]);
+}
+
+// final 1x1x1 layer: y[v][co] = b[co] + sum_ci W[ci][co] d1[v][ci]
+__global__ void k_final(int64_t V, int C, const uint16_t *__restrict__ d1, const float *__restrict__ W,
+                        const float *__restrict__ b, float *__restrict__ y)
+{
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < V; v += (int64_t)gridDim.x * 256) {
+        float o[3] = {b[0], b[1], b[2]};
+        for (int ci = 0; ci < C; ++ci) {
+            const float a = bf2f(d1[v * C + ci]);
+            for (int co = 0; co < 3; ++co) o[co] += W[ci * 3 + co] * a;
+        }
+        for (int co = 0; co < 3; ++co) y[v * 3 + co] = o[co];
+    }
+}
+
+// backward of the final layer, data part: gd1[v][ci] = sum_co W[ci][co] gy[v][co]
+__global__ void k_final_bwd_data(int64_t V, int C, const float *__restrict__ W, const float *__restrict__ gy,
+                                 float *__restrict__ gd1)
+{
+    const int64_t n = V * C;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int ci = (int)(e % C);
+        const int64_t v = e / C;
+        gd1[e] = W[ci * 3] * gy[v * 3] + W[ci * 3 + 1] * gy[v * 3 + 1] + W[ci * 3 + 2] * gy[v * 3 + 2];
+    }
+}
+
+// weight part: partials[chunk][q] for q = ci*3 + co (sum_v d1[v][ci] gy[v][co]) and
+// q = 3C + co (sum_v gy[v][co]); grid.x = q, grid.y = voxel chunk
+__global__ __launch_bounds__(256) void k_final_dw(int64_t V, int C, int64_t chunk, const uint16_t *__restrict__ d1,
+                                                  const float *__restrict__ gy, float *__restrict__ partials)
+{
+    __shared__ float red[256];
+    const int q = blockIdx.x, nw = 3 * C + 3;
+    const int co = q % 3, ci = q / 3;
+    const int64_t v_begin = (int64_t)blockIdx.y * chunk;
+    const int64_t v_end = v_begin + chunk < V ? v_begin + chunk : V;
+    float s = 0.f;
+    for (int64_t v = v_begin + threadIdx.x; v < v_end; v += 256)
+        s += (ci < C ? bf2f(d1[v * C + ci]) : 1.f) * gy[v * 3 + co];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * nw + q] = red[0];
+}
+
+// network input from a residual.  rtl: tile-lane FP64 vector (or NULL), rnat:
+// natural block-row FP64 vector (or NULL); s2 = sum r^2 over all entries.
+// x0[v][0..2] = r/s (s = rms), x0[v][3] = standardised ln k (precomputed).
+__global__ void k_prep(Geo geo, const double *__restrict__ rtl, const double *__restrict__ rnat,
+                       const double *__restrict__ s2, const uint16_t *__restrict__ lnk_std,
+                       uint16_t *__restrict__ x0)
+{
+    const int64_t V = (int64_t)geo.nx * geo.ny * geo.nz;
+    const double s = sqrt(s2[0] / (double)(3 * V));
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < V; v += (int64_t)gridDim.x * 256) {
+        const int i = (int)(v % geo.nx), j = (int)((v / geo.nx) % geo.ny), k = (int)(v / ((int64_t)geo.nx * geo.ny));
+        double r[3];
+        if (rtl) {
+            const int64_t sl = slot_of(geo, i, j, k);
+            for (int p = 0; p < 3; ++p) r[p] = rtl[vidx(sl, p)];
+        } else {
+            const int64_t row = row_of(geo, i, j, k);
+            for (int p = 0; p < 3; ++p) r[p] = rnat[3 * row + p];
+        }
+        for (int p = 0; p < 3; ++p) x0[v * 4 + p] = f2bf((float)(r[p] * inv));
+        x0[v * 4 + 3] = lnk_std[v];
+    }
+}
+
+// z = s * y back to a tile-lane (ztl) or natural (znat) FP64 vector
+__global__ void k_post(Geo geo, const float *__restrict__ y, const double *__restrict__ s2, double *__restrict__ ztl,
+                       double *__restrict__ znat)
+{
+    const int64_t V = (int64_t)geo.nx * geo.ny * geo.nz;
+    const double s = sqrt(s2[0] / (double)(3 * V));
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < V; v += (int64_t)gridDim.x * 256) {
+        const int i = (int)(v % geo.nx), j = (int)((v / geo.nx) % geo.ny), k = (int)(v / ((int64_t)geo.nx * geo.ny));
+        if (ztl) {
+            const int64_t sl = slot_of(geo, i, j, k);
+            for (int p = 0; p < 3; ++p) ztl[vidx(sl, p)] = s * (double)y[v * 3 + p];
+        } else {
+            const int64_t row = row_of(geo, i, j, k);
+            for (int p = 0; p < 3; ++p) znat[3 * row + p] = s * (double)y[v * 3 + p];
+        }
+    }
+}
+
+// standardised ln k (mean/std given) in voxel order, BF16; lnk given per block row
+__global__ void k_lnk_std(Geo geo, const float *__restrict__ lnk, double mean, double inv_sd, uint16_t *__restrict__ out)
+{
+    const int64_t V = (int64_t)geo.nx * geo.ny * geo.nz;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < V; v += (int64_t)gridDim.x * 256) {
+        const int i = (int)(v % geo.nx), j = (int)((v / geo.nx) % geo.ny), k = (int)(v / ((int64_t)geo.nx * geo.ny));
+        out[v] = f2bf((float)(((double)lnk[row_of(geo, i, j, k)] - mean) * inv_sd));
+    }
+}
+
+// loss partials: sum (y - e/s)^2 and sum (e/s)^2 for one sample; e natural FP64
+__global__ __launch_bounds__(256) void k_loss(Geo geo, const float *__restrict__ y, const double *__restrict__ e,
+                                              const double *__restrict__ s2, double *__restrict__ partials)
+{
+    __shared__ double r0[256], r1[256];
+    const int64_t V = (int64_t)geo.nx * geo.ny * geo.nz;
+    const double s = sqrt(s2[0] / (double)(3 * V));
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    double a = 0.0, b = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < V; v += (int64_t)gridDim.x * 256) {
+        const int i = (int)(v % geo.nx), j = (int)((v / geo.nx) % geo.ny), k = (int)(v / ((int64_t)geo.nx * geo.ny));
+        const int64_t row = row_of(geo, i, j, k);
+        for (int p = 0; p < 3; ++p) {
+            const double t = e[3 * row + p] * inv;
+            const double d = (double)y[v * 3 + p] - t;
+            a += d * d;
+            b += t * t;
+        }
+    }
+    r0[threadIdx.x] = a;
+    r1[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) { r0[threadIdx.x] += r0[threadIdx.x + w]; r1[threadIdx.x] += r1[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { partials[2 * blockIdx.x] = r0[0]; partials[2 * blockIdx.x + 1] = r1[0]; }
+}
+
+// gy = scale * 2 (y - e/s) / ||e/s||^2   (tt = ||e/s||^2 in sc[0])
+__global__ void k_gy(Geo geo, const float *__restrict__ y, const double *__restrict__ e, const double *__restrict__ s2,
+                     const double *__restrict__ tt, float scale, float *__restrict__ gy)
+{
+    const int64_t V = (int64_t)geo.nx * geo.ny * geo.nz;
+    const double s = sqrt(s2[0] / (double)(3 * V));
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    const double f = 2.0 * (double)scale / tt[0];
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < V; v += (int64_t)gridDim.x * 256) {
+        const int i = (int)(v % geo.nx), j = (int)((v / geo.nx) % geo.ny), k = (int)(v / ((int64_t)geo.nx * geo.ny));
+        const int64_t row = row_of(geo, i, j, k);
+        for (int p = 0; p < 3; ++p) gy[v * 3 + p] = (float)(f * ((double)y[v * 3 + p] - e[3 * row + p] * inv));
+    }
+}
+
+__global__ void k_adam(int64_t n, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, float lr, float c1, float c2)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const float mm = 0.9f * m[e] + 0.1f * g[e];
+        const float vv = 0.999f * v[e] + 0.001f * g[e] * g[e];
+        m[e] = mm;
+        v[e] = vv;
+        p[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
+    }
+}
+
+// pack W[tap][ci][co] (FP32) into B fragments: forward (k = tap*cin + ci, n = co)
+// or transposed for the data gradient (k = tap'*cout + co with tap' = 26 - tap, n = ci)
+__global__ void k_pack(const float *__restrict__ W, int cin, int cout, int transposed, int KB, int NB,
+                       v4s *__restrict__ Wf)
+{
+    const int64_t n = (int64_t)KB * NB * 64;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int lane = (int)(e % 64);
+        const int nb = (int)((e / 64) % NB);
+        const int kb = (int)(e / (64 * NB));
+        const int col = nb * 16 + (lane & 15);
+        v4s frag;
+        for (int i = 0; i < 4; ++i) {
+            const int k = kb * 16 + 4 * (lane >> 4) + i;
+            float w = 0.f;
+            if (!transposed) {
+                if (k < 27 * cin && col < cout) w = W[(int64_t)k * cout + col];   // k = tap*cin + ci
+            } else {
+                if (k < 27 * cout && col < cin) {
+                    const int tp = k / cout, co = k - tp * cout;
+                    w = W[((int64_t)(26 - tp) * cin + col) * cout + co];
+                }
+            }
+            frag[i] = (short)f2bf(w);
+        }
+        Wf[e] = frag;
+    }
+}
+
+// seeded He-uniform initialisation (SplitMix64 counter hash), biases zero
+__global__ void k_init(int64_t n, float *__restrict__ p, const int64_t *__restrict__ seg, int nseg, uint64_t seed)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        // seg: [woff, boff, fan_in, scale*1e6] per layer
+        float val = 0.f;
+        for (int l = 0; l < nseg; ++l) {
+            const int64_t wo = seg[4 * l], bo = seg[4 * l + 1];
+            if (e >= wo && e < bo) {
+                uint64_t z = seed + (uint64_t)(e + 1) * 0x9E3779B97F4A7C15ull;
+                z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+                z ^= z >> 31;
+                const double u = (double)(z >> 11) * 0x1.0p-53;
+                const double a = sqrt(6.0 / (double)seg[4 * l + 2]) * (double)seg[4 * l + 3] * 1e-6;
+                val = (float)((2.0 * u - 1.0) * a);
+            }
+        }
+        p[e] = val;
+    }
+}
+
+inline int nblk(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- the network object
+
+struct rsv_net {
+    rsv_ctx *c = nullptr;
+    Arch a;
+    int64_t step = 0;
+    float *P = nullptr, *G = nullptr, *M = nullptr, *Vv = nullptr;   // FP32 master, gradient, Adam moments
+    v4s *wf[10] = {nullptr}, *wt[10] = {nullptr};                    // packed BF16 weights
+    bool packed = false;
+    // workspace for one grid
+    int wx = 0, wy = 0, wz = 0;
+    uint16_t *x0 = nullptr, *a1 = nullptr, *s1 = nullptr, *p1 = nullptr, *a2 = nullptr, *s2 = nullptr, *p2 = nullptr,
+             *a3 = nullptr, *b3 = nullptr, *d2a = nullptr, *d2 = nullptr, *d1a = nullptr, *d1 = nullptr;
+    uint16_t *Gb = nullptr, *lnk_std = nullptr;
+    float *y = nullptr, *gy = nullptr, *g1 = nullptr, *g2 = nullptr, *gs1 = nullptr, *gs2 = nullptr, *part = nullptr;
+    double *d_sc = nullptr;   // [0] sum r^2, [1] sum (e/s)^2
+    int64_t part_cap = 0;
+
+    ~rsv_net() { release(); }
+    void free_ws()
+    {
+        void *ps[] = {x0, a1, s1, p1, a2, s2, p2, a3, b3, d2a, d2, d1a, d1, Gb, lnk_std, y, gy, g1, g2, gs1, gs2, part};
+        for (void *p : ps) dev_free(p);
+        x0 = a1 = s1 = p1 = a2 = s2 = p2 = a3 = b3 = d2a = d2 = d1a = d1 = Gb = lnk_std = nullptr;
+        y = gy = g1 = g2 = gs1 = gs2 = part = nullptr;
+        part_cap = 0;
+        wx = wy = wz = 0;
+    }
+    void release()
+    {
+        free_ws();
+        dev_free(P); dev_free(G); dev_free(M); dev_free(Vv); dev_free(d_sc);
+        for (int l = 0; l < 10; ++l) { dev_free(wf[l]); dev_free(wt[l]); }
+    }
+};
+
+static rsv_status net_pack(rsv_net *n)
+{
+    rsv_ctx *c = n->c;
+    for (int l = 0; l < 10; ++l) {
+        const int NB = n->a.cout[l] / 16, NBt = (n->a.cin[l] + 15) / 16;
+        hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)n->a.kb(l) * NB * 64)), dim3(256), 0, c->stream, n->P + n->a.woff[l],
+                           n->a.cin[l], n->a.cout[l], 0, n->a.kb(l), NB, n->wf[l]);
+        if (l > 0)
+            hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)n->a.kbt(l) * NBt * 64)), dim3(256), 0, c->stream,
+                               n->P + n->a.woff[l], n->a.cin[l], n->a.cout[l], 1, n->a.kbt(l), NBt, n->wt[l]);
+    }
+    RSV_LAUNCH(c);
+    n->packed = true;
+    return RSV_OK;
+}
+
+static rsv_status net_ws(rsv_net *n, int nx, int ny, int nz)
+{
+    if (n->wx == nx && n->wy == ny && n->wz == nz) return RSV_OK;
+    rsv_ctx *c = n->c;
+    RSV_HIP(c, hipStreamSynchronize(c->stream));
+    n->free_ws();
+    const int64_t V1 = (int64_t)nx * ny * nz, V2 = V1 / 8, V3 = V2 / 8;
+    const int c0 = n->a.c[0], c1 = n->a.c[1], c2 = n->a.c[2];
+    // largest data-path gradient: full resolution with c0 or c1 channels (the
+    // up-sampled input of the last decoder level), half resolution with c2
+    const int64_t gmax = std::max(V1 * std::max(c0, c1), V2 * std::max(c1, c2));
+    struct { void **p; size_t b; } L[] = {
+        {(void **)&n->x0, (size_t)V1 * 4 * 2}, {(void **)&n->a1, (size_t)V1 * c0 * 2}, {(void **)&n->s1, (size_t)V1 * c0 * 2},
+        {(void **)&n->p1, (size_t)V2 * c0 * 2}, {(void **)&n->a2, (size_t)V2 * c1 * 2}, {(void **)&n->s2, (size_t)V2 * c1 * 2},
+        {(void **)&n->p2, (size_t)V3 * c1 * 2}, {(void **)&n->a3, (size_t)V3 * c2 * 2}, {(void **)&n->b3, (size_t)V3 * c2 * 2},
+        {(void **)&n->d2a, (size_t)V2 * c1 * 2}, {(void **)&n->d2, (size_t)V2 * c1 * 2}, {(void **)&n->d1a, (size_t)V1 * c0 * 2},
+        {(void **)&n->d1, (size_t)V1 * c0 * 2}, {(void **)&n->Gb, (size_t)gmax * 2}, {(void **)&n->lnk_std, (size_t)V1 * 2},
+        {(void **)&n->y, (size_t)V1 * 3 * 4}, {(void **)&n->gy, (size_t)V1 * 3 * 4},
+        {(void **)&n->g1, (size_t)gmax * 4}, {(void **)&n->g2, (size_t)gmax * 4},
+        {(void **)&n->gs1, (size_t)V1 * c0 * 4}, {(void **)&n->gs2, (size_t)V2 * c1 * 4},
+    };
+    for (auto &e : L) {
+        rsv_status s = dev_alloc(c, e.p, e.b);
+        if (s != RSV_OK) { n->free_ws(); return s; }
+    }
+    n->wx = nx; n->wy = ny; n->wz = nz;
+    return RSV_OK;
+}
+
+static rsv_status part_reserve(rsv_net *n, int64_t nfloat)
+{
+    if (nfloat <= n->part_cap) return RSV_OK;
+    RSV_HIP(n->c, hipStreamSynchronize(n->c->stream));
+    dev_free(n->part);
+    n->part = nullptr;
+    rsv_status s = dev_alloc(n->c, (void **)&n->part, (size_t)nfloat * sizeof(float));
+    if (s == RSV_OK) n->part_cap = nfloat;
+    return s;
+}
+
+// y = conv(X) + b [+ skip], relu, BF16 out
+static rsv_status conv_fwd(rsv_net *n, int l, int nx, int ny, int nz, int up, const uint16_t *X, const uint16_t *skip,
+                           int relu, uint16_t *out)
+{
+    rsv_ctx *c = n->c;
+    ConvGeo g{nx, ny, nz, up, n->a.cin[l], n->a.cout[l], (int64_t)nx * ny * nz};
+    const int grid = (int)(((g.V + 15) / 16 + 3) / 4);
+    const int NB = g.cout / 16;
+    const float *b = n->P + n->a.boff[l];
+    switch (NB) {
+    case 1: hipLaunchKernelGGL((k_conv<1, true>), dim3(grid), dim3(256), 0, c->stream, g, X, n->wf[l], n->a.kb(l), b, skip, relu, (void *)out); break;
+    case 2: hipLaunchKernelGGL((k_conv<2, true>), dim3(grid), dim3(256), 0, c->stream, g, X, n->wf[l], n->a.kb(l), b, skip, relu, (void *)out); break;
+    case 4: hipLaunchKernelGGL((k_conv<4, true>), dim3(grid), dim3(256), 0, c->stream, g, X, n->wf[l], n->a.kb(l), b, skip, relu, (void *)out); break;
+    default: return set_err(c, RSV_ERR_ARG, "channel count must be 16, 32 or 64");
+    }
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+// dX (FP32, resolution of G) = transposed conv of the BF16 gradient G
+static rsv_status conv_bwd_data(rsv_net *n, int l, int nx, int ny, int nz, const uint16_t *G, float *dX)
+{
+    rsv_ctx *c = n->c;
+    ConvGeo g{nx, ny, nz, 0, n->a.cout[l], n->a.cin[l], (int64_t)nx * ny * nz};
+    const int grid = (int)(((g.V + 15) / 16 + 3) / 4);
+    const int NB = (g.cout + 15) / 16;
+    switch (NB) {
+    case 1: hipLaunchKernelGGL((k_conv<1, false>), dim3(grid), dim3(256), 0, c->stream, g, G, n->wt[l], n->a.kbt(l), (const float *)nullptr, (const uint16_t *)nullptr, 0, (void *)dX); break;
+    case 2: hipLaunchKernelGGL((k_conv<2, false>), dim3(grid), dim3(256), 0, c->stream, g, G, n->wt[l], n->a.kbt(l), (const float *)nullptr, (const uint16_t *)nullptr, 0, (void *)dX); break;
+    case 4: hipLaunchKernelGGL((k_conv<4, false>), dim3(grid), dim3(256), 0, c->stream, g, G, n->wt[l], n->a.kbt(l), (const float *)nullptr, (const uint16_t *)nullptr, 0, (void *)dX); break;
+    default: return set_err(c, RSV_ERR_ARG, "channel count must be 16, 32 or 64");
+    }
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+// grad(W_l) += scale * X^T G, grad(b_l) += scale * colsum(G)
+static rsv_status conv_bwd_weight(rsv_net *n, int l, int nx, int ny, int nz, int up, const uint16_t *X,
+                                  const uint16_t *G, float scale, float *grad_w, float *grad_b)
+{
+    rsv_ctx *c = n->c;
+    ConvGeo g{nx, ny, nz, up, n->a.cin[l], n->a.cout[l], (int64_t)nx * ny * nz};
+    const int64_t nvb = (g.V + 15) / 16;
+    const int tiles = 27 * ((g.cin + 15) / 16) * (g.cout / 16);
+    int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(nvb / 64, std::max(1, 2048 / tiles)));
+    const int per = (int)((nvb + chunks - 1) / chunks);
+    chunks = (int)((nvb + per - 1) / per);
+    const int64_t nw = 27LL * g.cin * g.cout;
+    rsv_status s = part_reserve(n, nw * chunks);
+    if (s != RSV_OK) return s;
+    hipLaunchKernelGGL(k_conv_dw, dim3(tiles, chunks), dim3(256), 0, c->stream, g, X, G, per, n->part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(nw)), dim3(256), 0, c->stream, (const float *)n->part, chunks, nw, scale, grad_w);
+    hipLaunchKernelGGL(k_colsum_bf16, dim3(g.cout), dim3(256), 0, c->stream, G, g.V, g.cout, scale, grad_b);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+// forward pass; x0 must be filled; result y (FP32 [V][3])
+static rsv_status net_forward(rsv_net *n, int nx, int ny, int nz)
+{
+    if (!n->packed) {
+        rsv_status s = net_pack(n);
+        if (s != RSV_OK) return s;
+    }
+    const int mx = nx / 2, my = ny / 2, mz = nz / 2, lx = nx / 4, ly = ny / 4, lz = nz / 4;
+    const int c0 = n->a.c[0], c1 = n->a.c[1];
+    rsv_ctx *c = n->c;
+    ProfScope ps(c, RSV_K_NET);
+    rsv_status s;
+    if ((s = conv_fwd(n, 0, nx, ny, nz, 0, n->x0, nullptr, 1, n->a1)) != RSV_OK) return s;
+    if ((s = conv_fwd(n, 1, nx, ny, nz, 0, n->a1, nullptr, 1, n->s1)) != RSV_OK) return s;
+    hipLaunchKernelGGL(k_pool, dim3(nblk((int64_t)mx * my * mz * c0)), dim3(256), 0, c->stream, nx, ny, nz, c0, n->s1, n->p1);
+    if ((s = conv_fwd(n, 2, mx, my, mz, 0, n->p1, nullptr, 1, n->a2)) != RSV_OK) return s;
+    if ((s = conv_fwd(n, 3, mx, my, mz, 0, n->a2, nullptr, 1, n->s2)) != RSV_OK) return s;
+    hipLaunchKernelGGL(k_pool, dim3(nblk((int64_t)lx * ly * lz * c1)), dim3(256), 0, c->stream, mx, my, mz, c1, n->s2, n->p2);
+    if ((s = conv_fwd(n, 4, lx, ly, lz, 0, n->p2, nullptr, 1, n->a3)) != RSV_OK) return s;
+    if ((s = conv_fwd(n, 5, lx, ly, lz, 0, n->a3, nullptr, 1, n->b3)) != RSV_OK) return s;
+    if ((s = conv_fwd(n, 6, mx, my, mz, 1, n->b3, n->s2, 1, n->d2a)) != RSV_OK) return s;
+    if ((s = conv_fwd(n, 7, mx, my, mz, 0, n->d2a, nullptr, 1, n->d2)) != RSV_OK) return s;
+    if ((s = conv_fwd(n, 8, nx, ny, nz, 1, n->d2, n->s1, 1, n->d1a)) != RSV_OK) return s;
+    if ((s = conv_fwd(n, 9, nx, ny, nz, 0, n->d1a, nullptr, 1, n->d1)) != RSV_OK) return s;
+    const int64_t V1 = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL(k_final, dim3(nblk(V1)), dim3(256), 0, c->stream, V1, c0, n->d1, n->P + n->a.woff[10],
+                       n->P + n->a.boff[10], n->y);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+// backward pass for gy (in n->g2 as [V1][3] FP32 on entry is not assumed: gy pointer given)
+static rsv_status net_backward(rsv_net *n, int nx, int ny, int nz, const float *gy, float scale)
+{
+    rsv_ctx *c = n->c;
+    ProfScope ps(c, RSV_K_NET);
+    const int mx = nx / 2, my = ny / 2, mz = nz / 2, lx = nx / 4, ly = ny / 4, lz = nz / 4;
+    const int c0 = n->a.c[0], c1 = n->a.c[1], c2 = n->a.c[2];
+    const int64_t V1 = (int64_t)nx * ny * nz, V2 = V1 / 8, V3 = V2 / 8;
+    float *gw = n->G;
+#define GW(l) (gw + n->a.woff[l])
+#define GB(l) (gw + n->a.boff[l])
+    rsv_status s;
+    // final layer: gd1 -> g1, weight and bias gradients by voxel chunks
+    {
+        const int nwf = c0 * 3 + 3;
+        const int64_t chunk = 4096;
+        const int nch = (int)((V1 + chunk - 1) / chunk);
+        if ((s = part_reserve(n, (int64_t)nch * nwf)) != RSV_OK) return s;
+        hipLaunchKernelGGL(k_final_bwd_data, dim3(nblk(V1 * c0)), dim3(256), 0, c->stream, V1, c0,
+                           (const float *)(n->P + n->a.woff[10]), gy, n->g1);
+        hipLaunchKernelGGL(k_final_dw, dim3(nwf, nch), dim3(256), 0, c->stream, V1, c0, chunk, (const uint16_t *)n->d1,
+                           gy, n->part);
+        hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, c->stream, (const float *)n->part, nch, (int64_t)nwf, scale,
+                           GW(10));
+        RSV_LAUNCH(c);
+    }
+    // data-path gradients are unscaled; weight gradients are multiplied by `scale`
+    auto layer = [&](int l, int lnx, int lny, int lnz, int up, const uint16_t *X, const uint16_t *Y, float *gY,
+                     float *gX, float *gskip) -> rsv_status {
+        const int64_t V = (int64_t)lnx * lny * lnz;
+        const int64_t ne = V * n->a.cout[l];
+        hipLaunchKernelGGL(k_mask, dim3(nblk(ne)), dim3(256), 0, c->stream, ne, (const float *)gY, Y, n->Gb, gskip);
+        RSV_LAUNCH(c);
+        rsv_status st = conv_bwd_weight(n, l, lnx, lny, lnz, up, X, n->Gb, scale, GW(l), GB(l));
+        if (st != RSV_OK) return st;
+        if (gX) st = conv_bwd_data(n, l, lnx, lny, lnz, n->Gb, gX);
+        return st;
+    };
+    // dec1b: in d1a, out d1
+    if ((s = layer(9, nx, ny, nz, 0, n->d1a, n->d1, n->g1, n->g2, nullptr)) != RSV_OK) return s;
+    // dec1a: out d1a = relu(conv8(up(d2)) + s1); skip gradient -> gs1
+    if ((s = layer(8, nx, ny, nz, 1, n->d2, n->d1a, n->g2, n->g1, n->gs1)) != RSV_OK) return s;
+    hipLaunchKernelGGL(k_up_bwd, dim3(nblk(V2 * c1)), dim3(256), 0, c->stream, nx, ny, nz, c1, (const float *)n->g1, n->g2);
+    // dec2b
+    if ((s = layer(7, mx, my, mz, 0, n->d2a, n->d2, n->g2, n->g1, nullptr)) != RSV_OK) return s;
+    // dec2a: skip gradient -> gs2
+    if ((s = layer(6, mx, my, mz, 1, n->b3, n->d2a, n->g1, n->g2, n->gs2)) != RSV_OK) return s;
+    hipLaunchKernelGGL(k_up_bwd, dim3(nblk(V3 * c2)), dim3(256), 0, c->stream, mx, my, mz, c2, (const float *)n->g2, n->g1);
+    // enc3b, enc3a
+    if ((s = layer(5, lx, ly, lz, 0, n->a3, n->b3, n->g1, n->g2, nullptr)) != RSV_OK) return s;
+    if ((s = layer(4, lx, ly, lz, 0, n->p2, n->a3, n->g2, n->g1, nullptr)) != RSV_OK) return s;
+    // pool 2: gs2 += pool_bwd(gp2)
+    hipLaunchKernelGGL(k_pool_bwd, dim3(nblk(V2 * c1)), dim3(256), 0, c->stream, mx, my, mz, c1, (const float *)n->g1, n->gs2);
+    // enc2b, enc2a
+    if ((s = layer(3, mx, my, mz, 0, n->a2, n->s2, n->gs2, n->g1, nullptr)) != RSV_OK) return s;
+    if ((s = layer(2, mx, my, mz, 0, n->p1, n->a2, n->g1, n->g2, nullptr)) != RSV_OK) return s;
+    hipLaunchKernelGGL(k_pool_bwd, dim3(nblk(V1 * c0)), dim3(256), 0, c->stream, nx, ny, nz, c0, (const float *)n->g2, n->gs1);
+    // enc1b, enc1a
+    if ((s = layer(1, nx, ny, nz, 0, n->a1, n->s1, n->gs1, n->g1, nullptr)) != RSV_OK) return s;
+    if ((s = layer(0, nx, ny, nz, 0, n->x0, n->a1, n->g1, nullptr, nullptr)) != RSV_OK) return s;
+#undef GW
+#undef GB
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+static rsv_status dims_check(rsv_ctx *c, const rsv_grid *g)
+{
+    if (g->geo.nx % 4 || g->geo.ny % 4 || g->geo.nz % 4)
+        return set_err(c, RSV_ERR_ARG, "learned preconditioner needs grid dimensions that are multiples of 4");
+    return RSV_OK;
+}
+
+// standardised ln k channel (mean/std over the grid, FP64 on the host) into out[V]
+static rsv_status set_lnk(rsv_net *n, const rsv_grid *g, const float *lnk_dev, uint16_t *out)
+{
+    rsv_ctx *c = n->c;
+    const int64_t V = g->ncell;
+    std::vector<float> h(V);
+    RSV_HIP(c, hipMemcpyAsync(h.data(), lnk_dev, V * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    RSV_HIP(c, hipStreamSynchronize(c->stream));
+    double m = 0.0, m2 = 0.0;
+    for (float v : h) m += v;
+    m /= (double)V;
+    for (float v : h) m2 += ((double)v - m) * ((double)v - m);
+    const double sd = std::sqrt(m2 / (double)V);
+    hipLaunchKernelGGL(k_lnk_std, dim3(nblk(V)), dim3(256), 0, c->stream, g->geo, lnk_dev, m, sd > 0 ? 1.0 / sd : 0.0,
+                       out);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+// Fills x0 from r (tile-lane rtl or natural rnat) and leaves sum r^2 in n->d_sc[0]
+static rsv_status prep(rsv_net *n, const rsv_grid *g, const double *rtl, const double *rnat, const uint16_t *lnk_std)
+{
+    rsv_ctx *c = n->c;
+    const int64_t len = rtl ? g->nv : 3 * g->ncell;
+    rsv_status s = launch_dot(c, len, rtl ? rtl : rnat, rtl ? rtl : rnat, SC_MISC);
+    if (s != RSV_OK) return s;
+    RSV_HIP(c, hipMemcpyAsync(n->d_sc, c->d_scal + SC_MISC, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_prep, dim3(nblk(g->ncell)), dim3(256), 0, c->stream, g->geo, rtl, rnat, (const double *)n->d_sc,
+                       lnk_std, n->x0);
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+struct Learned : PcImpl {
+    rsv_matrix *M = nullptr;
+    rsv_net *net = nullptr;
+    uint16_t *lnk_std = nullptr;   // this preconditioner's standardised ln k channel
+    ~Learned() override { dev_free(lnk_std); }
+    int64_t bytes() const override { return M->g->ncell * 2; }
+    rsv_status apply(const double *r, double *z) override
+    {
+        rsv_grid *g = M->g;
+        rsv_status s = net_ws(net, g->geo.nx, g->geo.ny, g->geo.nz);
+        if (s == RSV_OK) s = prep(net, g, r, nullptr, lnk_std);
+        if (s == RSV_OK) s = net_forward(net, g->geo.nx, g->geo.ny, g->geo.nz);
+        if (s != RSV_OK) return s;
+        hipLaunchKernelGGL(k_post, dim3(nblk(g->ncell)), dim3(256), 0, net->c->stream, g->geo, (const float *)net->y,
+                           (const double *)net->d_sc, z, (double *)nullptr);
+        RSV_LAUNCH(net->c);
+        return RSV_OK;
+    }
+};
+
+rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out)
+{
+    rsv_ctx *c = A->g->ctx;
+    if (!p->net || !p->lnk) return set_err(c, RSV_ERR_ARG, "learned preconditioner needs net and lnk");
+    rsv_status s = dims_check(c, A->g);
+    if (s != RSV_OK) return s;
+    rsv_net *n = p->net;
+    if (n->c != c) return set_err(c, RSV_ERR_ARG, "network belongs to another context");
+    Learned *L = new (std::nothrow) Learned();
+    if (!L) return set_err(c, RSV_ERR_OOM, "learned");
+    L->M = A;
+    L->net = n;
+    s = dev_alloc(c, (void **)&L->lnk_std, (size_t)A->g->ncell * 2);
+    if (s == RSV_OK) s = set_lnk(n, A->g, p->lnk, L->lnk_std);
+    if (s == RSV_OK) s = net_ws(n, A->g->geo.nx, A->g->geo.ny, A->g->geo.nz);
+    if (s != RSV_OK) { delete L; return s; }
+    *out = L;
+    return RSV_OK;
 }
 
 extern "C" {
-rsv_status rsv_net_create(rsv_ctx *c, const rsv_net_arch *, uint64_t, rsv_net **) { return set_err(c, RSV_ERR_ARG, "not available"); }
-void rsv_net_destroy(rsv_net *) {}
-int64_t rsv_net_num_params(const rsv_net *) { return 0; }
-rsv_status rsv_net_get_params(rsv_net *, float *, int64_t) { return RSV_ERR_ARG; }
-rsv_status rsv_net_set_params(rsv_net *, const float *, int64_t) { return RSV_ERR_ARG; }
-rsv_status rsv_net_save(rsv_net *, const char *) { return RSV_ERR_ARG; }
-rsv_status rsv_net_load(rsv_net *, const char *) { return RSV_ERR_ARG; }
-rsv_status rsv_net_forward(rsv_net *, rsv_grid *, const double *, const float *, double *) { return RSV_ERR_ARG; }
-rsv_status rsv_net_train_step(rsv_net *, rsv_grid *, int32_t, const double *, const double *, const float *, float, float *) { return RSV_ERR_ARG; }
-rsv_status rsv_net_loss_grad(rsv_net *, rsv_grid *, int32_t, const double *, const double *, const float *, float *, float *) { return RSV_ERR_ARG; }
+
+rsv_status rsv_net_create(rsv_ctx *c, const rsv_net_arch *arch, uint64_t seed, rsv_net **out)
+{
+    if (!c || !arch || !out) return set_err(c, RSV_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (arch->levels != 3) return set_err(c, RSV_ERR_ARG, "only 3-level networks are supported");
+    for (int q : {arch->c0, arch->c1, arch->c2})
+        if (q != 16 && q != 32 && q != 64) return set_err(c, RSV_ERR_ARG, "channel counts must be 16, 32 or 64");
+    rsv_net *n = new (std::nothrow) rsv_net();
+    if (!n) return set_err(c, RSV_ERR_OOM, "net");
+    n->c = c;
+    n->a.init(arch->c0, arch->c1, arch->c2);
+    const size_t pb = (size_t)n->a.np * sizeof(float);
+    rsv_status s = dev_alloc(c, (void **)&n->P, pb);
+    if (s == RSV_OK) s = dev_alloc(c, (void **)&n->G, pb);
+    if (s == RSV_OK) s = dev_alloc(c, (void **)&n->M, pb);
+    if (s == RSV_OK) s = dev_alloc(c, (void **)&n->Vv, pb);
+    if (s == RSV_OK) s = dev_alloc(c, (void **)&n->d_sc, 8 * sizeof(double));
+    for (int l = 0; l < 10 && s == RSV_OK; ++l) {
+        s = dev_alloc(c, (void **)&n->wf[l], (size_t)n->a.kb(l) * (n->a.cout[l] / 16) * 64 * sizeof(v4s));
+        if (s == RSV_OK)
+            s = dev_alloc(c, (void **)&n->wt[l], (size_t)n->a.kbt(l) * ((n->a.cin[l] + 15) / 16) * 64 * sizeof(v4s));
+    }
+    if (s != RSV_OK) { delete n; return s; }
+    // He-uniform init; the final layer is scaled by 0.1 so an untrained net starts small
+    std::vector<int64_t> seg(4 * NL);
+    for (int l = 0; l < NL; ++l) {
+        seg[4 * l] = n->a.woff[l];
+        seg[4 * l + 1] = n->a.boff[l];
+        seg[4 * l + 2] = (int64_t)(l < 10 ? 27 : 1) * n->a.cin[l];
+        seg[4 * l + 3] = l < 10 ? 1000000 : 100000;
+    }
+    int64_t *dseg = nullptr;
+    s = dev_alloc(c, (void **)&dseg, seg.size() * sizeof(int64_t));
+    if (s == RSV_OK && hipMemcpy(dseg, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
+        s = set_err(c, RSV_ERR_HIP, "hipMemcpy");
+    if (s == RSV_OK) {
+        hipLaunchKernelGGL(k_init, dim3(nblk(n->a.np)), dim3(256), 0, c->stream, n->a.np, n->P, (const int64_t *)dseg, NL,
+                           seed * 0xD1B54A32D192ED03ull + 0x632BE59BD9B4E019ull);
+        if (hipMemsetAsync(n->M, 0, pb, c->stream) != hipSuccess || hipMemsetAsync(n->Vv, 0, pb, c->stream) != hipSuccess)
+            s = set_err(c, RSV_ERR_HIP, "hipMemsetAsync");
+        if (hipStreamSynchronize(c->stream) != hipSuccess) s = set_err(c, RSV_ERR_HIP, "sync");
+    }
+    dev_free(dseg);
+    if (s == RSV_OK) s = net_pack(n);
+    if (s != RSV_OK) { delete n; return s; }
+    *out = n;
+    return RSV_OK;
 }
+
+void rsv_net_destroy(rsv_net *n)
+{
+    if (!n) return;
+    (void)hipStreamSynchronize(n->c->stream);
+    delete n;
+}
+
+int64_t rsv_net_num_params(const rsv_net *n) { return n ? n->a.np : 0; }
+
+rsv_status rsv_net_get_params(rsv_net *n, float *h, int64_t cnt)
+{
+    if (!n || !h || cnt != n->a.np) return set_err(n ? n->c : nullptr, RSV_ERR_ARG, "bad parameter buffer");
+    RSV_HIP(n->c, hipMemcpyAsync(h, n->P, cnt * sizeof(float), hipMemcpyDeviceToHost, n->c->stream));
+    RSV_HIP(n->c, hipStreamSynchronize(n->c->stream));
+    return RSV_OK;
+}
+
+rsv_status rsv_net_set_params(rsv_net *n, const float *h, int64_t cnt)
+{
+    if (!n || !h || cnt != n->a.np) return set_err(n ? n->c : nullptr, RSV_ERR_ARG, "bad parameter buffer");
+    RSV_HIP(n->c, hipMemcpyAsync(n->P, h, cnt * sizeof(float), hipMemcpyHostToDevice, n->c->stream));
+    RSV_HIP(n->c, hipMemsetAsync(n->M, 0, cnt * sizeof(float), n->c->stream));
+    RSV_HIP(n->c, hipMemsetAsync(n->Vv, 0, cnt * sizeof(float), n->c->stream));
+    n->step = 0;
+    rsv_status s = net_pack(n);
+    if (s != RSV_OK) return s;
+    RSV_HIP(n->c, hipStreamSynchronize(n->c->stream));
+    return RSV_OK;
+}
+
+rsv_status rsv_net_save(rsv_net *n, const char *path)
+{
+    if (!n || !path) return set_err(n ? n->c : nullptr, RSV_ERR_ARG, "NULL argument");
+    std::vector<float> h(n->a.np);
+    rsv_status s = rsv_net_get_params(n, h.data(), n->a.np);
+    if (s != RSV_OK) return s;
+    FILE *f = fopen(path, "wb");
+    if (!f) return set_err(n->c, RSV_ERR_ARG, std::string("cannot open ") + path);
+    const char magic[8] = {'R', 'S', 'V', 'N', 'E', 'T', '1', 0};
+    const int32_t hdr[4] = {3, n->a.c[0], n->a.c[1], n->a.c[2]};
+    const int64_t meta[2] = {n->a.np, n->step};
+    bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(hdr, 4, 4, f) == 4 && fwrite(meta, 8, 2, f) == 2 &&
+              fwrite(h.data(), 4, h.size(), f) == h.size();
+    fclose(f);
+    return ok ? RSV_OK : set_err(n->c, RSV_ERR_ARG, "write failed");
+}
+
+rsv_status rsv_net_load(rsv_net *n, const char *path)
+{
+    if (!n || !path) return set_err(n ? n->c : nullptr, RSV_ERR_ARG, "NULL argument");
+    FILE *f = fopen(path, "rb");
+    if (!f) return set_err(n->c, RSV_ERR_ARG, std::string("cannot open ") + path);
+    char magic[8];
+    int32_t hdr[4];
+    int64_t meta[2];
+    bool ok = fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "RSVNET1", 7) == 0 && fread(hdr, 4, 4, f) == 4 &&
+              fread(meta, 8, 2, f) == 2 && hdr[1] == n->a.c[0] && hdr[2] == n->a.c[1] && hdr[3] == n->a.c[2] &&
+              meta[0] == n->a.np;
+    std::vector<float> h(ok ? n->a.np : 0);
+    if (ok) ok = fread(h.data(), 4, h.size(), f) == h.size();
+    fclose(f);
+    if (!ok) return set_err(n->c, RSV_ERR_ARG, "not a network file of this architecture");
+    rsv_status s = rsv_net_set_params(n, h.data(), n->a.np);
+    n->step = meta[1];
+    return s;
+}
+
+rsv_status rsv_net_forward(rsv_net *n, rsv_grid *g, const double *r, const float *lnk, double *z)
+{
+    if (!n || !g || !r || !lnk || !z) return set_err(n ? n->c : nullptr, RSV_ERR_ARG, "NULL argument");
+    rsv_ctx *c = n->c;
+    rsv_status s = dims_check(c, g);
+    if (s == RSV_OK) s = net_ws(n, g->geo.nx, g->geo.ny, g->geo.nz);
+    if (s == RSV_OK) s = set_lnk(n, g, lnk, n->lnk_std);
+    if (s == RSV_OK) s = prep(n, g, nullptr, r, n->lnk_std);
+    if (s == RSV_OK) s = net_forward(n, g->geo.nx, g->geo.ny, g->geo.nz);
+    if (s != RSV_OK) return s;
+    hipLaunchKernelGGL(k_post, dim3(nblk(g->ncell)), dim3(256), 0, c->stream, g->geo, (const float *)n->y,
+                       (const double *)n->d_sc, (double *)nullptr, z);
+    RSV_LAUNCH(c);
+    RSV_HIP(c, hipStreamSynchronize(c->stream));
+    return RSV_OK;
+}
+
+static rsv_status loss_grad_batch(rsv_net *n, rsv_grid *g, int32_t nb, const double *r, const double *e,
+                                  const float *lnk, float *loss_out)
+{
+    rsv_ctx *c = n->c;
+    if (nb < 1) return set_err(c, RSV_ERR_ARG, "batch must be >= 1");
+    rsv_status s = dims_check(c, g);
+    if (s == RSV_OK) s = net_ws(n, g->geo.nx, g->geo.ny, g->geo.nz);
+    if (s != RSV_OK) return s;
+    if (!n->packed && (s = net_pack(n)) != RSV_OK) return s;
+    const int64_t V = g->ncell, N = 3 * V;
+    RSV_HIP(c, hipMemsetAsync(n->G, 0, (size_t)n->a.np * sizeof(float), c->stream));
+    double total = 0.0;
+    const int nbk = nblk(V) < 1024 ? nblk(V) : 1024;
+    if ((s = partials_reserve(c, 2 * nbk)) != RSV_OK) return s;
+    for (int b = 0; b < nb; ++b) {
+        if ((s = set_lnk(n, g, lnk + (int64_t)b * V, n->lnk_std)) != RSV_OK) return s;
+        if ((s = prep(n, g, nullptr, r + (int64_t)b * N, n->lnk_std)) != RSV_OK) return s;
+        if ((s = net_forward(n, g->geo.nx, g->geo.ny, g->geo.nz)) != RSV_OK) return s;
+        hipLaunchKernelGGL(k_loss, dim3(nbk), dim3(256), 0, c->stream, g->geo, (const float *)n->y, e + (int64_t)b * N,
+                           (const double *)n->d_sc, c->d_partials);
+        RSV_LAUNCH(c);
+        if ((s = launch_reduce(c, nbk, 2, SC_MISC)) != RSV_OK) return s;
+        if ((s = scal_to_host(c, SC_MISC, 2)) != RSV_OK) return s;
+        total += c->h_scal[SC_MISC] / c->h_scal[SC_MISC + 1];
+        RSV_HIP(c, hipMemcpyAsync(n->d_sc + 1, c->d_scal + SC_MISC + 1, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        // gy = (2 / nb) (y - e/s) / ||e/s||^2
+        hipLaunchKernelGGL(k_gy, dim3(nblk(V)), dim3(256), 0, c->stream, g->geo, (const float *)n->y, e + (int64_t)b * N,
+                           (const double *)n->d_sc, (const double *)(n->d_sc + 1), 1.0f / (float)nb, n->gy);
+        RSV_LAUNCH(c);
+        if ((s = net_backward(n, g->geo.nx, g->geo.ny, g->geo.nz, n->gy, 1.0f)) != RSV_OK) return s;
+    }
+    if (loss_out) *loss_out = (float)(total / nb);
+    return RSV_OK;
+}
+
+rsv_status rsv_net_loss_grad(rsv_net *n, rsv_grid *g, int32_t nb, const double *r, const double *e, const float *lnk,
+                             float *loss_out, float *grad_out)
+{
+    if (!n || !g || !r || !e || !lnk) return set_err(n ? n->c : nullptr, RSV_ERR_ARG, "NULL argument");
+    rsv_status s = loss_grad_batch(n, g, nb, r, e, lnk, loss_out);
+    if (s != RSV_OK) return s;
+    if (grad_out) {
+        RSV_HIP(n->c, hipMemcpyAsync(grad_out, n->G, (size_t)n->a.np * sizeof(float), hipMemcpyDeviceToHost, n->c->stream));
+    }
+    RSV_HIP(n->c, hipStreamSynchronize(n->c->stream));
+    return RSV_OK;
+}
+
+rsv_status rsv_net_train_step(rsv_net *n, rsv_grid *g, int32_t nb, const double *r, const double *e, const float *lnk,
+                              float lr, float *loss_out)
+{
+    if (!n || !g || !r || !e || !lnk) return set_err(n ? n->c : nullptr, RSV_ERR_ARG, "NULL argument");
+    rsv_status s = loss_grad_batch(n, g, nb, r, e, lnk, loss_out);
+    if (s != RSV_OK) return s;
+    n->step += 1;
+    const float c1 = 1.0f - powf(0.9f, (float)n->step), c2 = 1.0f - powf(0.999f, (float)n->step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n->a.np)), dim3(256), 0, n->c->stream, n->a.np, n->P, (const float *)n->G, n->M,
+                       n->Vv, lr, c1, c2);
+    RSV_LAUNCH(n->c);
+    s = net_pack(n);
+    if (s != RSV_OK) return s;
+    RSV_HIP(n->c, hipStreamSynchronize(n->c->stream));
+    return RSV_OK;
+}
+
+// ---------------------------------------------------------------- single-layer entry points
+
+rsv_status rsv_conv3d(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32_t cin, int32_t cout, const uint16_t *x,
+                      const float *w, const float *b, float *y)
+{
+    if (!c || !x || !w || !y) return set_err(c, RSV_ERR_ARG, "NULL argument");
+    if (cin % 4 || cin < 4 || cin > 64 || (cout != 16 && cout != 32 && cout != 64) || nx < 1 || ny < 1 || nz < 1)
+        return set_err(c, RSV_ERR_ARG, "conv3d needs cin a multiple of 4 up to 64, cout 16/32/64, positive dims");
+    const int KB = (27 * cin + 15) / 16, NB = cout / 16;
+    v4s *wf = nullptr;
+    rsv_status s = dev_alloc(c, (void **)&wf, (size_t)KB * NB * 64 * sizeof(v4s));
+    if (s != RSV_OK) return s;
+    hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)KB * NB * 64)), dim3(256), 0, c->stream, w, cin, cout, 0, KB, NB, wf);
+    ConvGeo g{nx, ny, nz, 0, cin, cout, (int64_t)nx * ny * nz};
+    const int grid = (int)(((g.V + 15) / 16 + 3) / 4);
+    if (NB == 1) hipLaunchKernelGGL((k_conv<1, false>), dim3(grid), dim3(256), 0, c->stream, g, x, wf, KB, b, (const uint16_t *)nullptr, 0, (void *)y);
+    if (NB == 2) hipLaunchKernelGGL((k_conv<2, false>), dim3(grid), dim3(256), 0, c->stream, g, x, wf, KB, b, (const uint16_t *)nullptr, 0, (void *)y);
+    if (NB == 4) hipLaunchKernelGGL((k_conv<4, false>), dim3(grid), dim3(256), 0, c->stream, g, x, wf, KB, b, (const uint16_t *)nullptr, 0, (void *)y);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dev_free(wf);
+    if (e != hipSuccess) return set_err(c, RSV_ERR_HIP, std::string("conv3d: ") + hipGetErrorString(e));
+    return RSV_OK;
+}
+
+rsv_status rsv_conv3d_bwd(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32_t cin, int32_t cout, const uint16_t *x,
+                          const float *w, const uint16_t *dy, float *dx, float *dw, float *db)
+{
+    if (!c || !x || !w || !dy) return set_err(c, RSV_ERR_ARG, "NULL argument");
+    if (cin % 4 || cin < 4 || cin > 64 || (cout != 16 && cout != 32 && cout != 64) || nx < 1 || ny < 1 || nz < 1)
+        return set_err(c, RSV_ERR_ARG, "conv3d needs cin a multiple of 4 up to 64, cout 16/32/64, positive dims");
+    if (dx && cin % 16) return set_err(c, RSV_ERR_ARG, "the data gradient needs cin in {16, 32, 64}");
+    // a one-layer network-like view to reuse the layer kernels
+    rsv_net tmp;
+    tmp.c = c;
+    tmp.a.init(16, 16, 16);
+    tmp.a.cin[1] = cin;
+    tmp.a.cout[1] = cout;
+    const int KBt = (27 * cout + 15) / 16, NBt = (cin + 15) / 16;
+    rsv_status s = RSV_OK;
+    ConvGeo g{nx, ny, nz, 0, cin, cout, (int64_t)nx * ny * nz};
+    if (dx) {
+        s = dev_alloc(c, (void **)&tmp.wt[1], (size_t)KBt * NBt * 64 * sizeof(v4s));
+        if (s == RSV_OK) {
+            hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)KBt * NBt * 64)), dim3(256), 0, c->stream, w, cin, cout, 1, KBt,
+                               NBt, tmp.wt[1]);
+            s = conv_bwd_data(&tmp, 1, nx, ny, nz, dy, dx);
+        }
+    }
+    if (s == RSV_OK && (dw || db)) {
+        float *gw = nullptr;
+        const int64_t nwb = 27LL * cin * cout + cout;
+        s = dev_alloc(c, (void **)&gw, (size_t)nwb * sizeof(float));
+        if (s == RSV_OK && hipMemsetAsync(gw, 0, (size_t)nwb * sizeof(float), c->stream) != hipSuccess)
+            s = set_err(c, RSV_ERR_HIP, "hipMemsetAsync");
+        if (s == RSV_OK) s = conv_bwd_weight(&tmp, 1, nx, ny, nz, 0, x, dy, 1.0f, gw, gw + 27LL * cin * cout);
+        if (s == RSV_OK && dw)
+            if (hipMemcpyAsync(dw, gw, 27LL * cin * cout * sizeof(float), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+                s = set_err(c, RSV_ERR_HIP, "hipMemcpyAsync");
+        if (s == RSV_OK && db)
+            if (hipMemcpyAsync(db, gw + 27LL * cin * cout, cout * sizeof(float), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+                s = set_err(c, RSV_ERR_HIP, "hipMemcpyAsync");
+        if (hipStreamSynchronize(c->stream) != hipSuccess && s == RSV_OK) s = set_err(c, RSV_ERR_HIP, "sync");
+        dev_free(gw);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess && s == RSV_OK) s = set_err(c, RSV_ERR_HIP, "sync");
+    (void)g;
+    return s;
+}
+
+}  // extern "C"

@@ -82,6 +82,8 @@ _SIGS = {
     "rsv_net_forward": ([vp, vp, vp, vp, vp], i32),
     "rsv_net_train_step": ([vp, vp, i32, vp, vp, vp, ctypes.c_float, _P(ctypes.c_float)], i32),
     "rsv_net_loss_grad": ([vp, vp, i32, vp, vp, vp, _P(ctypes.c_float), vp], i32),
+    "rsv_conv3d": ([vp, i32, i32, i32, i32, i32, vp, vp, vp, vp], i32),
+    "rsv_conv3d_bwd": ([vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp], i32),
     "rsv_profile_enable": ([vp, i32], i32),
     "rsv_profile_read": ([vp, vp, vp], i32),
     "rsv_device_info": ([vp, vp, i32], i32),
@@ -332,3 +334,21 @@ class Net:
         if self.h:
             lib().rsv_net_destroy(self.h)
             self.h = None
+
+
+def conv3d(ctx: Context, dims, cin, cout, x, w, b, y):
+    """One 3x3x3 layer: y[V][cout] (FP32) from x[V][cin] (BF16 bits, int16
+    tensor), w[27][cin][cout] and b[cout] (FP32); all device tensors."""
+    nx, ny, nz = dims
+    _check(ctx, lib().rsv_conv3d(ctx.h, nx, ny, nz, cin, cout, _ptr(x), _ptr(w),
+                                 _ptr(b) if b is not None else None, _ptr(y)))
+    return y
+
+
+def conv3d_bwd(ctx: Context, dims, cin, cout, x, w, dy, dx=None, dw=None, db=None):
+    """Gradients of conv3d for dy[V][cout] (BF16 bits): dx, dw, db (FP32,
+    device; any may be None)."""
+    nx, ny, nz = dims
+    opt = lambda t: _ptr(t) if t is not None else None  # noqa: E731
+    _check(ctx, lib().rsv_conv3d_bwd(ctx.h, nx, ny, nz, cin, cout, _ptr(x), _ptr(w), _ptr(dy),
+                                     opt(dx), opt(dw), opt(db)))
