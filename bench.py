@@ -10,8 +10,9 @@ residual.  One step = assemble the block matrix, then for each solver form:
 preconditioner setup + solve.  Forms: BiCGSTAB + BILU0 (the headline
 time-to-solve), GMRES(30) + RAS(4x4x4 subdomains, overlap 1, ILU(0)),
 GMRES(30) + BILU0 with FP64 factors, GMRES(30) + BILU0 with FP32 factors,
-and FGMRES(30) + the learned U-Net preconditioner when a trained network
-is given (--net).
+and FGMRES(30) + the learned U-Net preconditioner (BILU0 fallback), whose
+network is trained first on C4-shaped systems (64x64x32, disjoint seeds;
+training time reported apart) or loaded (--net).
 
 Prints one JSON line.
 """
@@ -61,6 +62,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="bicgstab_bilu0,gmres_ras64,gmres_bilu0,gmres_bilu0_fp32")
     ap.add_argument("--net", default=None, help="trained U-Net weights for the learned form")
+    ap.add_argument("--learned-steps", type=int, default=1500,
+                    help="without --net: Adam steps of training on C4 systems before the timed steps (0: no learned form)")
+    ap.add_argument("--learned-seeds", default="1000-1015")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with one device-to-device copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path",
@@ -99,9 +105,34 @@ def main():
     forms = [f for f in args.forms.split(",") if f]
     net = None
     lnk32 = None
-    if args.net:
+    training = None
+    if args.net or args.learned_steps > 0:
         net = rsv.Net(ctx)
-        net.load(args.net)
+        if args.net:
+            net.load(args.net)
+        else:
+            # train on C4-shaped systems (disjoint seeds), reported apart from the solves
+            from paper_1602_05901_amd import train as T
+            t0 = time.perf_counter()
+            a, z = (int(v) for v in args.learned_seeds.split("-"))
+            data = []
+            for sd in range(a, z + 1):
+                sy = T.System(ctx, I.preset("C4", seed=sd))
+                R, E, _ = T.harvest(ctx, sy)
+                data.append((sy.g, R, E, sy.lnk, sy))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            losses = T.train(ctx, net, [d[:4] for d in data], args.learned_steps, batch=8, lr=1e-3, seed=0)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            training = {"workload": "C4 64x64x32", "seeds": args.learned_seeds,
+                        "pairs": int(sum(d[1].shape[0] for d in data)), "harvest_s": round(t1 - t0, 3),
+                        "steps": args.learned_steps, "batch": 8, "train_s": round(t2 - t1, 3),
+                        "loss_first": losses[0], "loss_last": float(np.mean(losses[-50:]))}
+            log(f"trained the network: {training}")
+            for d in data:
+                d[4].close()
+            del data
         lnk32 = torch.from_numpy(lnk.astype(np.float32)).to(dev)
         forms_all["fgmres_learned"] = (rsv.FGMRES, dict(type=rsv.PC_LEARNED, net=net, lnk=lnk32))
         forms.append("fgmres_learned")
@@ -173,8 +204,8 @@ def main():
     if os.path.exists(tpath):
         try:
             tj = json.load(open(tpath))
-            if tj.get("kernel") == dom and tj.get("workload") == args.workload:
-                traffic = tj.get("bytes_per_launch")
+            if tj.get("workload") == args.workload and dom in tj.get("kernels", {}):
+                traffic = tj["kernels"][dom]["bytes_per_launch"]
         except Exception:  # noqa: BLE001
             traffic = None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -215,6 +246,9 @@ def main():
                                f"headline {head}, tol 1e-8", "unknowns": 3 * cfg.ncell,
                    "forms": forms, "seed": args.seed},
         "solves": summary,
+        "vs_plain_gmres_bilu0": ({f: round(summary[f]["solve_s"] / summary["gmres_bilu0"]["solve_s"], 3) for f in forms}
+                                 if "gmres_bilu0" in summary else None),
+        "learned_training": training,
         "ilu_apply_GBps": round(ab["ilu_apply"] / (ilu_ms * 1e-3) / 1e9, 1) if kcnt["ilu_fwd"] else None,
         "spmv_GBps": kernels.get("spmv", {}).get("GBps"),
         "kernels": kernels,
@@ -224,6 +258,13 @@ def main():
         "device": ctx.device_info(),
     }
     print(json.dumps(line), flush=True)
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 1073741824 bytes read, 1073741824 bytes written")
     A.close(); g.close(); ctx.close()
 
 
