@@ -42,33 +42,38 @@ __device__ inline int64_t fidx(int64_t slot, int e, int ne) { return ((slot >> 6
 // that inlines these helpers, whatever the contraction choices around them
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <typename T>
-__device__ __forceinline__ T dot3(const T *m, const T *v) { return fma_t(m[2], v[2], fma_t(m[1], v[1], m[0] * v[0])); }
-
-// forward: out = r - (L_-z vz + L_-y vy + L_-x vx); the three block products
-// are independent chains summed at the end (short dependency path per step)
+// forward: out = r - (L_-z vz + L_-y vy + L_-x vx), one FMA chain per
+// component (terms in the order -z, -y, -x), the three chains advanced in
+// lockstep; negated products are free operand modifiers
 template <typename T>
 __device__ __forceinline__ void fwd_cell(const T *l, const T *vz, const T *vy, const T *vx, const T *rr, T *out)
 {
+    T acc[3] = {rr[0], rr[1], rr[2]};
+    const T *v[3] = {vz, vy, vx};
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        const T az = dot3(l + 3 * p, vz), ay = dot3(l + 9 + 3 * p, vy), ax = dot3(l + 18 + 3 * p, vx);
-        out[p] = rr[p] - ((az + ay) + ax);
-    }
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) acc[p] = fma_t(-l[9 * s + 3 * p + q], v[s][q], acc[p]);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) out[p] = acc[p];
 }
-// backward: out = Dinv (y - (U_+x vx + U_+y vy + U_+z vz))
+// backward: out = Dinv (y - (U_+x vx + U_+y vy + U_+z vz)), same chain order (+x, +y, +z)
 template <typename T>
 __device__ __forceinline__ void bwd_cell(const T *u, const T *dd, const T *vx, const T *vy, const T *vz, const T *yy,
                                          T *out)
 {
-    T tv[3];
+    T tv[3] = {yy[0], yy[1], yy[2]};
+    const T *v[3] = {vx, vy, vz};
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        const T ax = dot3(u + 3 * p, vx), ay = dot3(u + 9 + 3 * p, vy), az = dot3(u + 18 + 3 * p, vz);
-        tv[p] = yy[p] - ((ax + ay) + az);
-    }
+    for (int s = 0; s < 3; ++s)
 #pragma unroll
-    for (int p = 0; p < 3; ++p) out[p] = dot3(dd + 3 * p, tv);
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) tv[p] = fma_t(-u[9 * s + 3 * p + q], v[s][q], tv[p]);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) out[p] = fma_t(dd[3 * p + 2], tv[2], fma_t(dd[3 * p + 1], tv[1], dd[3 * p] * tv[0]));
 }
 
 // ---------------------------------------------------------------- factorisation (one launch per hyperplane)
@@ -308,6 +313,8 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
     int32_t *tags = (int32_t *)(smem + (size_t)D * slot_elems * sizeof(T));
     int32_t *consumed = tags + D;
     int32_t *tile_sh = consumed + 1;
+    // exchange rows of the compute wave ([64][3] T) after the ring and its 64 tag words
+    const uint32_t xch_off = (uint32_t)((size_t)D * slot_elems * sizeof(T) + 64 * sizeof(int32_t));
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
     int li, lj;
     lane_ij(L, li, lj);
@@ -412,34 +419,44 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 const bool okx = !hasx || !need || (uint32_t)(wx >> 32) == a.epoch;
                 const bool oky = !hasy || !need || (uint32_t)(wy >> 32) == a.epoch;
                 if (!(okx && oky)) {
-                    // Slow path.  Rows become valid in step order, so first wait (in
-                    // LDS) until the previous step has been delivered; then only the
-                    // loader of the oldest pending step polls device memory, with
-                    // exponential backoff, instead of every waiting wave at once.
+                    // Slow path.  Forward sweep (seven loaders): every loader polls
+                    // its own step's rows at a short fixed interval, so consecutive
+                    // steps are not serialised on each other's poll round trips.
+                    // Backward FP64 sweep (three loaders): rows become valid in step
+                    // order, so first wait (in LDS) until the previous step has been
+                    // delivered; then only the loader of the oldest pending step
+                    // polls device memory, with exponential backoff.  (Measured:
+                    // the first is faster forward, the second backward.)
                     const uint64_t t0 = wall_clock64();
                     uint32_t n = 0;
-                    if (t > 0)
+                    constexpr bool serial = NLOAD < 7;
+                    if (serial && t > 0)
                         while (__hip_atomic_load(&tags[(G - 1) % D], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G) {
                             if (spin_guard(a.flags, t0, n)) break;
                             __builtin_amdgcn_s_sleep(2);
                         }
                     int backoff = 1;
                     for (;;) {
-                        if (hasx) wx = face_ld(xin + (int64_t)t * RW + L);
-                        if (hasy) wy = face_ld(yin + (int64_t)t * RW + L);
+                        if (hasx) wx = face_ld(xin + (int64_t)t * RW + lq);
+                        if (hasy) wy = face_ld(yin + (int64_t)t * RW + lq);
                         const bool ok = (!hasx || !need || (uint32_t)(wx >> 32) == a.epoch) &&
                                         (!hasy || !need || (uint32_t)(wy >> 32) == a.epoch);
                         if (__ballot(!ok) == 0ull) break;
                         if (spin_guard(a.flags, t0, n)) break;
-                        for (int q = 0; q < backoff; ++q) __builtin_amdgcn_s_sleep(8);
-                        backoff = backoff < 16 ? 2 * backoff : 16;
+                        if (!serial) {
+                            __builtin_amdgcn_s_sleep(2);
+                        } else {
+                            for (int q = 0; q < backoff; ++q) __builtin_amdgcn_s_sleep(8);
+                            backoff = backoff < 16 ? 2 * backoff : 16;
+                        }
                     }
                 }
                 // the low 32 bits of word q are 32-bit half q of the row's values
+                // (zero when the tile has no such neighbour: the value of an absent cell)
                 uint32_t *fs = (uint32_t *)(sl + NE * 64);
                 if (L < RW) {
-                    fs[L] = (uint32_t)wx;
-                    fs[RW + L] = (uint32_t)wy;
+                    fs[L] = hasx ? (uint32_t)wx : 0u;
+                    fs[RW + L] = hasy ? (uint32_t)wy : 0u;
                 }
                 // the slot's LDS writes complete before its tag is published
                 __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
@@ -469,17 +486,25 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             const bool py = DIR == 0 ? (lj == 7 && ty < g.nty - 1) : (lj == 0 && ty > 0);
             uint64_t *fxo = a.faceX + (int64_t)T_ * frow;
             uint64_t *fyo = a.faceY + (int64_t)T_ * frow;
-            T last[3] = {0, 0, 0};
             uint32_t waited = 0;
             if (a.trace && L == 0) a.trace[4 * T_ + 0] = wall_clock64();
-            // operands of a step: slot data for this lane plus the face values of
-            // the boundary lanes, read from LDS one step ahead into one of two
-            // register sets (the loop is unrolled by two, so nothing is copied)
-            auto fetch = [&](T *nf, T *nfx, T *nfy, int t) {
-                const int G = gstep + t;
-                const int slot = G % D;
-                const T *sl = ring + (size_t)slot * slot_elems;
-                if (__hip_atomic_load(&tags[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != G + 1) {
+            // Neighbour values come through LDS: every step the wave writes its
+            // three results to its exchange row; at the next step an interior
+            // lane reads the row of its -x (+x) and -y (+y) neighbour lane and a
+            // boundary lane reads the face entry the loader put in the step's
+            // slot.  One wave only, so its LDS accesses stay in program order.
+            const uint32_t slot_bytes = (uint32_t)slot_elems * sizeof(T);
+            const uint32_t xo_int = xch_off + (uint32_t)lx * 3 * sizeof(T);
+            const uint32_t yo_int = xch_off + (uint32_t)ly * 3 * sizeof(T);
+            const uint32_t xo_face = (uint32_t)(NE * 64 + lj * 3) * sizeof(T);
+            const uint32_t yo_face = (uint32_t)(NE * 64 + 24 + li * 3) * sizeof(T);
+            T *xrow = (T *)(smem + xch_off) + L * 3;
+            xrow[0] = xrow[1] = xrow[2] = (T)0;
+            T last[3] = {0, 0, 0};   // this lane's previous result: the -z (+z) neighbour value
+            // spin until the loaders have delivered step G into `slot` (tag G + 1);
+            // `seen` is a tag value already read
+            auto wait_slot = [&](int slot, int G, int seen) {
+                if (seen != G + 1) {
                     ++waited;
                     const uint64_t t0 = wall_clock64();
                     uint32_t n = 0;
@@ -490,47 +515,52 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 }
                 // LDS only: the slot's data were written before the tag (see the loader)
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            };
+            auto load_ops = [&](T *nf, int slot) {
+                const T *sl = ring + (size_t)slot * slot_elems;
 #pragma unroll
                 for (int e = 0; e < NE; ++e) nf[e] = sl[e * 64 + L];
-                const T *fsv = sl + NE * 64;   // x face: entries [8][3], then y face
+            };
+            int slot = gstep % D;                                   // slot of the current step
+            int row = DIR == 0 ? 0 : wrap_nz(nz + 13, nz);          // tile row of the current step
+            // Step t with operands f (already in registers).  Order: neighbour
+            // reads and the next slot's tag; the cell update; exchange-row
+            // writes; release of this step's slot (all its reads are consumed);
+            // the next step's operands into fn (they land while the global
+            // stores below are issued).
+            auto step = [&](const T *f, T *fn, int t) {
+                const int G = gstep + t;
+                const int nslot = slot + 1 == D ? 0 : slot + 1;
+                const T *bx = (const T *)(smem + (cx ? (uint32_t)slot * slot_bytes + xo_face : xo_int));
+                const T *by = (const T *)(smem + (cy ? (uint32_t)slot * slot_bytes + yo_face : yo_int));
+                T vx[3], vy[3];
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
-                    nfx[p] = fsv[lj * 3 + p];
-                    nfy[p] = fsv[24 + li * 3 + p];
+                    vx[p] = bx[p];
+                    vy[p] = by[p];
                 }
-            };
-            // the slot of step t is in registers: hand it back to the loaders
-            auto release = [&](int t) {
-                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); global stores stay in flight
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                if (L == 0) __hip_atomic_store(consumed, gstep + t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            };
-            const T zx = hasx ? (T)1 : (T)0, zy = hasy ? (T)1 : (T)0;
-            auto step = [&](const T *f, const T *fx, const T *fy, int t) {
+                const bool more = t + 1 < nsteps;
+                const int seen = more ? __hip_atomic_load(&tags[nslot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
                 const int kk = DIR == 0 ? t - d : t - e_;
                 const bool act = kk >= 0 && kk < nz;
-                T vx[3], vy[3], vz[3];
+                T out[3];
+                if (DIR == 0) fwd_cell(f, last, vy, vx, f + 27, out);
+                else bwd_cell(f, f + 27, vx, vy, last, f + 36, out);
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
-                    vx[p] = shfl_d(last[p], lx);
-                    vy[p] = shfl_d(last[p], ly);
-                    vz[p] = last[p];
+                    out[p] = act ? out[p] : (T)0;
+                    xrow[p] = out[p];
+                    last[p] = out[p];
                 }
-                if (cx)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) vx[p] = zx * fx[p];
-                if (cy)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) vy[p] = zy * fy[p];
+                // every read of this step's slot has been consumed above: hand it back
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                if (L == 0) __hip_atomic_store(consumed, G + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                if (more) {
+                    wait_slot(nslot, G + 1, seen);
+                    load_ops(fn, nslot);
+                }
                 if (act) {
-                    if (kk == 0) vz[0] = vz[1] = vz[2] = 0;
-                    T out[3];
-                    if (DIR == 0) {
-                        fwd_cell(f, vz, vy, vx, f + 27, out);
-                    } else {
-                        bwd_cell(f, f + 27, vx, vy, vz, f + 36, out);
-                    }
-                    const int row = DIR == 0 ? wrap_nz(t, nz) : wrap_nz(nz + 13 - t, nz);
                     if (DIR == 0) {
                         T *yp = yout + (rowbase + row) * 192 + L;
 #pragma unroll
@@ -550,23 +580,19 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
 #pragma unroll
                         for (int p = 0; p < 3; ++p) face_put(fp + p * W, out[p], a.epoch);
                     }
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) last[p] = out[p];
-                } else {
-                    last[0] = last[1] = last[2] = 0;
                 }
+                slot = nslot;
+                if (DIR == 0) row = row + 1 == nz ? 0 : row + 1;
+                else row = row == 0 ? nz - 1 : row - 1;
             };
-            T fa[NE], fxa[3], fya[3], fb[NE], fxb[3], fyb[3];
-            fetch(fa, fxa, fya, 0);
+            T fa[NE], fb[NE];
+            wait_slot(slot, gstep, __hip_atomic_load(&tags[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            load_ops(fa, slot);
             for (int t = 0; t < nsteps; t += 2) {
                 if (a.trace && L == 0 && t == 8) a.trace[4 * T_ + 1] = wall_clock64();
-                release(t);
-                if (t + 1 < nsteps) fetch(fb, fxb, fyb, t + 1);
-                step(fa, fxa, fya, t);
+                step(fa, fb, t);
                 if (t + 1 >= nsteps) break;
-                release(t + 1);
-                if (t + 2 < nsteps) fetch(fa, fxa, fya, t + 2);
-                step(fb, fxb, fyb, t + 1);
+                step(fb, fa, t + 1);
             }
             if (a.trace && L == 0) {
                 a.trace[4 * T_ + 2] = wall_clock64();
@@ -587,6 +613,12 @@ inline size_t sweep_slot_bytes(int dir)
 {
     const int NE = (dir == 0) ? 30 : 39;
     return (size_t)(NE * 64 + 48) * sizeof(T);
+}
+// dynamic LDS of a sweep: D ring slots, 64 tag words, the exchange rows
+template <typename T>
+inline size_t sweep_lds_bytes(int dir, int D)
+{
+    return (size_t)D * sweep_slot_bytes<T>(dir) + 64 * sizeof(int32_t) + 64 * 3 * sizeof(T);
 }
 
 // ---------------------------------------------------------------- the preconditioner object
@@ -774,7 +806,7 @@ struct Bilu0 : PcImpl {
             SweepArgs a = sweep_args(nw);
             a.D = (int)sweep_ring_depth(c, 0, 1);
             SweepSrc<float> s0{Lf32, (int64_t)27 * 64, 0, nullptr, 0, 0, r, nullptr};
-            size_t sh = (size_t)a.D * sweep_slot_bytes<float>(0) + 64 * sizeof(int32_t);
+            size_t sh = sweep_lds_bytes<float>(0, a.D);
             int t1 = prof_begin(c, RSV_K_ILU_FWD);
             hipLaunchKernelGGL((k_sweep<0, float, NLoad<0, float>::v>), dim3(nw), dim3(64 * (1 + NLoad<0, float>::v)), sh, c->stream, a, s0,
                                (float *)ybuf, (double *)nullptr);
@@ -783,7 +815,7 @@ struct Bilu0 : PcImpl {
             SweepArgs b = sweep_args(nw);
             b.D = (int)sweep_ring_depth(c, 1, 1);
             SweepSrc<float> s1{U32, (int64_t)27 * 64, 0, Dinv32, (int64_t)9 * 64, 0, nullptr, (const float *)ybuf};
-            sh = (size_t)b.D * sweep_slot_bytes<float>(1) + 64 * sizeof(int32_t);
+            sh = sweep_lds_bytes<float>(1, b.D);
             int t2 = prof_begin(c, RSV_K_ILU_BWD);
             hipLaunchKernelGGL((k_sweep<1, float, NLoad<1, float>::v>), dim3(nw), dim3(64 * (1 + NLoad<1, float>::v)), sh, c->stream, b, s1,
                                (float *)nullptr, z);
@@ -793,7 +825,7 @@ struct Bilu0 : PcImpl {
             SweepArgs a = sweep_args(nw);
             a.D = (int)sweep_ring_depth(c, 0, 0);
             SweepSrc<double> s0{Lf, (int64_t)27 * 64, 0, nullptr, 0, 0, r, nullptr};
-            size_t sh = (size_t)a.D * sweep_slot_bytes<double>(0) + 64 * sizeof(int32_t);
+            size_t sh = sweep_lds_bytes<double>(0, a.D);
             int t1 = prof_begin(c, RSV_K_ILU_FWD);
             hipLaunchKernelGGL((k_sweep<0, double, NLoad<0, double>::v>), dim3(nw), dim3(64 * (1 + NLoad<0, double>::v)), sh, c->stream, a, s0,
                                (double *)ybuf, (double *)nullptr);
@@ -804,7 +836,7 @@ struct Bilu0 : PcImpl {
             b.D = (int)sweep_ring_depth(c, 1, 0);
             SweepSrc<double> s1{M->d_A, (int64_t)63 * 64, (int64_t)36 * 64, Dinv, (int64_t)9 * 64, 0, nullptr,
                                 (const double *)ybuf};
-            sh = (size_t)b.D * sweep_slot_bytes<double>(1) + 64 * sizeof(int32_t);
+            sh = sweep_lds_bytes<double>(1, b.D);
             int t2 = prof_begin(c, RSV_K_ILU_BWD);
             hipLaunchKernelGGL((k_sweep<1, double, NLoad<1, double>::v>), dim3(nw), dim3(64 * (1 + NLoad<1, double>::v)), sh, c->stream, b, s1,
                                (double *)nullptr, z);
@@ -821,7 +853,7 @@ struct Bilu0 : PcImpl {
 
 int64_t sweep_ring_depth(const rsv_ctx *c, int dir, int fp32)
 {
-    const size_t cap = (size_t)c->lds_max - 1024;
+    const size_t cap = (size_t)c->lds_max - 64 * sizeof(int32_t) - 64 * 3 * sizeof(double);
     const size_t sb = fp32 ? sweep_slot_bytes<float>(dir) : sweep_slot_bytes<double>(dir);
     return (int64_t)std::max<size_t>(2, std::min<size_t>(12, cap / sb));
 }
