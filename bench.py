@@ -137,6 +137,8 @@ def main():
         forms_all["fgmres_learned"] = (rsv.FGMRES, dict(type=rsv.PC_LEARNED, net=net, lnk=lnk32))
         forms.append("fgmres_learned")
 
+    hbm_peak = [0]   # device memory in use (all allocations, torch and the library) after each solve
+
     def step(profile_headline=False):
         out = {}
         torch.cuda.synchronize()
@@ -160,6 +162,8 @@ def main():
             if prof:
                 out["kernels"] = ctx.profile_read()
                 ctx.profile(False)
+            free_b, total_b = torch.cuda.mem_get_info()
+            hbm_peak[0] = max(hbm_peak[0], total_b - free_b)
             err = float(torch.linalg.norm(x - xtd) / torch.linalg.norm(xtd))
             out[name] = {"setup_s": t2 - t1, "solve_s": t3 - t2, "its": st["its"], "relres": st["final_relres"],
                          "status": st["status"], "err_vs_xtrue": err, "fallbacks": st["fallbacks"]}
@@ -255,6 +259,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "device_bytes": A.device_bytes,
+        "hbm_used_bytes": int(hbm_peak[0]),
+        "hbm_total_bytes": int(torch.cuda.mem_get_info()[1]),
         "device": ctx.device_info(),
     }
     print(json.dumps(line), flush=True)
