@@ -216,7 +216,10 @@ __global__ __launch_bounds__(BS) void k_bwd_plane(Geo g, const int32_t *__restri
 // s + 7.  FP64 values are split into 32-bit halves, each stored with the
 // 32-bit call epoch in the upper half of a 64-bit word (FP32 values: one
 // word), so a word is valid exactly when its tag equals the current epoch --
-// no fences between tiles, no clearing between calls.  The loader of step t
+// no fences between tiles, no clearing between calls.  Word (p*W + h)*8 + e
+// of a row holds half h of component p of entry e, so the eight boundary
+// lanes store eight consecutive words (whole 64-byte segments, no partial
+// writes).  The loader of step t
 // reads the row (one word per lane), waits until every needed word carries
 // the epoch, and writes the values into the slot.  Tiles are handed out by an
 // atomic ticket in topological order, so a tile only waits on tiles held by
@@ -235,15 +238,16 @@ __device__ inline void face_st(uint64_t *p, uint64_t v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void face_put(uint64_t *p, double v, uint32_t ep)
+// component p of entry e of a face row (see the word order above)
+__device__ inline void face_put(uint64_t *row, int e, int p, double v, uint32_t ep)
 {
     const uint64_t b = (uint64_t)__double_as_longlong(v);
-    face_st(p, ((uint64_t)ep << 32) | (b & 0xffffffffull));
-    face_st(p + 1, ((uint64_t)ep << 32) | (b >> 32));
+    face_st(row + (2 * p) * 8 + e, ((uint64_t)ep << 32) | (b & 0xffffffffull));
+    face_st(row + (2 * p + 1) * 8 + e, ((uint64_t)ep << 32) | (b >> 32));
 }
-__device__ inline void face_put(uint64_t *p, float v, uint32_t ep)
+__device__ inline void face_put(uint64_t *row, int e, int p, float v, uint32_t ep)
 {
-    face_st(p, ((uint64_t)ep << 32) | (uint64_t)__float_as_uint(v));
+    face_st(row + p * 8 + e, ((uint64_t)ep << 32) | (uint64_t)__float_as_uint(v));
 }
 
 __device__ inline double shfl_d(double v, int src) { return __shfl(v, src, 64); }
@@ -340,7 +344,8 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             // ------------------------------------------------ loader waves
             const uint64_t *xin = a.faceX + (int64_t)(DIR == 0 ? T_ - 1 : T_ + 1) * frow;
             const uint64_t *yin = a.faceY + (int64_t)(DIR == 0 ? T_ - g.ntx : T_ + g.ntx) * frow;
-            const int eq = L / (3 * W);   // face entry of this lane's word
+            const int eq = L & 7;                    // face entry of this lane's word
+            const int fdst = (eq * 3 + (L >> 3) / W) * W + (L >> 3) % W;   // its 32-bit half in the slot's [8][3] values
             constexpr int nv = DIR == 0 ? 27 : 36;
             struct Regs {
                 T v[nv + 3];
@@ -455,8 +460,8 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 // (zero when the tile has no such neighbour: the value of an absent cell)
                 uint32_t *fs = (uint32_t *)(sl + NE * 64);
                 if (L < RW) {
-                    fs[L] = hasx ? (uint32_t)wx : 0u;
-                    fs[RW + L] = hasy ? (uint32_t)wy : 0u;
+                    fs[fdst] = hasx ? (uint32_t)wx : 0u;
+                    fs[RW + fdst] = hasy ? (uint32_t)wy : 0u;
                 }
                 // the slot's LDS writes complete before its tag is published
                 __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
@@ -571,14 +576,14 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                         for (int p = 0; p < 3; ++p) zp[p * 64] = (double)out[p];
                     }
                     if (px) {
-                        uint64_t *fp = fxo + (int64_t)(t - 7) * RW + lj * 3 * W;
+                        uint64_t *fp = fxo + (int64_t)(t - 7) * RW;
 #pragma unroll
-                        for (int p = 0; p < 3; ++p) face_put(fp + p * W, out[p], a.epoch);
+                        for (int p = 0; p < 3; ++p) face_put(fp, lj, p, out[p], a.epoch);
                     }
                     if (py) {
-                        uint64_t *fp = fyo + (int64_t)(t - 7) * RW + li * 3 * W;
+                        uint64_t *fp = fyo + (int64_t)(t - 7) * RW;
 #pragma unroll
-                        for (int p = 0; p < 3; ++p) face_put(fp + p * W, out[p], a.epoch);
+                        for (int p = 0; p < 3; ++p) face_put(fp, li, p, out[p], a.epoch);
                     }
                 }
                 slot = nslot;

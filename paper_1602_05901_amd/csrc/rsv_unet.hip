@@ -200,21 +200,26 @@ __global__ void k_sum_chunks(const float *__restrict__ partials, int nchunk, int
     }
 }
 
-// per-channel column sums of a [V][C] tensor (bias gradients), fixed order
-__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t *__restrict__ G, int64_t V, int C,
-                                                     float scale, float *__restrict__ grad)
+// per-channel column sums of a [V][C] BF16 tensor (bias gradients): block b sums
+// rows [b*chunk, (b+1)*chunk) with 256/C rows in flight (coalesced rows), one
+// partial per (block, channel); the partials are summed in block order after.
+__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t *__restrict__ G, int64_t V, int C, int64_t chunk,
+                                                     float *__restrict__ partials)
 {
     __shared__ float red[256];
-    const int c = blockIdx.x;
+    const int rows = 256 / C, c = threadIdx.x % C, r0 = threadIdx.x / C;
+    const int64_t v_begin = (int64_t)blockIdx.x * chunk;
+    const int64_t v_end = v_begin + chunk < V ? v_begin + chunk : V;
     float s = 0.f;
-    for (int64_t v = threadIdx.x; v < V; v += 256) s += bf2f(G[v * C + c]);
+    if (r0 < rows)
+        for (int64_t v = v_begin + r0; v < v_end; v += rows) s += bf2f(G[v * C + c]);
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+    if (threadIdx.x < C) {
+        float t = 0.f;
+        for (int q = 0; q < rows; ++q) t += red[q * C + threadIdx.x];
+        partials[(int64_t)blockIdx.x * C + threadIdx.x] = t;
     }
-    if (threadIdx.x == 0) grad[c] += scale * red[0];
 }
 
 // ---------------------------------------------------------------- elementwise pieces
@@ -640,11 +645,15 @@ static rsv_status conv_bwd_weight(rsv_net *n, int l, int nx, int ny, int nz, int
     const int per = (int)((nvb + chunks - 1) / chunks);
     chunks = (int)((nvb + per - 1) / per);
     const int64_t nw = 27LL * g.cin * g.cout;
-    rsv_status s = part_reserve(n, nw * chunks);
+    const int64_t bchunk = 2048;
+    const int bch = (int)((g.V + bchunk - 1) / bchunk);
+    rsv_status s = part_reserve(n, std::max<int64_t>(nw * chunks, (int64_t)bch * g.cout));
     if (s != RSV_OK) return s;
     hipLaunchKernelGGL(k_conv_dw, dim3(tiles, chunks), dim3(256), 0, c->stream, g, X, G, per, n->part);
     hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(nw)), dim3(256), 0, c->stream, (const float *)n->part, chunks, nw, scale, grad_w);
-    hipLaunchKernelGGL(k_colsum_bf16, dim3(g.cout), dim3(256), 0, c->stream, G, g.V, g.cout, scale, grad_b);
+    // bias: the partials buffer is reused after the weight sums (same stream)
+    hipLaunchKernelGGL(k_colsum_bf16, dim3(bch), dim3(256), 0, c->stream, G, g.V, g.cout, bchunk, n->part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, c->stream, (const float *)n->part, bch, (int64_t)g.cout, scale, grad_b);
     RSV_LAUNCH(c);
     return RSV_OK;
 }

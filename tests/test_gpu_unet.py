@@ -297,20 +297,20 @@ def test_fgmres_learned_converges_with_fallback(rsv, ctx):
     ref = O.gmres(Ao, b, pc=O.ILU(Ao), m=30, tol=1e-8, maxit=1000)
     g = rsv.Grid(ctx, *dims)
     A = rsv.Matrix(g, dev(B))
-    for seed, scale in ((1, 1.0), (2, 0.0)):
+    for seed, scale in ((1, 1.0), (2, 0.0), (3, np.nan)):
         net = rsv.Net(ctx, seed=seed)
-        if scale == 0.0:            # zeroed weights: N(r) = 0, every column falls back
-            net.set_params(np.zeros(net.num_params, np.float32))
+        if scale != 1.0:            # zeroed or NaN weights: every column of a cycle falls back
+            net.set_params(np.full(net.num_params, scale, np.float32))
         M = rsv.Precond(A, type=rsv.PC_LEARNED, net=net, lnk=dev(lnk.astype(np.float32)))
         x = torch.zeros(3 * cfg.ncell, dtype=torch.float64, device="cuda")
         st = rsv.solve(A, M, dev(b), x, method=rsv.FGMRES, restart=30, tol=1e-8, maxit=2000)
         log("  fgmres learned", seed, st)
         assert st["status"] == rsv.OK and st["final_relres"] <= 1e-8
         assert rel(x.cpu().numpy(), ref["x"]) <= 1e-6
-        if scale == 0.0:
-            # same decisions as the oracle's FGMRES with a zero map and the ILU(0) fallback
-            ref0 = O.fgmres(Ao, b, pc=lambda r: np.zeros_like(r), fallback=O.ILU(Ao), theta=0.99, m=30,
-                            tol=1e-8, maxit=2000)
+        if scale != 1.0:
+            # same decisions as the oracle's FGMRES with that map and the ILU(0) fallback
+            ref0 = O.fgmres(Ao, b, pc=lambda r, v=scale: np.full_like(r, 0.0) * v, fallback=O.ILU(Ao),
+                            theta=0.99, m=30, tol=1e-8, maxit=2000)
             assert st["fallbacks"] == ref0["fallbacks"] >= 3
             assert st["its"] == ref0["its"]
         M.close(); net.close()
