@@ -317,6 +317,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
     int32_t *tags = (int32_t *)(smem + (size_t)D * slot_elems * sizeof(T));
     int32_t *consumed = tags + D;
     int32_t *tile_sh = consumed + 1;
+    int32_t *ftags = tile_sh + 1;   // per slot: step whose face values are in the slot (+1)
     // exchange rows of the compute wave ([64][3] T) after the ring and its 64 tag words
     const uint32_t xch_off = (uint32_t)((size_t)D * slot_elems * sizeof(T) + 64 * sizeof(int32_t));
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
     lane_ij(L, li, lj);
     const int64_t frow = (int64_t)(nz + 7) * RW;
     if (threadIdx.x == 0) *consumed = 0;
-    for (int s = threadIdx.x; s < D; s += blockDim.x) tags[s] = 0;
+    for (int s = threadIdx.x; s < D; s += blockDim.x) tags[s] = ftags[s] = 0;
     __syncthreads();
     int gstep = 0;   // running step count across tiles (tags are gstep + 1)
     for (;;) {
@@ -420,6 +421,10 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
                 for (int e = 0; e < nv + 3; ++e) sl[e * 64 + L] = R.v[e];
+                // operands first (the compute wave prefetches them while faces are pending)
+                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __hip_atomic_store(&tags[slot], G + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 const bool need = face_need(t);
                 const bool okx = !hasx || !need || (uint32_t)(wx >> 32) == a.epoch;
                 const bool oky = !hasy || !need || (uint32_t)(wy >> 32) == a.epoch;
@@ -436,7 +441,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     uint32_t n = 0;
                     constexpr bool serial = NLOAD < 7;
                     if (serial && t > 0)
-                        while (__hip_atomic_load(&tags[(G - 1) % D], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G) {
+                        while (__hip_atomic_load(&ftags[(G - 1) % D], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G) {
                             if (spin_guard(a.flags, t0, n)) break;
                             __builtin_amdgcn_s_sleep(2);
                         }
@@ -463,10 +468,10 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     fs[fdst] = hasx ? (uint32_t)wx : 0u;
                     fs[RW + fdst] = hasy ? (uint32_t)wy : 0u;
                 }
-                // the slot's LDS writes complete before its tag is published
+                // the face writes complete before the face tag is published
                 __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                __hip_atomic_store(&tags[slot], G + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_store(&ftags[slot], G + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             };
             // two steps in flight per loader: the next step's loads are issued
             // before the current one is delivered
@@ -508,12 +513,12 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             T last[3] = {0, 0, 0};   // this lane's previous result: the -z (+z) neighbour value
             // spin until the loaders have delivered step G into `slot` (tag G + 1);
             // `seen` is a tag value already read
-            auto wait_slot = [&](int slot, int G, int seen) {
+            auto wait_slot = [&](int32_t *tg, int slot, int G, int seen) {
                 if (seen != G + 1) {
                     ++waited;
                     const uint64_t t0 = wall_clock64();
                     uint32_t n = 0;
-                    while (__hip_atomic_load(&tags[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != G + 1) {
+                    while (__hip_atomic_load(&tg[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != G + 1) {
                         if (spin_guard(a.flags, t0, n)) break;
                         __builtin_amdgcn_s_sleep(0);
                     }
@@ -533,9 +538,11 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             // writes; release of this step's slot (all its reads are consumed);
             // the next step's operands into fn (they land while the global
             // stores below are issued).
+            int fseen = 0;   // face tag of the current step's slot, read one step ahead
             auto step = [&](const T *f, T *fn, int t) {
                 const int G = gstep + t;
                 const int nslot = slot + 1 == D ? 0 : slot + 1;
+                wait_slot(ftags, slot, G, fseen);   // the boundary lanes read this step's faces
                 const T *bx = (const T *)(smem + (cx ? (uint32_t)slot * slot_bytes + xo_face : xo_int));
                 const T *by = (const T *)(smem + (cy ? (uint32_t)slot * slot_bytes + yo_face : yo_int));
                 T vx[3], vy[3];
@@ -562,8 +569,9 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 if (L == 0) __hip_atomic_store(consumed, G + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
                 if (more) {
-                    wait_slot(nslot, G + 1, seen);
+                    wait_slot(tags, nslot, G + 1, seen);
                     load_ops(fn, nslot);
+                    fseen = __hip_atomic_load(&ftags[nslot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
                 if (act) {
                     if (DIR == 0) {
@@ -591,8 +599,9 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 else row = row == 0 ? nz - 1 : row - 1;
             };
             T fa[NE], fb[NE];
-            wait_slot(slot, gstep, __hip_atomic_load(&tags[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            wait_slot(tags, slot, gstep, __hip_atomic_load(&tags[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
             load_ops(fa, slot);
+            fseen = __hip_atomic_load(&ftags[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             for (int t = 0; t < nsteps; t += 2) {
                 if (a.trace && L == 0 && t == 8) a.trace[4 * T_ + 1] = wall_clock64();
                 step(fa, fb, t);
