@@ -87,40 +87,59 @@ __device__ inline int64_t src_voxel(const ConvGeo &g, int x, int y, int z, int d
 }
 
 // ---------------------------------------------------------------- convolution as implicit GEMM
-// One wavefront: 16 output voxels x (16*NB) output channels.  GEMM row m = voxel,
-// column n = output channel, k = tap*cin + ci.  Operand fragments of
+// One wavefront: 16*MB output voxels x (16*NB) output channels.  GEMM row m =
+// voxel, column n = output channel, k = tap*cin + ci.  Operand fragments of
 // v_mfma_f32_16x16x16_bf16: lane l holds A[m = l%16][k = 4*(l/16) .. +3] and
 // B[k = 4*(l/16) .. +3][n = l%16]; the result holds D[m = 4*(l/16) + i][n = l%16].
-// Weights are pre-packed so that B fragments are one 8-byte load per lane.
-template <int NB, bool OUT_BF16>
+// Weights are pre-packed so that B fragments are one 8-byte load per lane; an A
+// fragment (16 consecutive voxels x 16 k) is one contiguous 512-byte row of
+// the channels-last input when the tap keeps the voxels inside the grid row.
+// Each B fragment feeds MB products and each A fragment NB.
+template <int MB, int NB, bool OUT_BF16>
 __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const uint16_t *__restrict__ X, const v4s *__restrict__ Wf,
                                               int KB, const float *__restrict__ bias,
                                               const uint16_t *__restrict__ skip, int relu, void *__restrict__ out)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t v0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    const int64_t v0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MB);
     if (v0 >= g.V) return;
     const int m = lane & 15, kq = 4 * (lane >> 4);
-    const int64_t v = v0 + m;
-    const bool live = v < g.V;   // the last tile of a level may be partial
-    const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
-    v4f acc[NB];
+    int px[MB], py[MB], pz[MB];
+    bool live[MB];   // the last tile of a level may be partial
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int mb = 0; mb < MB; ++mb) {
+        const int64_t v = v0 + mb * 16 + m;
+        live[mb] = v < g.V;
+        px[mb] = (int)(v % g.nx);
+        py[mb] = (int)((v / g.nx) % g.ny);
+        pz[mb] = (int)(v / ((int64_t)g.nx * g.ny));
+    }
+    v4f acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
     const int K = 27 * g.cin;
     for (int kb = 0; kb < KB; ++kb) {
         const int k = kb * 16 + kq;
-        v4s a = v4s{0, 0, 0, 0};
-        if (k < K && live) {
-            const int tap = k / g.cin, ci = k - tap * g.cin;
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const int64_t u = src_voxel(g, x, y, z, dx, dy, dz);
-            if (u >= 0) a = *(const v4s *)(X + u * g.cin + ci);
+        const bool kin = k < K;
+        const int tap = kin ? k / g.cin : 0, ci = k - tap * g.cin;
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        v4s a[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            a[mb] = v4s{0, 0, 0, 0};
+            if (kin && live[mb]) {
+                const int64_t u = src_voxel(g, px[mb], py[mb], pz[mb], dx, dy, dz);
+                if (u >= 0) a[mb] = *(const v4s *)(X + u * g.cin + ci);
+            }
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const v4s b = Wf[((int64_t)kb * NB + nb) * 64 + lane];
-            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nb], 0, 0, 0);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], b, acc[mb][nb], 0, 0, 0);
         }
     }
     const int n = lane & 15, mr = 4 * (lane >> 4);
@@ -129,16 +148,44 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const uint16_t *__restr
         const int co = nb * 16 + n;
         const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t vo = v0 + mr + i;
-            if (vo >= g.V) continue;
-            float val = acc[nb][i] + bb;
-            if (skip) val += bf2f(skip[vo * g.cout + co]);
-            if (relu) val = val > 0.f ? val : 0.f;
-            if (OUT_BF16) ((uint16_t *)out)[vo * g.cout + co] = f2bf(val);
-            else ((float *)out)[vo * g.cout + co] = val;
-        }
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t vo = v0 + mb * 16 + mr + i;
+                if (vo >= g.V) continue;
+                float val = acc[mb][nb][i] + bb;
+                if (skip) val += bf2f(skip[vo * g.cout + co]);
+                if (relu) val = val > 0.f ? val : 0.f;
+                if (OUT_BF16) ((uint16_t *)out)[vo * g.cout + co] = f2bf(val);
+                else ((float *)out)[vo * g.cout + co] = val;
+            }
     }
+}
+
+// launch of k_conv: NB = cout / 16 column blocks; 4 voxel blocks per wave on
+// large levels (weight fragments reused four times), 1 on small ones (more waves)
+template <bool OUT_BF16>
+hipError_t launch_conv(hipStream_t st, const ConvGeo &g, const uint16_t *X, const v4s *Wf, int KB, const float *bias,
+                       const uint16_t *skip, int relu, void *out)
+{
+    const int NB = (g.cout + 15) / 16;
+    const int MB = g.V >= 131072 ? 4 : 1;
+    const int64_t waves = (g.V + 16 * MB - 1) / (16 * MB);
+    const dim3 grid((unsigned)((waves + 3) / 4)), blk(256);
+#define RSV_CONV(mb, nb) hipLaunchKernelGGL((k_conv<mb, nb, OUT_BF16>), grid, blk, 0, st, g, X, Wf, KB, bias, skip, relu, out)
+    if (MB == 4) {
+        if (NB == 1) RSV_CONV(4, 1);
+        else if (NB == 2) RSV_CONV(4, 2);
+        else if (NB == 4) RSV_CONV(4, 4);
+        else return hipErrorInvalidValue;
+    } else {
+        if (NB == 1) RSV_CONV(1, 1);
+        else if (NB == 2) RSV_CONV(1, 2);
+        else if (NB == 4) RSV_CONV(1, 4);
+        else return hipErrorInvalidValue;
+    }
+#undef RSV_CONV
+    return hipGetLastError();
 }
 
 // Weight gradient dW[tap][ci][co] = sum_v X[v + off(tap)][ci] * G[v][co] as an
@@ -603,16 +650,9 @@ static rsv_status conv_fwd(rsv_net *n, int l, int nx, int ny, int nz, int up, co
 {
     rsv_ctx *c = n->c;
     ConvGeo g{nx, ny, nz, up, n->a.cin[l], n->a.cout[l], (int64_t)nx * ny * nz};
-    const int grid = (int)(((g.V + 15) / 16 + 3) / 4);
-    const int NB = g.cout / 16;
-    const float *b = n->P + n->a.boff[l];
-    switch (NB) {
-    case 1: hipLaunchKernelGGL((k_conv<1, true>), dim3(grid), dim3(256), 0, c->stream, g, X, n->wf[l], n->a.kb(l), b, skip, relu, (void *)out); break;
-    case 2: hipLaunchKernelGGL((k_conv<2, true>), dim3(grid), dim3(256), 0, c->stream, g, X, n->wf[l], n->a.kb(l), b, skip, relu, (void *)out); break;
-    case 4: hipLaunchKernelGGL((k_conv<4, true>), dim3(grid), dim3(256), 0, c->stream, g, X, n->wf[l], n->a.kb(l), b, skip, relu, (void *)out); break;
-    default: return set_err(c, RSV_ERR_ARG, "channel count must be 16, 32 or 64");
-    }
-    RSV_LAUNCH(c);
+    if (g.cout % 16) return set_err(c, RSV_ERR_ARG, "channel count must be 16, 32 or 64");
+    const hipError_t e = launch_conv<true>(c->stream, g, X, n->wf[l], n->a.kb(l), n->P + n->a.boff[l], skip, relu, out);
+    if (e != hipSuccess) return set_err(c, RSV_ERR_HIP, std::string("conv launch: ") + hipGetErrorString(e));
     return RSV_OK;
 }
 
@@ -621,15 +661,9 @@ static rsv_status conv_bwd_data(rsv_net *n, int l, int nx, int ny, int nz, const
 {
     rsv_ctx *c = n->c;
     ConvGeo g{nx, ny, nz, 0, n->a.cout[l], n->a.cin[l], (int64_t)nx * ny * nz};
-    const int grid = (int)(((g.V + 15) / 16 + 3) / 4);
-    const int NB = (g.cout + 15) / 16;
-    switch (NB) {
-    case 1: hipLaunchKernelGGL((k_conv<1, false>), dim3(grid), dim3(256), 0, c->stream, g, G, n->wt[l], n->a.kbt(l), (const float *)nullptr, (const uint16_t *)nullptr, 0, (void *)dX); break;
-    case 2: hipLaunchKernelGGL((k_conv<2, false>), dim3(grid), dim3(256), 0, c->stream, g, G, n->wt[l], n->a.kbt(l), (const float *)nullptr, (const uint16_t *)nullptr, 0, (void *)dX); break;
-    case 4: hipLaunchKernelGGL((k_conv<4, false>), dim3(grid), dim3(256), 0, c->stream, g, G, n->wt[l], n->a.kbt(l), (const float *)nullptr, (const uint16_t *)nullptr, 0, (void *)dX); break;
-    default: return set_err(c, RSV_ERR_ARG, "channel count must be 16, 32 or 64");
-    }
-    RSV_LAUNCH(c);
+    if (g.cout % 16) return set_err(c, RSV_ERR_ARG, "channel count must be 16, 32 or 64");
+    const hipError_t e = launch_conv<false>(c->stream, g, G, n->wt[l], n->a.kbt(l), nullptr, nullptr, 0, dX);
+    if (e != hipSuccess) return set_err(c, RSV_ERR_HIP, std::string("conv launch: ") + hipGetErrorString(e));
     return RSV_OK;
 }
 
@@ -1049,11 +1083,7 @@ rsv_status rsv_conv3d(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32_t ci
     if (s != RSV_OK) return s;
     hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)KB * NB * 64)), dim3(256), 0, c->stream, w, cin, cout, 0, KB, NB, wf);
     ConvGeo g{nx, ny, nz, 0, cin, cout, (int64_t)nx * ny * nz};
-    const int grid = (int)(((g.V + 15) / 16 + 3) / 4);
-    if (NB == 1) hipLaunchKernelGGL((k_conv<1, false>), dim3(grid), dim3(256), 0, c->stream, g, x, wf, KB, b, (const uint16_t *)nullptr, 0, (void *)y);
-    if (NB == 2) hipLaunchKernelGGL((k_conv<2, false>), dim3(grid), dim3(256), 0, c->stream, g, x, wf, KB, b, (const uint16_t *)nullptr, 0, (void *)y);
-    if (NB == 4) hipLaunchKernelGGL((k_conv<4, false>), dim3(grid), dim3(256), 0, c->stream, g, x, wf, KB, b, (const uint16_t *)nullptr, 0, (void *)y);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_conv<false>(c->stream, g, x, wf, KB, b, nullptr, 0, y);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     dev_free(wf);
     if (e != hipSuccess) return set_err(c, RSV_ERR_HIP, std::string("conv3d: ") + hipGetErrorString(e));

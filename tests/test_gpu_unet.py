@@ -93,8 +93,11 @@ def net_params(seed, ch=(16, 32, 64), bias=0.05):
 
 # ---------------------------------------------------------------- one layer
 
+# small levels (one voxel block per wave), ragged ones, and two large levels
+# (four voxel blocks per wave; the second with a partial last block)
 CONV_CASES = [((8, 8, 4), 4, 16), ((8, 8, 4), 16, 16), ((6, 5, 3), 16, 32), ((4, 4, 4), 32, 64),
-              ((4, 4, 2), 64, 32), ((5, 3, 7), 64, 64), ((16, 16, 8), 16, 16), ((3, 1, 1), 4, 32)]
+              ((4, 4, 2), 64, 32), ((5, 3, 7), 64, 64), ((16, 16, 8), 16, 16), ((3, 1, 1), 4, 32),
+              ((64, 64, 32), 4, 16), ((65, 45, 45), 16, 32)]
 
 
 @pytest.mark.parametrize("dims,cin,cout", CONV_CASES)
