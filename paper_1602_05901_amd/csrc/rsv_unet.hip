@@ -162,6 +162,92 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const uint16_t *__restr
     }
 }
 
+// LDS-tiled variant for inputs of at most 32 channels: a workgroup computes a
+// 16 (x) x 4 (y) x 4 (z) output block; the 18 x 6 x 6 input halo (zero outside
+// the grid, nearest-up-sampled when `up`) and the packed weights are staged in
+// LDS once, so every MFMA operand comes from LDS.  Wave w owns output plane
+// z0 + w; its voxel block mb is the x-run at y0 + mb.
+constexpr int CT_X = 16, CT_Y = 4, CT_Z = 4, CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2;
+constexpr int CH_N = CH_X * CH_Y * CH_Z;   // 648 halo voxels
+
+inline size_t conv_lds_bytes(int cin, int KB, int NB) { return (size_t)CH_N * cin * 2 + (size_t)KB * NB * 64 * sizeof(v4s); }
+
+template <int NB, bool OUT_BF16>
+__global__ __launch_bounds__(256) void k_conv_lds(ConvGeo g, const uint16_t *__restrict__ X, const v4s *__restrict__ Wf,
+                                                  int KB, const float *__restrict__ bias,
+                                                  const uint16_t *__restrict__ skip, int relu, void *__restrict__ out)
+{
+    extern __shared__ __align__(16) unsigned char cl[];
+    v4s *wl = (v4s *)cl;                                        // [KB][NB][64]
+    uint16_t *xl = (uint16_t *)(cl + (size_t)KB * NB * 64 * sizeof(v4s));   // [648][cin]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ntx = (g.nx + CT_X - 1) / CT_X, nty = (g.ny + CT_Y - 1) / CT_Y;
+    const int b = blockIdx.x;
+    const int x0 = (b % ntx) * CT_X, y0 = ((b / ntx) % nty) * CT_Y, z0 = (b / (ntx * nty)) * CT_Z;
+    const int cin = g.cin, c4 = cin / 4;
+    // stage the weights and the halo
+    for (int e = threadIdx.x; e < KB * NB * 64; e += 256) wl[e] = Wf[e];
+    for (int e = threadIdx.x; e < CH_N * c4; e += 256) {
+        const int h = e / c4, q = e - h * c4;
+        const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
+        const int64_t u = src_voxel(g, x0, y0, z0, hx - 1, hy - 1, hz - 1);
+        v4s val = v4s{0, 0, 0, 0};
+        if (u >= 0) val = *(const v4s *)(X + u * cin + 4 * q);
+        *(v4s *)(xl + (size_t)h * cin + 4 * q) = val;
+    }
+    __syncthreads();
+    const int m = lane & 15, kq = 4 * (lane >> 4);
+    v4f acc[CT_Y][NB];
+#pragma unroll
+    for (int mb = 0; mb < CT_Y; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int K = 27 * cin;
+    for (int kb = 0; kb < KB; ++kb) {
+        const int k = kb * 16 + kq;
+        const bool kin = k < K;
+        const int tap = kin ? k / cin : 0, ci = k - tap * cin;
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo offsets (0..2)
+        v4s a[CT_Y];
+#pragma unroll
+        for (int mb = 0; mb < CT_Y; ++mb) {
+            const int h = ((wave + dz) * CH_Y + (mb + dy)) * CH_X + (m + dx);
+            a[mb] = kin ? *(const v4s *)(xl + (size_t)h * cin + ci) : v4s{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const v4s bf = wl[(kb * NB + nb) * 64 + lane];
+#pragma unroll
+            for (int mb = 0; mb < CT_Y; ++mb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], bf, acc[mb][nb], 0, 0, 0);
+        }
+    }
+    const int n = lane & 15, mr = 4 * (lane >> 4);
+    const int z = z0 + wave;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 16 + n;
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int mb = 0; mb < CT_Y; ++mb) {
+            const int y = y0 + mb;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + mr + i;
+                if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+                const int64_t vo = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+                float val = acc[mb][nb][i] + bb;
+                if (skip) val += bf2f(skip[vo * g.cout + co]);
+                if (relu) val = val > 0.f ? val : 0.f;
+                if (OUT_BF16) ((uint16_t *)out)[vo * g.cout + co] = f2bf(val);
+                else ((float *)out)[vo * g.cout + co] = val;
+            }
+        }
+    }
+}
+
+constexpr size_t CONV_LDS_MAX = 96 * 1024;
+
 // launch of k_conv: NB = cout / 16 column blocks; 4 voxel blocks per wave on
 // large levels (weight fragments reused four times), 1 on small ones (more waves)
 template <bool OUT_BF16>
@@ -169,6 +255,28 @@ hipError_t launch_conv(hipStream_t st, const ConvGeo &g, const uint16_t *X, cons
                        const uint16_t *skip, int relu, void *out)
 {
     const int NB = (g.cout + 15) / 16;
+    if (g.cin <= 32 && conv_lds_bytes(g.cin, KB, NB) <= CONV_LDS_MAX && g.V >= 4096) {
+        static bool attr[2][5] = {};
+        const size_t sh = conv_lds_bytes(g.cin, KB, NB);
+        const int64_t nblk_ = (int64_t)((g.nx + CT_X - 1) / CT_X) * ((g.ny + CT_Y - 1) / CT_Y) * ((g.nz + CT_Z - 1) / CT_Z);
+#define RSV_CONVL(nb)                                                                                                     \
+    do {                                                                                                              \
+        if (!attr[OUT_BF16][nb]) {                                                                                    \
+            hipError_t e_ = hipFuncSetAttribute((const void *)k_conv_lds<nb, OUT_BF16>,                               \
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)CONV_LDS_MAX);       \
+            if (e_ != hipSuccess) return e_;                                                                          \
+            attr[OUT_BF16][nb] = true;                                                                                \
+        }                                                                                                             \
+        hipLaunchKernelGGL((k_conv_lds<nb, OUT_BF16>), dim3((unsigned)nblk_), dim3(256), sh, st, g, X, Wf, KB, bias, \
+                           skip, relu, out);                                                                          \
+    } while (0)
+        if (NB == 1) RSV_CONVL(1);
+        else if (NB == 2) RSV_CONVL(2);
+        else if (NB == 4) RSV_CONVL(4);
+        else return hipErrorInvalidValue;
+#undef RSV_CONVL
+        return hipGetLastError();
+    }
     const int MB = g.V >= 131072 ? 4 : 1;
     const int64_t waves = (g.V + 16 * MB - 1) / (16 * MB);
     const dim3 grid((unsigned)((waves + 3) / 4)), blk(256);

@@ -155,7 +155,7 @@ def net_inputs(dims, seed):
     return r, lnk
 
 
-@pytest.mark.parametrize("dims", [(8, 8, 4), (16, 16, 8), (12, 8, 4), (4, 4, 4)])
+@pytest.mark.parametrize("dims", [(8, 8, 4), (16, 16, 8), (12, 8, 4), (4, 4, 4), (32, 32, 8), (36, 20, 12)])
 def test_net_forward_parity(rsv, ctx, dims):
     log("net forward", dims)
     ch = (16, 32, 64)
@@ -192,8 +192,9 @@ def test_net_rejects_bad_grid(rsv, ctx):
     g.close(); net.close()
 
 
-def test_net_loss_grad_parity(rsv, ctx):
-    dims, ch, nb = (8, 8, 4), (16, 32, 64), 2
+@pytest.mark.parametrize("dims", [(8, 8, 4), (32, 16, 8)])
+def test_net_loss_grad_parity(rsv, ctx, dims):
+    ch, nb = (16, 32, 64), 2
     log("net loss/grad", dims, nb)
     p = net_params(20)
     V = dims[0] * dims[1] * dims[2]
