@@ -129,6 +129,13 @@ int32_t rsv_version(void);
  * [3] ring depth of the forward FP64 sweep, [4] of the backward FP64 sweep.
  * Writes min(n, 5) entries.  Errors: RSV_ERR_ARG. */
 rsv_status rsv_device_info(const rsv_ctx *ctx, int64_t *info, int32_t n);
+/* Bound, in seconds, on every wait of the pipelined wavefront kernels (a tile
+ * waiting for a neighbouring tile's values; default 2).  A wait that exceeds
+ * it stops all waits of that launch, the launch runs to its end, and the call
+ * that issued it (preconditioner apply, solve) returns RSV_ERR_TIMEOUT.  A
+ * hang watchdog: the solver's kernels never spin unbounded.
+ * Errors: RSV_ERR_ARG (ctx NULL, seconds not in (0, 60]). */
+rsv_status rsv_set_wait_limit(rsv_ctx *ctx, double seconds);
 
 /* ---------------------------------------------------------------- grid and MAP */
 

@@ -122,6 +122,14 @@ rsv_status rsv_profile_read(rsv_ctx *c, double *ms, int64_t *cnt)
 
 int32_t rsv_version(void) { return RSV_VERSION; }
 
+rsv_status rsv_set_wait_limit(rsv_ctx *c, double seconds)
+{
+    if (!c || !(seconds > 0.0) || seconds > 60.0) return set_err(c, RSV_ERR_ARG, "wait limit must be in (0, 60] s");
+    c->wait_ticks = (uint64_t)(seconds * 1e8);   // the device wall clock runs at 100 MHz
+    if (c->wait_ticks == 0) c->wait_ticks = 1;
+    return RSV_OK;
+}
+
 rsv_status rsv_device_info(const rsv_ctx *c, int64_t *info, int32_t n)
 {
     if (!c || !info || n < 0) return set_err(nullptr, RSV_ERR_ARG, "NULL argument");

@@ -31,7 +31,6 @@
 namespace {
 
 constexpr int BS = 256;
-constexpr uint64_t SPIN_LIMIT_TICKS = 200000000ull;   // 2 s of the 100 MHz wall clock
 
 __device__ inline int64_t fidx(int64_t slot, int e, int ne) { return ((slot >> 6) * ne + e) * 64 + (slot & 63); }
 
@@ -256,28 +255,18 @@ __device__ inline float shfl_d(float v, int src) { return __shfl(v, src, 64); }
 // Spin-loop guard: checks the clock and the shared error flag only every 256th
 // call (the flag read is a device-scope load, which waits for every memory
 // operation the wave still has in flight).
-__device__ inline bool spin_guard(int32_t *flags, uint64_t t0, uint32_t &n)
+__device__ inline bool spin_guard(int32_t *flags, uint64_t t0, uint32_t &n, uint64_t limit)
 {
     if ((++n & 255u) != 0u) return false;
     const int32_t fl = __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (fl & FLAG_TIMEOUT) return true;
-    if (wall_clock64() - t0 > SPIN_LIMIT_TICKS) {
+    if (wall_clock64() - t0 > limit) {
         atomicOr(&flags[0], FLAG_TIMEOUT);
         return true;
     }
     return false;
 }
 
-__device__ inline bool timed_out(int32_t *flags, uint64_t t0)
-{
-    const int32_t fl = __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (fl & FLAG_TIMEOUT) return true;
-    if (wall_clock64() - t0 > SPIN_LIMIT_TICKS) {
-        atomicOr(&flags[0], FLAG_TIMEOUT);
-        return true;
-    }
-    return false;
-}
 
 struct SweepArgs {
     Geo g;
@@ -288,6 +277,7 @@ struct SweepArgs {
     uint64_t *faceY;
     uint32_t epoch;
     int32_t *flags;
+    uint64_t wait_limit;         // wall-clock ticks a wait may last
     int D;                       // LDS ring slots
     uint64_t *trace;             // optional: per tile [start, step 8 reached, end, steps that waited for data]
 };
@@ -414,7 +404,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     const uint64_t t0 = wall_clock64();
                     uint32_t n = 0;
                     while (__hip_atomic_load(consumed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G - D + 1) {
-                        if (spin_guard(a.flags, t0, n)) break;
+                        if (spin_guard(a.flags, t0, n, a.wait_limit)) break;
                         __builtin_amdgcn_s_sleep(1);
                     }
                 }
@@ -442,7 +432,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     constexpr bool serial = NLOAD < 7;
                     if (serial && t > 0)
                         while (__hip_atomic_load(&ftags[(G - 1) % D], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G) {
-                            if (spin_guard(a.flags, t0, n)) break;
+                            if (spin_guard(a.flags, t0, n, a.wait_limit)) break;
                             __builtin_amdgcn_s_sleep(2);
                         }
                     int backoff = 1;
@@ -452,7 +442,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                         const bool ok = (!hasx || !need || (uint32_t)(wx >> 32) == a.epoch) &&
                                         (!hasy || !need || (uint32_t)(wy >> 32) == a.epoch);
                         if (__ballot(!ok) == 0ull) break;
-                        if (spin_guard(a.flags, t0, n)) break;
+                        if (spin_guard(a.flags, t0, n, a.wait_limit)) break;
                         if (!serial) {
                             __builtin_amdgcn_s_sleep(2);
                         } else {
@@ -519,7 +509,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     const uint64_t t0 = wall_clock64();
                     uint32_t n = 0;
                     while (__hip_atomic_load(&tg[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != G + 1) {
-                        if (spin_guard(a.flags, t0, n)) break;
+                        if (spin_guard(a.flags, t0, n, a.wait_limit)) break;
                         __builtin_amdgcn_s_sleep(0);
                     }
                 }
@@ -773,6 +763,7 @@ struct Bilu0 : PcImpl {
         a.epoch = c->epoch++;
         if (c->epoch == 0) c->epoch = 1;
         a.flags = c->d_flags;
+        a.wait_limit = c->wait_ticks;
         a.trace = trace;
         c->ticket_base[0] += (uint64_t)(g.ntx * g.nty) + nwaves;
         return a;

@@ -127,6 +127,7 @@ struct rsv_ctx {
     double *d_partials = nullptr; // device partial sums
     int64_t partials_cap = 0;     // doubles
     uint32_t epoch = 1;           // wavefront face-exchange epoch
+    uint64_t wait_ticks = 200000000ull;   // bound on a wavefront wait (100 MHz wall clock; 2 s)
     uint64_t *d_tickets = nullptr;// tile ticket counters (8 counters)
     uint64_t ticket_base[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int32_t *d_flags = nullptr;   // [0] error flags, [1] bad cell (min)

@@ -365,6 +365,7 @@ rsv_status rsv_precond_apply(rsv_precond *P, const double *r, double *z)
     rsv_matrix *M = P->A;
     rsv_ctx *c = M->g->ctx;
     rsv_status s = ws_reserve(M, 2);
+    if (s == RSV_OK) s = flags_reset(c);
     if (s != RSV_OK) return s;
     const int64_t n = M->g->nv;
     double *rt = M->ws->pool, *zt = M->ws->pool + n;

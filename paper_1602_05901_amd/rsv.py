@@ -87,6 +87,7 @@ _SIGS = {
     "rsv_profile_enable": ([vp, i32], i32),
     "rsv_profile_read": ([vp, vp, vp], i32),
     "rsv_device_info": ([vp, vp, i32], i32),
+    "rsv_set_wait_limit": ([vp, ctypes.c_double], i32),
 }
 K_NAMES = ["spmv", "ilu_fwd", "ilu_bwd", "ras", "ortho", "vec", "factor", "net"]
 
@@ -148,6 +149,9 @@ class Context:
         _check(self, lib().rsv_device_info(self.h, v.ctypes.data, 5))
         return {"num_cu": int(v[0]), "lds_per_workgroup": int(v[1]), "lds_per_cu": int(v[2]),
                 "sweep_ring_fwd": int(v[3]), "sweep_ring_bwd": int(v[4])}
+
+    def set_wait_limit(self, seconds):
+        _check(self, lib().rsv_set_wait_limit(self.h, seconds))
 
     def profile(self, on=True):
         _check(self, lib().rsv_profile_enable(self.h, 1 if on else 0))

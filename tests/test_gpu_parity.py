@@ -372,3 +372,32 @@ def test_C2_full_solve(rsv, ctx, method):
     check_solve(st, ref, xg, relres, its_band=(method != "bicgstab_bilu0"),
                 hist_steps=(6 if method == "bicgstab_bilu0" else 10))
     assert rel(xg, xt) <= 1e-5
+
+
+# ---------------------------------------------------------------- hang watchdog
+
+def test_wait_limit_reports_timeout_and_recovers(rsv, ctx):
+    """A tiny bound on the wavefront waits (forced from the host) makes the
+    pipelined sweeps give up waiting for neighbouring tiles: every wait ends,
+    the launch drains, and the apply returns RSV_ERR_TIMEOUT.  With the
+    default bound restored the next apply is correct again."""
+    log("wait limit")
+    S = Sys(rsv, ctx, cfg_of((64, 64, 32), seed=3))
+    M = rsv.Precond(S.A, type=rsv.PC_BILU0)
+    n = 3 * S.cfg.ncell
+    r = I.test_vector(5, n)
+    z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(rsv.RsvError):
+        ctx.set_wait_limit(0.0)
+    ctx.set_wait_limit(1e-7)
+    try:
+        with pytest.raises(rsv.RsvError) as ei:
+            M.apply(dev(r), z)
+        assert ei.value.status == rsv.ERR_TIMEOUT
+    finally:
+        ctx.set_wait_limit(2.0)
+    M.apply(dev(r), z)
+    ref = O.ILU(S.Ao).apply(r)
+    assert rel(z.cpu().numpy(), ref) <= 1e-12
+    M.close()
+    S.close()
