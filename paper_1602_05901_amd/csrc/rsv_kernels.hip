@@ -11,6 +11,34 @@ namespace {
 constexpr int BS = 256;          // threads per block for streaming kernels
 constexpr int RED_T = 1024;      // threads of the final reduction
 
+// Sum of v over the 64 lanes of a wave (butterfly; every lane gets the sum).
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sums of K per-thread values over the block, one barrier for all K: each
+// wave reduces its K values by butterflies, the waves' results meet in LDS
+// (red[K][nw]) and thread i < K adds them in wave order.  Writes out[i].
+template <int KB>
+__device__ inline void block_sums(const double *acc, int K, double *red, double *out)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+        if (i < K) {
+            const double v = wave_sum(acc[i]);
+            if ((threadIdx.x & 63) == 0) red[i * nw + w] = v;
+        }
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        double t = 0.0;
+        for (int q = 0; q < nw; ++q) t += red[threadIdx.x * nw + q];
+        out[threadIdx.x] = t;
+    }
+}
+
 // Sum of v over the block (deterministic butterfly + fixed-order LDS pass);
 // result valid in thread 0.
 __device__ inline double block_sum(double v, double *lds)
@@ -82,15 +110,17 @@ __global__ __launch_bounds__(BS) void k_spmv(Geo g, const double *__restrict__ A
     }
 }
 
+// final stage: wave w sums outputs kk = w, w + 16, ... over the nb block
+// partials ([nb][K]), lane-strided then by butterfly (fixed order, no barriers)
 __global__ __launch_bounds__(RED_T) void k_reduce(const double *__restrict__ partials, int nb, int K,
                                                  double *__restrict__ out)
 {
-    __shared__ double lds[16];
-    for (int kk = 0; kk < K; ++kk) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int kk = w; kk < K; kk += RED_T / 64) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += RED_T) s += partials[(int64_t)b * K + kk];
-        s = block_sum(s, lds);
-        if (threadIdx.x == 0) out[kk] = s;
+        for (int b = lane; b < nb; b += 64) s += partials[(int64_t)b * K + kk];
+        s = wave_sum(s);
+        if (lane == 0) out[kk] = s;
     }
 }
 
@@ -191,7 +221,7 @@ template <int KB>
 __global__ __launch_bounds__(BS) void k_mdot(int64_t n, const double *__restrict__ V, int64_t ldv, int K,
                                              const double *__restrict__ w, double *__restrict__ partials)
 {
-    __shared__ double lds[16];
+    __shared__ double red[KB * (BS / 64)];
     double acc[KB];
 #pragma unroll
     for (int i = 0; i < KB; ++i) acc[i] = 0.0;
@@ -201,14 +231,7 @@ __global__ __launch_bounds__(BS) void k_mdot(int64_t n, const double *__restrict
         for (int i = 0; i < KB; ++i)
             if (i < K) acc[i] += V[i * ldv + e] * we;
     }
-    for (int i = 0; i < K; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < KB; ++q)
-            if (q == i) s = acc[q];
-        s = block_sum(s, lds);
-        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * K + i] = s;
-    }
+    block_sums<KB>(acc, K, red, partials + (int64_t)blockIdx.x * K);
 }
 
 // w -= sum_i c_i V_i (c_i = sc[kc+i], ascending i); then partial V_i . w (MODE 0) or w.w (MODE 1)
@@ -217,7 +240,7 @@ __global__ __launch_bounds__(BS) void k_upd(int64_t n, const double *__restrict_
                                             double *__restrict__ w, const double *__restrict__ c,
                                             double *__restrict__ partials)
 {
-    __shared__ double lds[16];
+    __shared__ double red[(MODE == 0 ? KB : 1) * (BS / 64)];
     double coef[KB];
     double acc[MODE == 0 ? KB : 1];
 #pragma unroll
@@ -243,14 +266,7 @@ __global__ __launch_bounds__(BS) void k_upd(int64_t n, const double *__restrict_
         }
     }
     const int nout = (MODE == 0) ? K : 1;
-    for (int i = 0; i < nout; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < (MODE == 0 ? KB : 1); ++q)
-            if (q == i) s = acc[q];
-        s = block_sum(s, lds);
-        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * nout + i] = s;
-    }
+    block_sums<(MODE == 0 ? KB : 1)>(acc, nout, red, partials + (int64_t)blockIdx.x * nout);
 }
 
 template <int KB>
@@ -339,6 +355,16 @@ int vec_blocks(int64_t n)
 {
     int64_t b = (n + BS - 1) / BS;
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 2048);
+}
+
+// the multi-vector (CGS2) kernels (grid size chosen by measurement)
+#ifndef RSV_MVEC_BLOCKS
+#define RSV_MVEC_BLOCKS 4096
+#endif
+int mvec_blocks(int64_t n)
+{
+    int64_t b = (n + BS - 1) / BS;
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), RSV_MVEC_BLOCKS);
 }
 
 rsv_status launch_reduce(rsv_ctx *c, int nblocks, int K, int k0)
@@ -444,7 +470,7 @@ rsv_status launch_axpby(rsv_ctx *c, int64_t n, double a, const double *x, double
 rsv_status launch_mdot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, const double *w, int k0)
 {
     if (K < 1 || K > KMAX) return set_err(c, RSV_ERR_ARG, "mdot K");
-    const int nb = vec_blocks(n);
+    const int nb = mvec_blocks(n);
     rsv_status s = partials_reserve(c, (int64_t)nb * K);
     if (s != RSV_OK) return s;
 #define L_MDOT(KB) hipLaunchKernelGGL(k_mdot<KB>, dim3(nb), dim3(BS), 0, c->stream, n, V, ldv, K, w, c->d_partials)
@@ -460,7 +486,7 @@ rsv_status launch_mdot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int 
 rsv_status launch_upd_dot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0)
 {
     if (K < 1 || K > KMAX) return set_err(c, RSV_ERR_ARG, "upd K");
-    const int nb = vec_blocks(n);
+    const int nb = mvec_blocks(n);
     rsv_status s = partials_reserve(c, (int64_t)nb * K);
     if (s != RSV_OK) return s;
 #define L_UPD(KB) hipLaunchKernelGGL((k_upd<KB, 0>), dim3(nb), dim3(BS), 0, c->stream, n, V, ldv, K, w, c->d_scal + kc, c->d_partials)
@@ -476,7 +502,7 @@ rsv_status launch_upd_dot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, i
 rsv_status launch_upd_norm(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0)
 {
     if (K < 1 || K > KMAX) return set_err(c, RSV_ERR_ARG, "upd K");
-    const int nb = vec_blocks(n);
+    const int nb = mvec_blocks(n);
     rsv_status s = partials_reserve(c, nb);
     if (s != RSV_OK) return s;
 #define L_UPDN(KB) hipLaunchKernelGGL((k_upd<KB, 1>), dim3(nb), dim3(BS), 0, c->stream, n, V, ldv, K, w, c->d_scal + kc, c->d_partials)
