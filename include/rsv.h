@@ -84,7 +84,9 @@ typedef struct rsv_pc_params {
     rsv_net *net;        /* LEARNED: trained network (not owned) */
     const float *lnk;    /* LEARNED: DEVICE pointer, ln k per cell in block-row order (not copied; must outlive the precond) */
     double theta;        /* LEARNED: fallback when a step's residual estimate exceeds theta * previous (default 0.99) */
-    int32_t reserved[8];
+    int32_t learned_mode;/* LEARNED: 0 (default) z = s N(r/s); 1 z = t + s N(r1/s) with t = BILU0^-1 r,
+                          * r1 = r - A t, s = rms(r1): the network corrects what one BILU0 step leaves */
+    int32_t reserved[7];
 } rsv_pc_params;
 
 /* Solver parameters; mirrors SOLVER (rtol, atol, maxit, restart). */

@@ -248,7 +248,8 @@ rsv_status scal_set(rsv_ctx *c, int k0, const double *vals, int n);
 // ------------------------------------------------------------------ preconditioners
 rsv_status bilu0_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
 rsv_status ras_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
-rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out);
+// base: the BILU0 preconditioner a learned_mode 1 network corrects (not owned)
+rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, PcImpl *base);
 // LDS ring depth (slots) of the pipelined BILU0 sweeps for this device
 int64_t sweep_ring_depth(const rsv_ctx *c, int dir, int fp32);
 

@@ -337,7 +337,7 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
         rsv_pc_params fb = *p;
         fb.type = RSV_PC_BILU0;
         s = bilu0_create(A, &fb, &P->fallback, bad_cell);
-        if (s == RSV_OK) s = learned_create(A, p, &P->impl);
+        if (s == RSV_OK) s = learned_create(A, p, &P->impl, P->fallback);
         break;
     }
     default: s = set_err(c, RSV_ERR_ARG, "bad preconditioner type");

@@ -521,9 +521,9 @@ __global__ void k_prep(Geo geo, const double *__restrict__ rtl, const double *__
     }
 }
 
-// z = s * y back to a tile-lane (ztl) or natural (znat) FP64 vector
+// z = s * y (+ add, tile-lane, when given) back to a tile-lane (ztl) or natural (znat) FP64 vector
 __global__ void k_post(Geo geo, const float *__restrict__ y, const double *__restrict__ s2, double *__restrict__ ztl,
-                       double *__restrict__ znat)
+                       double *__restrict__ znat, const double *__restrict__ add = nullptr)
 {
     const int64_t V = (int64_t)geo.nx * geo.ny * geo.nz;
     const double s = sqrt(s2[0] / (double)(3 * V));
@@ -531,7 +531,8 @@ __global__ void k_post(Geo geo, const float *__restrict__ y, const double *__res
         const int i = (int)(v % geo.nx), j = (int)((v / geo.nx) % geo.ny), k = (int)(v / ((int64_t)geo.nx * geo.ny));
         if (ztl) {
             const int64_t sl = slot_of(geo, i, j, k);
-            for (int p = 0; p < 3; ++p) ztl[vidx(sl, p)] = s * (double)y[v * 3 + p];
+            for (int p = 0; p < 3; ++p)
+                ztl[vidx(sl, p)] = (add ? add[vidx(sl, p)] : 0.0) + s * (double)y[v * 3 + p];
         } else {
             const int64_t row = row_of(geo, i, j, k);
             for (int p = 0; p < 3; ++p) znat[3 * row + p] = s * (double)y[v * 3 + p];
@@ -941,23 +942,37 @@ struct Learned : PcImpl {
     rsv_matrix *M = nullptr;
     rsv_net *net = nullptr;
     uint16_t *lnk_std = nullptr;   // this preconditioner's standardised ln k channel
-    ~Learned() override { dev_free(lnk_std); }
-    int64_t bytes() const override { return M->g->ncell * 2; }
+    PcImpl *base = nullptr;        // mode 1: the BILU0 step the network corrects
+    double *t1 = nullptr, *r1 = nullptr;   // mode 1: BILU0^-1 r and r - A t1 (tile-lane)
+    ~Learned() override
+    {
+        dev_free(lnk_std);
+        dev_free(t1);
+        dev_free(r1);
+    }
+    int64_t bytes() const override { return M->g->ncell * 2 + (base ? 2 * M->g->nv * (int64_t)sizeof(double) : 0); }
     rsv_status apply(const double *r, double *z) override
     {
         rsv_grid *g = M->g;
+        rsv_ctx *c = net->c;
         rsv_status s = net_ws(net, g->geo.nx, g->geo.ny, g->geo.nz);
-        if (s == RSV_OK) s = prep(net, g, r, nullptr, lnk_std);
+        const double *in = r;
+        if (s == RSV_OK && base) {
+            s = base->apply(r, t1);
+            if (s == RSV_OK) s = launch_spmv(c, g->geo, M->d_A, SPMV_RESID, t1, r1, r, 0.0, 0.0, SC_MISC);
+            in = r1;
+        }
+        if (s == RSV_OK) s = prep(net, g, in, nullptr, lnk_std);
         if (s == RSV_OK) s = net_forward(net, g->geo.nx, g->geo.ny, g->geo.nz);
         if (s != RSV_OK) return s;
-        hipLaunchKernelGGL(k_post, dim3(nblk(g->ncell)), dim3(256), 0, net->c->stream, g->geo, (const float *)net->y,
-                           (const double *)net->d_sc, z, (double *)nullptr);
-        RSV_LAUNCH(net->c);
+        hipLaunchKernelGGL(k_post, dim3(nblk(g->ncell)), dim3(256), 0, c->stream, g->geo, (const float *)net->y,
+                           (const double *)net->d_sc, z, (double *)nullptr, (const double *)(base ? t1 : nullptr));
+        RSV_LAUNCH(c);
         return RSV_OK;
     }
 };
 
-rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out)
+rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, PcImpl *base)
 {
     rsv_ctx *c = A->g->ctx;
     if (!p->net || !p->lnk) return set_err(c, RSV_ERR_ARG, "learned preconditioner needs net and lnk");
@@ -972,6 +987,18 @@ rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out)
     s = dev_alloc(c, (void **)&L->lnk_std, (size_t)A->g->ncell * 2);
     if (s == RSV_OK) s = set_lnk(n, A->g, p->lnk, L->lnk_std);
     if (s == RSV_OK) s = net_ws(n, A->g->geo.nx, A->g->geo.ny, A->g->geo.nz);
+    if (s == RSV_OK && p->learned_mode == 1) {
+        if (!base) s = set_err(c, RSV_ERR_ARG, "learned mode 1 needs the BILU0 base");
+        L->base = base;
+        if (s == RSV_OK) s = dev_alloc(c, (void **)&L->t1, (size_t)A->g->nv * sizeof(double));
+        if (s == RSV_OK) s = dev_alloc(c, (void **)&L->r1, (size_t)A->g->nv * sizeof(double));
+        // phantom slots of the tile-lane vectors stay zero
+        if (s == RSV_OK && (hipMemsetAsync(L->t1, 0, (size_t)A->g->nv * sizeof(double), c->stream) != hipSuccess ||
+                            hipMemsetAsync(L->r1, 0, (size_t)A->g->nv * sizeof(double), c->stream) != hipSuccess))
+            s = set_err(c, RSV_ERR_HIP, "hipMemsetAsync");
+    } else if (s == RSV_OK && p->learned_mode != 0) {
+        s = set_err(c, RSV_ERR_ARG, "learned_mode must be 0 or 1");
+    }
     if (s != RSV_OK) { delete L; return s; }
     *out = L;
     return RSV_OK;

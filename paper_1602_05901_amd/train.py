@@ -51,8 +51,10 @@ class System:
         self.g.close()
 
 
-def harvest(ctx, sysm: System, every=5, restart=30, tol=1e-8, maxit=5000):
-    """(r_k, e_k) pairs of one system, stacked [P, 3*ncell] on the device."""
+def harvest(ctx, sysm: System, every=5, restart=30, tol=1e-8, maxit=5000, mode=0):
+    """(r_k, e_k) pairs of one system, stacked [P, 3*ncell] on the device.
+    mode 1: the pairs the corrector of one BILU0 step learns from,
+    (r_k - A t_k, e_k - t_k) with t_k = BILU0^-1 r_k."""
     import torch
     M = rsv.Precond(sysm.A, type=rsv.PC_BILU0)
     x = torch.zeros_like(sysm.b)
@@ -66,8 +68,14 @@ def harvest(ctx, sysm: System, every=5, restart=30, tol=1e-8, maxit=5000):
             rsv.solve(sysm.A, M, sysm.b, x, method=rsv.GMRES, restart=restart, tol=0.0, maxit=k)
         r = sysm.b.clone()
         sysm.A.spmv(x, r, alpha=-1.0, beta=1.0)
+        e = sysm.xt - x
+        if mode == 1:
+            t = torch.zeros_like(r)
+            M.apply(r, t)
+            sysm.A.spmv(t, r, alpha=-1.0, beta=1.0)
+            e = e - t
         rs.append(r)
-        es.append(sysm.xt - x)
+        es.append(e)
     M.close()
     return torch.stack(rs), torch.stack(es), K
 
@@ -95,23 +103,28 @@ def train(ctx, net, data, steps, batch=8, lr=1e-3, seed=0, log=None):
     return losses
 
 
-def evaluate(ctx, sysm: System, net=None, restart=30, tol=1e-8):
-    """FGMRES(30)+net (BILU0 fallback) when net is given, else GMRES(30)+BILU0."""
+def evaluate(ctx, sysm: System, net=None, restart=30, tol=1e-8, theta=0.99, none=False, maxit=10000, mode=0):
+    """FGMRES(30)+net (BILU0 fallback when a column does not reduce the residual
+    estimate by theta; theta = inf: the network alone) when net is given;
+    GMRES(30) without a preconditioner when none; else GMRES(30)+BILU0."""
     import torch
-    if net is None:
+    if none:
+        M, method = None, rsv.GMRES
+    elif net is None:
         M = rsv.Precond(sysm.A, type=rsv.PC_BILU0)
         method = rsv.GMRES
     else:
-        M = rsv.Precond(sysm.A, type=rsv.PC_LEARNED, net=net, lnk=sysm.lnk)
+        M = rsv.Precond(sysm.A, type=rsv.PC_LEARNED, net=net, lnk=sysm.lnk, theta=theta, learned_mode=mode)
         method = rsv.FGMRES
     x = torch.zeros_like(sysm.b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = rsv.solve(sysm.A, M, sysm.b, x, method=method, restart=restart, tol=tol, maxit=10000)
+    st = rsv.solve(sysm.A, M, sysm.b, x, method=method, restart=restart, tol=tol, maxit=maxit)
     torch.cuda.synchronize()
     st["solve_s"] = time.perf_counter() - t0
     st["err_vs_xtrue"] = float(torch.linalg.norm(x - sysm.xt) / torch.linalg.norm(sysm.xt))
-    M.close()
+    if M is not None:
+        M.close()
     return st
 
 
@@ -130,7 +143,12 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--net-seed", type=int, default=0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--thetas", default="", help="extra fallback thresholds to evaluate, comma separated")
+    ap.add_argument("--mode", type=int, default=0, help="0: the network maps the residual; 1: it corrects one BILU0 step")
+    ap.add_argument("--maxit-alone", type=int, default=3000,
+                    help="step limit for the network alone and for no preconditioner")
     args = ap.parse_args(argv)
+    args.thetas = [float(t) for t in args.thetas.split(",") if t]
 
     import torch
 
@@ -142,7 +160,7 @@ def main(argv=None):
     data, nits = [], []
     for s in _seeds(args.seeds):
         sy = System(ctx, I.preset(args.workload, seed=s))
-        R, E, K = harvest(ctx, sy)
+        R, E, K = harvest(ctx, sy, mode=args.mode)
         data.append((sy.g, R, E, sy.lnk))
         nits.append(K)
         sy._keep = sy
@@ -162,13 +180,18 @@ def main(argv=None):
     for s in _seeds(args.eval_seeds):
         sy = System(ctx, I.preset(args.workload, seed=s))
         row = {"seed": s}
-        for name, n in (("plain", None), ("learned", net), ("untrained", untrained)):
-            st = evaluate(ctx, sy, n)
-            row[name] = {k: st[k] for k in ("its", "fallbacks", "solve_s", "final_relres", "err_vs_xtrue")}
+        md = args.mode
+        runs = [("plain", dict()), ("learned", dict(net=net, mode=md)), ("untrained", dict(net=untrained, mode=md)),
+                ("learned_only", dict(net=net, theta=float("inf"), maxit=args.maxit_alone, mode=md)),
+                ("no_preconditioner", dict(none=True, maxit=args.maxit_alone))]
+        runs += [(f"learned_theta_{t}", dict(net=net, theta=t, mode=md)) for t in args.thetas]
+        for name, kw in runs:
+            st = evaluate(ctx, sy, **kw)
+            row[name] = {k: st[k] for k in ("its", "fallbacks", "solve_s", "final_relres", "err_vs_xtrue", "status")}
         rows.append(row)
         log(json.dumps(row))
         sy.close()
-    out = {"workload": args.workload, "train_seeds": args.seeds, "pairs": npairs, "harvest_s": t_h,
+    out = {"workload": args.workload, "mode": args.mode, "train_seeds": args.seeds, "pairs": npairs, "harvest_s": t_h,
            "steps": args.steps, "batch": args.batch, "train_s": t_train, "loss_first": losses[0],
            "loss_last": float(np.mean(losses[-20:])), "eval": rows}
     print(json.dumps(out), flush=True)

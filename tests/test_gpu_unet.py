@@ -319,3 +319,34 @@ def test_fgmres_learned_converges_with_fallback(rsv, ctx):
             assert st["its"] == ref0["its"]
         M.close(); net.close()
     A.close(); g.close()
+
+
+def test_learned_mode1_is_bilu0_step_plus_network_correction(rsv, ctx):
+    """learned_mode 1: z = t + s N((r - A t)/s) with t = BILU0^-1 r, checked
+    against the same composition through separate calls (BILU0 apply, SpMV,
+    network forward)."""
+    dims = (16, 16, 8)
+    cfg = I.GenConfig(*dims, I.LNK_IID, 1.0, 0.0, 2.0, 0, 1e3, 1.0, 7)
+    lnk = I.lnk(cfg)
+    g = rsv.Grid(ctx, *dims)
+    A = rsv.Matrix(g, dev(I.blocks(cfg, lnk)))
+    net = rsv.Net(ctx, seed=4)
+    l32 = dev(lnk.astype(np.float32))
+    n = 3 * cfg.ncell
+    r = dev(I.test_vector(8, n))
+    M1 = rsv.Precond(A, type=rsv.PC_LEARNED, net=net, lnk=l32, learned_mode=1)
+    z = torch.zeros_like(r)
+    M1.apply(r, z)
+    B = rsv.Precond(A, type=rsv.PC_BILU0)
+    t = torch.zeros_like(r)
+    B.apply(r, t)
+    r1 = r.clone()
+    A.spmv(t, r1, alpha=-1.0, beta=1.0)
+    z1 = torch.zeros_like(r)
+    net.forward(g, r1, l32, z1)
+    corr = (z - t).cpu().numpy()
+    assert rel(corr, z1.cpu().numpy()) <= 1e-2
+    assert rel(z.cpu().numpy(), (t + z1).cpu().numpy()) <= 1e-3
+    with pytest.raises(rsv.RsvError):
+        rsv.Precond(A, type=rsv.PC_LEARNED, net=net, lnk=l32, learned_mode=2)
+    M1.close(); B.close(); A.close(); g.close(); net.close()
