@@ -92,6 +92,14 @@ def main():
     ctx = rsv.Context(0)
     g = rsv.Grid(ctx, cfg.nx, cfg.ny, cfg.nz)
     A = rsv.Matrix(g, Bd)
+    # the host-buffer path of the boundary (blocks in host memory, copied over
+    # PCIe and laid out by the library): timed once, never part of `value`
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    Ah = rsv.Matrix(g, B)
+    torch.cuda.synchronize()
+    host_assemble_s = time.perf_counter() - th
+    Ah.close()
     b = torch.zeros_like(xtd)
     A.spmv(xtd, b)          # manufactured right-hand side, on the GPU
     torch.cuda.synchronize()
@@ -258,6 +266,8 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "assemble_from_host_s": round(host_assemble_s, 4),
+        "assemble_from_host_GBps": round(B.nbytes / host_assemble_s / 1e9, 2),
         "device_bytes": A.device_bytes,
         "hbm_used_bytes": int(hbm_peak[0]),
         "hbm_total_bytes": int(torch.cuda.mem_get_info()[1]),
