@@ -216,7 +216,13 @@ __global__ __launch_bounds__(BS) void k_axpby(int64_t n, double a, const double 
 
 constexpr int KMAX = 64;   // max vectors in a multi-dot (GMRES restart <= 60)
 
-// partial dots V_i . w for i < K (+ w.w when ww)
+// The multi-vector kernels load all KB vectors of an element unconditionally,
+// vector index clamped to K-1 (in bounds; the extra terms are multiplied by a
+// zero coefficient or their sums are discarded), so the loads are issued back
+// to back instead of one branch -- and one memory round trip -- per vector.
+__device__ __forceinline__ int64_t vrow(int i, int K, int64_t ldv) { return (int64_t)(i < K ? i : K - 1) * ldv; }
+
+// partial dots V_i . w for i < K
 template <int KB>
 __global__ __launch_bounds__(BS) void k_mdot(int64_t n, const double *__restrict__ V, int64_t ldv, int K,
                                              const double *__restrict__ w, double *__restrict__ partials)
@@ -226,10 +232,12 @@ __global__ __launch_bounds__(BS) void k_mdot(int64_t n, const double *__restrict
 #pragma unroll
     for (int i = 0; i < KB; ++i) acc[i] = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
+        double v[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) v[i] = V[vrow(i, K, ldv) + e];
         const double we = w[e];
 #pragma unroll
-        for (int i = 0; i < KB; ++i)
-            if (i < K) acc[i] += V[i * ldv + e] * we;
+        for (int i = 0; i < KB; ++i) acc[i] += v[i] * we;
     }
     block_sums<KB>(acc, K, red, partials + (int64_t)blockIdx.x * K);
 }
@@ -249,18 +257,15 @@ __global__ __launch_bounds__(BS) void k_upd(int64_t n, const double *__restrict_
     for (int i = 0; i < (MODE == 0 ? KB : 1); ++i) acc[i] = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
         double v[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) v[i] = V[vrow(i, K, ldv) + e];
         double we = w[e];
 #pragma unroll
-        for (int i = 0; i < KB; ++i)
-            if (i < K) {
-                v[i] = V[i * ldv + e];
-                we -= coef[i] * v[i];
-            }
+        for (int i = 0; i < KB; ++i) we -= coef[i] * v[i];
         w[e] = we;
         if (MODE == 0) {
 #pragma unroll
-            for (int i = 0; i < KB; ++i)
-                if (i < K) acc[i] += v[i] * we;
+            for (int i = 0; i < KB; ++i) acc[i] += v[i] * we;
         } else {
             acc[0] += we * we;
         }
@@ -277,10 +282,12 @@ __global__ __launch_bounds__(BS) void k_combine(int64_t n, const double *__restr
 #pragma unroll
     for (int i = 0; i < KB; ++i) coef[i] = (i < K) ? y[i] : 0.0;
     for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
+        double v[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) v[i] = V[vrow(i, K, ldv) + e];
         double s = accumulate ? u[e] : 0.0;
 #pragma unroll
-        for (int i = 0; i < KB; ++i)
-            if (i < K) s += coef[i] * V[i * ldv + e];
+        for (int i = 0; i < KB; ++i) s += coef[i] * v[i];
         u[e] = s;
     }
 }
@@ -464,8 +471,9 @@ rsv_status launch_axpby(rsv_ctx *c, int64_t n, double a, const double *x, double
 }
 
 #define KB_DISPATCH(K, MACRO) \
-    if ((K) <= 4) { MACRO(4); } else if ((K) <= 8) { MACRO(8); } else if ((K) <= 16) { MACRO(16); } \
-    else if ((K) <= 32) { MACRO(32); } else { MACRO(64); }
+    if ((K) <= 8) { MACRO(8); } else if ((K) <= 16) { MACRO(16); } else if ((K) <= 24) { MACRO(24); } \
+    else if ((K) <= 32) { MACRO(32); } else if ((K) <= 40) { MACRO(40); } else if ((K) <= 48) { MACRO(48); } \
+    else if ((K) <= 56) { MACRO(56); } else { MACRO(64); }
 
 rsv_status launch_mdot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, const double *w, int k0)
 {
