@@ -84,55 +84,128 @@ __global__ __launch_bounds__(RB) void k_ras_factor(RasDev R, const double *__res
     }
 }
 
+// Local vectors yl, zl are [3][n + 1]: entry n of each component is a
+// permanent zero, the value of an absent neighbour.  Every load of a cell is
+// issued unconditionally (absent neighbours read the zero entry; their factor
+// blocks are zero), and the neighbour indices of a thread's first cell in the
+// next plane are fetched during the current plane, so after each barrier a
+// plane costs one memory round trip (the neighbour values, with the factor
+// blocks and r loaded alongside) instead of one per branch.
+template <typename T, int DIR>
+struct RasCell {
+    int64_t c, slot, m[3];
+    __device__ void fetch(const RasDev &R, int64_t cc)
+    {
+        c = cc;
+        slot = R.slot[cc];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int32_t mq = R.nb[(DIR == 0 ? q : 3 + q) * R.n + cc];
+            m[q] = mq >= 0 ? mq : R.n;
+        }
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void ras_fwd_cell(const RasCell<T, 0> &C, int64_t n, int64_t n1, const T *__restrict__ Lf,
+                                             const double *__restrict__ r, T *__restrict__ yl)
+{
+    T l[27], rr[3], y[3][3];
+#pragma unroll
+    for (int e = 0; e < 27; ++e) l[e] = Lf[e * n + C.c];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) rr[a] = (T)r[vidx(C.slot, a)];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) y[q][b] = yl[b * n1 + C.m[q]];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            acc += l[q * 9 + 3 * a] * y[q][0] + l[q * 9 + 3 * a + 1] * y[q][1] + l[q * 9 + 3 * a + 2] * y[q][2];
+        yl[a * n1 + C.c] = rr[a] - acc;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void ras_bwd_cell(const RasCell<T, 1> &C, const RasDev &R, int64_t n1, const T *__restrict__ U,
+                                             const T *__restrict__ Dinv, const T *__restrict__ yl, T *__restrict__ zl,
+                                             double *__restrict__ z)
+{
+    const int64_t n = R.n;
+    T u[27], dd[9], yy[3], zz[3][3];
+#pragma unroll
+    for (int e = 0; e < 27; ++e) u[e] = U[e * n + C.c];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) dd[e] = Dinv[e * n + C.c];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) yy[a] = yl[a * n1 + C.c];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) zz[q][b] = zl[b * n1 + C.m[q]];
+    T tv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            acc += u[q * 9 + 3 * a] * zz[q][0] + u[q * 9 + 3 * a + 1] * zz[q][1] + u[q * 9 + 3 * a + 2] * zz[q][2];
+        tv[a] = yy[a] - acc;
+    }
+    T out[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = dd[3 * a] * tv[0] + dd[3 * a + 1] * tv[1] + dd[3 * a + 2] * tv[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) zl[a * n1 + C.c] = out[a];
+    if (R.owned[C.c])
+#pragma unroll
+        for (int a = 0; a < 3; ++a) z[vidx(C.slot, a)] = (double)out[a];
+}
+
 template <typename T>
 __global__ __launch_bounds__(RB) void k_ras_apply(RasDev R, const T *__restrict__ Lf, const T *__restrict__ Dinv,
                                                   const T *__restrict__ U, const double *__restrict__ r,
                                                   T *__restrict__ yl, T *__restrict__ zl, double *__restrict__ z)
 {
     const int s = blockIdx.x;
-    const int64_t n = R.n;
+    const int64_t n = R.n, n1 = n + 1;
     const int np = R.sub_np[s];
     const int64_t *pp = R.pp + R.sub_pp0[s];
-    for (int p = 0; p < np; ++p) {
-        for (int64_t c = pp[p] + threadIdx.x; c < pp[p + 1]; c += RB) {
-            const int64_t slot = R.slot[c];
-            T acc[3] = {0, 0, 0};
-            for (int q = 0; q < 3; ++q) {
-                const int32_t m = R.nb[q * n + c];
-                if (m >= 0) {
-                    const T y0 = yl[m], y1 = yl[n + m], y2 = yl[2 * n + m];
-                    for (int a = 0; a < 3; ++a)
-                        acc[a] += Lf[(q * 9 + 3 * a) * n + c] * y0 + Lf[(q * 9 + 3 * a + 1) * n + c] * y1 +
-                                  Lf[(q * 9 + 3 * a + 2) * n + c] * y2;
-                }
+    const int tid = threadIdx.x;
+    {
+        RasCell<T, 0> nxt{};
+        if (pp[0] + tid < pp[1]) nxt.fetch(R, pp[0] + tid);
+        for (int p = 0; p < np; ++p) {
+            const int64_t c0 = pp[p] + tid, end = pp[p + 1];
+            const RasCell<T, 0> cur = nxt;
+            if (p + 1 < np && pp[p + 1] + tid < pp[p + 2]) nxt.fetch(R, pp[p + 1] + tid);
+            if (c0 < end) ras_fwd_cell<T>(cur, n, n1, Lf, r, yl);
+            for (int64_t c = c0 + RB; c < end; c += RB) {
+                RasCell<T, 0> C;
+                C.fetch(R, c);
+                ras_fwd_cell<T>(C, n, n1, Lf, r, yl);
             }
-            for (int a = 0; a < 3; ++a) yl[a * n + c] = (T)r[vidx(slot, a)] - acc[a];
+            __syncthreads();
         }
-        __syncthreads();
     }
-    for (int p = np - 1; p >= 0; --p) {
-        for (int64_t c = pp[p] + threadIdx.x; c < pp[p + 1]; c += RB) {
-            const int64_t slot = R.slot[c];
-            T acc[3] = {0, 0, 0};
-            for (int q = 0; q < 3; ++q) {
-                const int32_t m = R.nb[(3 + q) * n + c];
-                if (m >= 0) {
-                    const T z0 = zl[m], z1 = zl[n + m], z2 = zl[2 * n + m];
-                    for (int a = 0; a < 3; ++a)
-                        acc[a] += U[(q * 9 + 3 * a) * n + c] * z0 + U[(q * 9 + 3 * a + 1) * n + c] * z1 +
-                                  U[(q * 9 + 3 * a + 2) * n + c] * z2;
-                }
+    {
+        RasCell<T, 1> nxt{};
+        if (np > 0 && pp[np - 1] + tid < pp[np]) nxt.fetch(R, pp[np - 1] + tid);
+        for (int p = np - 1; p >= 0; --p) {
+            const int64_t c0 = pp[p] + tid, end = pp[p + 1];
+            const RasCell<T, 1> cur = nxt;
+            if (p > 0 && pp[p - 1] + tid < pp[p]) nxt.fetch(R, pp[p - 1] + tid);
+            if (c0 < end) ras_bwd_cell<T>(cur, R, n1, U, Dinv, yl, zl, z);
+            for (int64_t c = c0 + RB; c < end; c += RB) {
+                RasCell<T, 1> C;
+                C.fetch(R, c);
+                ras_bwd_cell<T>(C, R, n1, U, Dinv, yl, zl, z);
             }
-            T tv[3];
-            for (int a = 0; a < 3; ++a) tv[a] = yl[a * n + c] - acc[a];
-            T out[3];
-            for (int a = 0; a < 3; ++a)
-                out[a] = Dinv[(3 * a) * n + c] * tv[0] + Dinv[(3 * a + 1) * n + c] * tv[1] + Dinv[(3 * a + 2) * n + c] * tv[2];
-            for (int a = 0; a < 3; ++a) zl[a * n + c] = out[a];
-            if (R.owned[c])
-                for (int a = 0; a < 3; ++a) z[vidx(slot, a)] = (double)out[a];
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -325,8 +398,8 @@ struct Ras : PcImpl {
             st = alloc((void **)&Lf32, (size_t)n * 27 * sizeof(float));
             if (st == RSV_OK) st = alloc((void **)&Dinv32, (size_t)n * 9 * sizeof(float));
             if (st == RSV_OK) st = alloc((void **)&U32, (size_t)n * 27 * sizeof(float));
-            if (st == RSV_OK) st = alloc(&yl, (size_t)n * 3 * sizeof(float));
-            if (st == RSV_OK) st = alloc(&zl, (size_t)n * 3 * sizeof(float));
+            if (st == RSV_OK) st = alloc(&yl, (size_t)(n + 1) * 3 * sizeof(float));
+            if (st == RSV_OK) st = alloc(&zl, (size_t)(n + 1) * 3 * sizeof(float));
             if (st != RSV_OK) return st;
             hipLaunchKernelGGL(k_cvt, dim3(2048), dim3(256), 0, c->stream, n * 27, Lf, Lf32);
             hipLaunchKernelGGL(k_cvt, dim3(2048), dim3(256), 0, c->stream, n * 9, Dinv, Dinv32);
@@ -338,10 +411,13 @@ struct Ras : PcImpl {
             dev_free(U); U = nullptr;
             nbytes -= n * 63 * (int64_t)sizeof(double);
         } else {
-            st = alloc(&yl, (size_t)n * 3 * sizeof(double));
-            if (st == RSV_OK) st = alloc(&zl, (size_t)n * 3 * sizeof(double));
+            st = alloc(&yl, (size_t)(n + 1) * 3 * sizeof(double));
+            if (st == RSV_OK) st = alloc(&zl, (size_t)(n + 1) * 3 * sizeof(double));
             if (st != RSV_OK) return st;
         }
+        // the zero entries (index n of each component) of the local vectors
+        RSV_HIP(c, hipMemsetAsync(yl, 0, (size_t)(n + 1) * 3 * (fp32 ? sizeof(float) : sizeof(double)), c->stream));
+        RSV_HIP(c, hipMemsetAsync(zl, 0, (size_t)(n + 1) * 3 * (fp32 ? sizeof(float) : sizeof(double)), c->stream));
         RSV_HIP(c, hipStreamSynchronize(c->stream));
         return RSV_OK;
     }
