@@ -110,31 +110,19 @@ __global__ __launch_bounds__(BS) void k_spmv(Geo g, const double *__restrict__ A
     }
 }
 
-// final stage over the nb block partials ([nb][K]), fixed order.  Few outputs
-// (K <= 8): the whole block per output (two barriers each); many outputs:
-// wave w takes kk = w, w + 16, ..., lane-strided loads then a butterfly, no
-// barriers.
+// final stage over the nb block partials ([nb][K]), fixed order: one
+// workgroup per output, thread t sums partials t, t + RED_T, ... (loads
+// issued eight at a time), then the block sum.
 __global__ __launch_bounds__(RED_T) void k_reduce(const double *__restrict__ partials, int nb, int K,
                                                  double *__restrict__ out)
 {
-    if (K <= 8) {
-        __shared__ double lds[16];
-        for (int kk = 0; kk < K; ++kk) {
-            double s = 0.0;
-            for (int b = threadIdx.x; b < nb; b += RED_T) s += partials[(int64_t)b * K + kk];
-            s = block_sum(s, lds);
-            if (threadIdx.x == 0) out[kk] = s;
-        }
-        return;
-    }
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int kk = w; kk < K; kk += RED_T / 64) {
-        double s = 0.0;
+    __shared__ double lds[RED_T / 64];
+    const int kk = blockIdx.x;
+    double s = 0.0;
 #pragma unroll 8
-        for (int b = lane; b < nb; b += 64) s += partials[(int64_t)b * K + kk];
-        s = wave_sum(s);
-        if (lane == 0) out[kk] = s;
-    }
+    for (int b = threadIdx.x; b < nb; b += RED_T) s += partials[(int64_t)b * K + kk];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) out[kk] = s;
 }
 
 __global__ __launch_bounds__(BS) void k_nat_to_tl(Geo g, const double *__restrict__ nat, double *__restrict__ tl)
@@ -389,7 +377,8 @@ int mvec_blocks(int64_t n)
 
 rsv_status launch_reduce(rsv_ctx *c, int nblocks, int K, int k0)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_T), 0, c->stream, c->d_partials, nblocks, K, c->d_scal + k0);
+    if (K <= 0) return RSV_OK;
+    hipLaunchKernelGGL(k_reduce, dim3(K), dim3(RED_T), 0, c->stream, c->d_partials, nblocks, K, c->d_scal + k0);
     RSV_LAUNCH(c);
     return RSV_OK;
 }
