@@ -7,8 +7,9 @@ Workload (default C2): 128x128x64 cells (3,145,728 unknowns), layered
 log-normal permeability (layer mean ~ N(0,1.5), cell noise ~ N(0,2)), four
 source cells, b = A x_true, x0 = 0, tol 1e-8 on the recomputed FP64 relative
 residual.  One step = assemble the block matrix, then for each solver form:
-preconditioner setup + solve.  Forms: BiCGSTAB + BILU0 (the headline
-time-to-solve), GMRES(30) + RAS(4x4x4 subdomains, overlap 1, ILU(0)),
+preconditioner setup + solve.  Forms: GMRES(30) + RAS(4x4x4 subdomains,
+overlap 1, ILU(0) local solves: the paper's own solver configuration, the
+headline time-to-solve), BiCGSTAB + BILU0,
 GMRES(30) + BILU0 with FP64 factors, GMRES(30) + BILU0 with FP32 factors,
 and FGMRES(30) + the learned U-Net preconditioner (BILU0 fallback), whose
 network is trained first on C4-shaped systems (64x64x32, disjoint seeds;
@@ -48,6 +49,34 @@ def algorithmic_bytes(nx, ny, nz):
     }
 
 
+def ras_algorithmic_bytes(nx, ny, nz, parts, ov):
+    """Bytes of the local sweeps of RAS per launch: the stored blocks of every
+    local matrix (couplings inside Omega_s) and the vector passes over every
+    Omega_s cell, summed over the subdomains (padding of the boxes excluded)."""
+    import numpy as np
+
+    def starts(n, p):
+        base, rem = divmod(n, p)
+        return [b * base + min(b, rem) for b in range(p + 1)]
+
+    xs, ys, zs = starts(nx, parts[0]), starts(ny, parts[1]), starts(nz, parts[2])
+    c = nl = 0
+    for sz in range(parts[2]):
+        for sy in range(parts[1]):
+            for sx in range(parts[0]):
+                lo = [max(0, v - ov) for v in (xs[sx], ys[sy], zs[sz])]
+                hi = [min(n, v + ov) for n, v in zip((nx, ny, nz), (xs[sx + 1], ys[sy + 1], zs[sz + 1]))]
+                ax = [np.arange(a, b) for a, b in zip(lo, hi)]
+                d = [np.maximum(0, np.maximum(core0 - a, a - (core1 - 1)))
+                     for a, core0, core1 in zip(ax, (xs[sx], ys[sy], zs[sz]), (xs[sx + 1], ys[sy + 1], zs[sz + 1]))]
+                inside = (d[0][:, None, None] + d[1][None, :, None] + d[2][None, None, :]) <= ov
+                c += int(inside.sum())
+                nl += int((inside[1:] & inside[:-1]).sum() + (inside[:, 1:] & inside[:, :-1]).sum()
+                          + (inside[:, :, 1:] & inside[:, :, :-1]).sum())
+    N = 3 * c
+    return {"ilu_fwd": 72 * nl + 16 * N, "ilu_bwd": 72 * (nl + c) + 16 * N, "cells": c, "pairs": nl}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -60,7 +89,7 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="bicgstab_bilu0,gmres_ras64,gmres_bilu0,gmres_bilu0_fp32")
+    ap.add_argument("--forms", default="gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32")
     ap.add_argument("--net", default=None, help="trained U-Net weights for the learned form")
     ap.add_argument("--learned-steps", type=int, default=1500,
                     help="without --net: Adam steps of training on C4 systems before the timed steps (0: no learned form)")
@@ -156,19 +185,20 @@ def main():
         out["assemble_s"] = time.perf_counter() - ta
         for name in forms:
             method, pkw = forms_all[name]
-            prof = profile_headline and name == forms[0]
+            prof = profile_headline and (name == forms[0] or name == "bicgstab_bilu0")
             t1 = time.perf_counter()
             M = rsv.Precond(A, **pkw)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             x = torch.zeros_like(b)
             if prof:
-                ctx.profile(True)
+                # two events per recorded launch: only the classes the roofline needs
+                ctx.profile(True, classes=("spmv", "ilu_fwd", "ilu_bwd"))
             st = rsv.solve(A, M, b, x, method=method, restart=30, tol=1e-8, maxit=10000)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             if prof:
-                out["kernels"] = ctx.profile_read()
+                out["kernels_" + name] = ctx.profile_read()
                 ctx.profile(False)
             free_b, total_b = torch.cuda.mem_get_info()
             hbm_peak[0] = max(hbm_peak[0], total_b - free_b)
@@ -199,30 +229,52 @@ def main():
     summary = {f: {"solve_s": med(f, "solve_s"), "setup_s": med(f, "setup_s"), "its": res[-1][f]["its"],
                    "relres": res[-1][f]["relres"], "err_vs_xtrue": res[-1][f]["err_vs_xtrue"],
                    "fallbacks": res[-1][f]["fallbacks"]} for f in forms}
-    # live kernel timing (HIP events on the solver stream) over the headline solves
-    kms = {k: sum(r["kernels"][k][0] for r in res) for k in rsv.K_NAMES}
-    kcnt = {k: sum(r["kernels"][k][1] for r in res) for k in rsv.K_NAMES}
-    ab = algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz)
+    # live kernel timing (HIP events on the solver stream), per profiled form
+    ab_global = algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz)
+    ab_ras = None
+
+    def kernel_table(form):
+        nonlocal ab_ras
+        kms = {k: sum(r["kernels_" + form][k][0] for r in res) for k in rsv.K_NAMES}
+        kcnt = {k: sum(r["kernels_" + form][k][1] for r in res) for k in rsv.K_NAMES}
+        ab = dict(ab_global)
+        if forms_all[form][1].get("type") == rsv.PC_RAS:
+            # the sweeps of this form are the local RAS sweeps
+            pk = forms_all[form][1]
+            ab_ras = ras_algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz, (pk["ras_px"], pk["ras_py"], pk["ras_pz"]),
+                                           pk["ras_overlap"])
+            ab["ilu_fwd"], ab["ilu_bwd"] = ab_ras["ilu_fwd"], ab_ras["ilu_bwd"]
+        tab = {k: {"avg_us": 1e3 * kms[k] / kcnt[k], "launches": kcnt[k],
+                   "GBps": (ab[k] / (kms[k] / kcnt[k] * 1e-3) / 1e9) if k in ab and k != "ilu_apply" else None}
+               for k in rsv.K_NAMES if kcnt[k] > 0}
+        return kms, kcnt, ab, tab
+
+    kms, kcnt, ab, kernels_head = kernel_table(head)
     cand = [k for k in ("spmv", "ilu_fwd", "ilu_bwd") if kcnt[k] > 0]
     dom = max(cand, key=lambda k: kms[k])
     avg_ms = kms[dom] / kcnt[dom]
     achieved = ab[dom] / (avg_ms * 1e-3) / 1e9
-    kernels = {k: {"avg_us": 1e3 * kms[k] / kcnt[k], "launches": kcnt[k],
-                   "GBps": (ab[k] / (kms[k] / kcnt[k] * 1e-3) / 1e9) if k in ab else None}
-               for k in rsv.K_NAMES if kcnt[k] > 0}
-    ilu_ms = (kms["ilu_fwd"] + kms["ilu_bwd"]) / max(kcnt["ilu_fwd"], 1)
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
         try:
             tj = json.load(open(tpath))
-            if tj.get("workload") == args.workload and dom in tj.get("kernels", {}):
-                traffic = tj["kernels"][dom]["bytes_per_launch"]
+            if tj.get("workload") == args.workload:
+                traffic = tj["forms"][head]["kernels"][dom]["bytes_per_launch"]
         except Exception:  # noqa: BLE001
             traffic = None
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+    roofline = {"bound": "hbm", "kernel": dom, "form": head, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": ab[dom], "avg_launch_us": round(avg_ms * 1e3, 2)}
+    # the global BILU0 and SpMV kernels, from the BiCGSTAB + BILU0 solves
+    kernels = None
+    ilu_GBps = spmv_GBps = None
+    if "bicgstab_bilu0" in forms:
+        bk_ms, bk_cnt, bab, kernels = kernel_table("bicgstab_bilu0")
+        if bk_cnt["ilu_fwd"]:
+            ilu_ms = (bk_ms["ilu_fwd"] + bk_ms["ilu_bwd"]) / bk_cnt["ilu_fwd"]
+            ilu_GBps = round(bab["ilu_apply"] / (ilu_ms * 1e-3) / 1e9, 1)
+        spmv_GBps = kernels.get("spmv", {}).get("GBps")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -232,11 +284,19 @@ def main():
         Ao = O.BCSR.from_stencil(cfg.nx, cfg.ny, cfg.nz, B)
         bo = Ao.spmv(xt)
         t1 = time.perf_counter()
-        F = O.ILU(Ao)
-        ro = O.bicgstab(Ao, bo, pc=F, tol=1e-8, maxit=10000)
+        method, pk = forms_all[head]
+        if pk.get("type") == rsv.PC_RAS:
+            F = O.RAS(Ao, (cfg.nx, cfg.ny, cfg.nz), (pk["ras_px"], pk["ras_py"], pk["ras_pz"]), pk["ras_overlap"])
+            ro = O.gmres(Ao, bo, pc=F, m=30, tol=1e-8, maxit=10000)
+            what = "GMRES(30)+RAS(%dx%dx%d, overlap %d) solve (RAS setup" % (pk["ras_px"], pk["ras_py"], pk["ras_pz"],
+                                                                          pk["ras_overlap"])
+        else:
+            F = O.ILU(Ao)
+            ro = O.bicgstab(Ao, bo, pc=F, tol=1e-8, maxit=10000)
+            what = "BiCGSTAB+BILU0 solve (ILU(0) setup"
         t2 = time.perf_counter()
         cpu = {"value": round(t2 - t1, 3), "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": f"full {args.workload} BiCGSTAB+BILU0 solve (ILU(0) setup + {ro['its']} iterations, "
+               "sample": f"full {args.workload} {what} + {ro['its']} iterations, "
                          f"relres {ro['relres']:.2e}), serial FP64 C on one host thread"}
         log(f"oracle: {t2 - t1:.2f}s ({ro['its']} its)")
 
@@ -261,9 +321,11 @@ def main():
         "vs_plain_gmres_bilu0": ({f: round(summary[f]["solve_s"] / summary["gmres_bilu0"]["solve_s"], 3) for f in forms}
                                  if "gmres_bilu0" in summary else None),
         "learned_training": training,
-        "ilu_apply_GBps": round(ab["ilu_apply"] / (ilu_ms * 1e-3) / 1e9, 1) if kcnt["ilu_fwd"] else None,
-        "spmv_GBps": kernels.get("spmv", {}).get("GBps"),
+        "ilu_apply_GBps": ilu_GBps,
+        "spmv_GBps": spmv_GBps,
         "kernels": kernels,
+        "kernels_headline": kernels_head,
+        "ras_local": ab_ras,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "assemble_from_host_s": round(host_assemble_s, 4),

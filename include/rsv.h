@@ -80,7 +80,9 @@ typedef struct rsv_pc_params {
     int32_t ras_px, ras_py, ras_pz;  /* RAS: subdomain boxes per axis (default 4,4,4) */
     int32_t ras_overlap; /* RAS: matrix-graph overlap distance (default 1) */
     int32_t iluk_level;  /* must be 0 (ILU(0)); kept to mirror RAS_PARS */
-    int32_t pipelined;   /* 1 (default): sync-free tiled wavefront sweeps; 0: one launch per hyperplane */
+    int32_t pipelined;   /* 1 (default): sync-free tiled wavefront sweeps (RAS: every subdomain's local
+                          * system in one auxiliary grid of boxes, swept together); 0: BILU0 one launch
+                          * per hyperplane, RAS one workgroup per subdomain (reference mappings) */
     rsv_net *net;        /* LEARNED: trained network (not owned) */
     const float *lnk;    /* LEARNED: DEVICE pointer, ln k per cell in block-row order (not copied; must outlive the precond) */
     double theta;        /* LEARNED: fallback when a step's residual estimate exceeds theta * previous (default 0.99) */
@@ -270,6 +272,10 @@ enum {
 };
 /* on = 1 starts (and zeroes) the per-class totals, on = 0 stops recording. */
 rsv_status rsv_profile_enable(rsv_ctx *ctx, int32_t on);
+/* Classes recorded while profiling is on: bit k set records class k (default
+ * all).  Each recorded launch adds two events to the stream, so a caller that
+ * times whole solves while profiling records only the classes it needs. */
+rsv_status rsv_profile_classes(rsv_ctx *ctx, uint32_t mask);
 /* Synchronises the stream and writes per-class total milliseconds and launch
  * counts (HOST arrays of RSV_K_COUNT entries; either may be NULL). */
 rsv_status rsv_profile_read(rsv_ctx *ctx, double *ms, int64_t *launches);

@@ -72,7 +72,7 @@ static void prof_resolve(rsv_ctx *c)
 
 int prof_begin(rsv_ctx *c, int kind)
 {
-    if (!c->prof_on) return -1;
+    if (!c->prof_on || !((c->prof_mask >> kind) & 1u)) return -1;
     if (c->prof_used + 2 > (int)c->prof_ev.size()) prof_resolve(c);
     const int tok = c->prof_used;
     c->prof_used += 2;
@@ -105,6 +105,13 @@ rsv_status rsv_profile_enable(rsv_ctx *c, int32_t on)
         prof_resolve(c);
         c->prof_on = false;
     }
+    return RSV_OK;
+}
+
+rsv_status rsv_profile_classes(rsv_ctx *c, uint32_t mask)
+{
+    if (!c) return set_err(nullptr, RSV_ERR_ARG, "ctx is NULL");
+    c->prof_mask = mask;
     return RSV_OK;
 }
 

@@ -279,6 +279,8 @@ struct SweepArgs {
     int32_t *flags;
     uint64_t wait_limit;         // wall-clock ticks a wait may last
     int D;                       // LDS ring slots
+    int btx, bty;                // tiles per box in x and y: faces are exchanged only between
+                                 // tiles of one box (the whole grid is one box for BILU0)
     uint64_t *trace;             // optional: per tile [start, step 8 reached, end, steps that waited for data]
 };
 
@@ -288,6 +290,9 @@ struct SweepSrc {
     const T *p0; int64_t s0, o0;                  // factor blocks (27): L (fwd) or U (bwd)
     const T *p1; int64_t s1, o1;                  // D^{-1} (bwd only, 9)
     const double *v64; const T *vT;               // 3-vector input: r (FP64, fwd) or y (T, bwd)
+    const int32_t *zmap;                          // bwd, optional: slot of the output vector that takes
+                                                  // each cell's result ([slot], -1: no store); null:
+                                                  // the output has this grid's layout
 };
 
 // NLOAD loader waves per workgroup (each keeps two steps in flight)
@@ -302,7 +307,8 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
     const int nz = g.nz, NT = g.ntx * g.nty, nsteps = nz + 14;
     const int D = a.D;
     constexpr int NE = DIR == 0 ? 30 : 39;       // T entries per lane per step (27 blocks [+9 D^-1] + 3 vector)
-    constexpr int slot_elems = NE * 64 + 48;     // + x and y faces (8 entries x 3 components each)
+    constexpr int NS = DIR == 0 ? NE : NE + 1;   // + the output map entry (bwd)
+    constexpr int slot_elems = NS * 64 + 48;     // + x and y faces (8 entries x 3 components each)
     T *ring = (T *)smem;
     int32_t *tags = (int32_t *)(smem + (size_t)D * slot_elems * sizeof(T));
     int32_t *consumed = tags + D;
@@ -329,8 +335,9 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
         if (T_ < 0) break;
         const int tx = T_ % g.ntx, ty = T_ / g.ntx;
         const int64_t rowbase = (int64_t)T_ * nz;
-        const bool hasx = DIR == 0 ? tx > 0 : tx < g.ntx - 1;
-        const bool hasy = DIR == 0 ? ty > 0 : ty < g.nty - 1;
+        const int bx = tx % a.btx, by = ty % a.bty;   // tile position inside its box
+        const bool hasx = DIR == 0 ? bx > 0 : bx < a.btx - 1;
+        const bool hasy = DIR == 0 ? by > 0 : by < a.bty - 1;
         if (wave > 0) {
             // ------------------------------------------------ loader waves
             const uint64_t *xin = a.faceX + (int64_t)(DIR == 0 ? T_ - 1 : T_ + 1) * frow;
@@ -340,6 +347,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             constexpr int nv = DIR == 0 ? 27 : 36;
             struct Regs {
                 T v[nv + 3];
+                int32_t zm;        // output map entry (bwd with a map)
                 uint64_t wx, wy;   // face words of the same step
             };
             // face words: always two loads per lane (a tile without that neighbour
@@ -382,6 +390,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     const T *q2 = src.vT + rb * 192 + Ls;
 #pragma unroll
                     for (int p = 0; p < 3; ++p) R.v[nv + p] = q2[p * 64];
+                    R.zm = src.zmap ? src.zmap[rb * 64 + Ls] : -1;
                 }
                 // face words of the same step, issued with its data (they may still
                 // be stale when the step is delivered; then they are polled again)
@@ -411,6 +420,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
                 for (int e = 0; e < nv + 3; ++e) sl[e * 64 + L] = R.v[e];
+                if constexpr (DIR == 1) ((int32_t *)(sl + NE * 64))[L] = R.zm;
                 // operands first (the compute wave prefetches them while faces are pending)
                 __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -453,7 +463,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 }
                 // the low 32 bits of word q are 32-bit half q of the row's values
                 // (zero when the tile has no such neighbour: the value of an absent cell)
-                uint32_t *fs = (uint32_t *)(sl + NE * 64);
+                uint32_t *fs = (uint32_t *)(sl + NS * 64);
                 if (L < RW) {
                     fs[fdst] = hasx ? (uint32_t)wx : 0u;
                     fs[RW + fdst] = hasy ? (uint32_t)wy : 0u;
@@ -482,8 +492,8 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             const int lx = DIR == 0 ? (li > 0 ? ij_lane(li - 1, lj) : L) : (li < 7 ? ij_lane(li + 1, lj) : L);
             const int ly = DIR == 0 ? (lj > 0 ? ij_lane(li, lj - 1) : L) : (lj < 7 ? ij_lane(li, lj + 1) : L);
             const bool cx = DIR == 0 ? li == 0 : li == 7, cy = DIR == 0 ? lj == 0 : lj == 7;
-            const bool px = DIR == 0 ? (li == 7 && tx < g.ntx - 1) : (li == 0 && tx > 0);
-            const bool py = DIR == 0 ? (lj == 7 && ty < g.nty - 1) : (lj == 0 && ty > 0);
+            const bool px = DIR == 0 ? (li == 7 && bx < a.btx - 1) : (li == 0 && bx > 0);
+            const bool py = DIR == 0 ? (lj == 7 && by < a.bty - 1) : (lj == 0 && by > 0);
             uint64_t *fxo = a.faceX + (int64_t)T_ * frow;
             uint64_t *fyo = a.faceY + (int64_t)T_ * frow;
             uint32_t waited = 0;
@@ -496,8 +506,8 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             const uint32_t slot_bytes = (uint32_t)slot_elems * sizeof(T);
             const uint32_t xo_int = xch_off + (uint32_t)lx * 3 * sizeof(T);
             const uint32_t yo_int = xch_off + (uint32_t)ly * 3 * sizeof(T);
-            const uint32_t xo_face = (uint32_t)(NE * 64 + lj * 3) * sizeof(T);
-            const uint32_t yo_face = (uint32_t)(NE * 64 + 24 + li * 3) * sizeof(T);
+            const uint32_t xo_face = (uint32_t)(NS * 64 + lj * 3) * sizeof(T);
+            const uint32_t yo_face = (uint32_t)(NS * 64 + 24 + li * 3) * sizeof(T);
             T *xrow = (T *)(smem + xch_off) + L * 3;
             xrow[0] = xrow[1] = xrow[2] = (T)0;
             T last[3] = {0, 0, 0};   // this lane's previous result: the -z (+z) neighbour value
@@ -541,6 +551,10 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     vx[p] = bx[p];
                     vy[p] = by[p];
                 }
+                // output slot of a mapped backward sweep (read before the slot is released)
+                int32_t zm = -1;
+                if constexpr (DIR == 1)
+                    if (src.zmap) zm = ((const int32_t *)(ring + (size_t)slot * slot_elems + NE * 64))[L];
                 const bool more = t + 1 < nsteps;
                 const int seen = more ? __hip_atomic_load(&tags[nslot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
                 const int kk = DIR == 0 ? t - d : t - e_;
@@ -568,8 +582,12 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                         T *yp = yout + (rowbase + row) * 192 + L;
 #pragma unroll
                         for (int p = 0; p < 3; ++p) yp[p * 64] = out[p];
-                    } else {
+                    } else if (!src.zmap) {
                         double *zp = zout + (rowbase + row) * 192 + L;
+#pragma unroll
+                        for (int p = 0; p < 3; ++p) zp[p * 64] = (double)out[p];
+                    } else if (zm >= 0) {
+                        double *zp = zout + ((int64_t)zm >> 6) * 192 + (zm & 63);
 #pragma unroll
                         for (int p = 0; p < 3; ++p) zp[p * 64] = (double)out[p];
                     }
@@ -615,8 +633,8 @@ template <int DIR, typename T> struct NLoad { static constexpr int v = (DIR == 1
 template <typename T>
 inline size_t sweep_slot_bytes(int dir)
 {
-    const int NE = (dir == 0) ? 30 : 39;
-    return (size_t)(NE * 64 + 48) * sizeof(T);
+    const int NS = (dir == 0) ? 30 : 40;   // entries per lane (+ the bwd output map entry)
+    return (size_t)(NS * 64 + 48) * sizeof(T);
 }
 // dynamic LDS of a sweep: D ring slots, 64 tag words, the exchange rows
 template <typename T>
@@ -640,6 +658,8 @@ struct Bilu0 : PcImpl {
     uint64_t *faceX = nullptr, *faceY = nullptr;
     int32_t *tile_order = nullptr;
     int64_t nbytes = 0;
+    int btx = 0, bty = 0;                        // tiles per box (0: the whole grid)
+    const int32_t *zmap = nullptr;               // optional output map of the pipelined apply (not owned)
 
     ~Bilu0() override
     {
@@ -664,6 +684,9 @@ struct Bilu0 : PcImpl {
     {
         const Geo &g = M->g->geo;
         const int64_t rows = g.nslot / 64;
+        if (btx <= 0) btx = g.ntx;
+        if (bty <= 0) bty = g.nty;
+        if (g.ntx % btx != 0 || g.nty % bty != 0) return set_err(c, RSV_ERR_ARG, "boxes must tile the grid");
         rsv_status s = alloc((void **)&Lf, (size_t)rows * 27 * 64 * sizeof(double));
         if (s == RSV_OK) s = alloc((void **)&Dinv, (size_t)rows * 9 * 64 * sizeof(double));
         if (s != RSV_OK) return s;
@@ -716,8 +739,9 @@ struct Bilu0 : PcImpl {
             if (s != RSV_OK) return s;
             std::vector<int32_t> ord(NT);
             for (int t = 0; t < NT; ++t) ord[t] = t;
+            // topological order: by anti-diagonal of the tile inside its box
             std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-                const int da = a % g.ntx + a / g.ntx, db = b % g.ntx + b / g.ntx;
+                const int da = (a % g.ntx) % btx + (a / g.ntx) % bty, db = (b % g.ntx) % btx + (b / g.ntx) % bty;
                 return da < db;
             });
             RSV_HIP(c, hipMemcpy(tile_order, ord.data(), NT * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -764,6 +788,8 @@ struct Bilu0 : PcImpl {
         if (c->epoch == 0) c->epoch = 1;
         a.flags = c->d_flags;
         a.wait_limit = c->wait_ticks;
+        a.btx = btx;
+        a.bty = bty;
         a.trace = trace;
         c->ticket_base[0] += (uint64_t)(g.ntx * g.nty) + nwaves;
         return a;
@@ -810,7 +836,7 @@ struct Bilu0 : PcImpl {
         if (fp32) {
             SweepArgs a = sweep_args(nw);
             a.D = (int)sweep_ring_depth(c, 0, 1);
-            SweepSrc<float> s0{Lf32, (int64_t)27 * 64, 0, nullptr, 0, 0, r, nullptr};
+            SweepSrc<float> s0{Lf32, (int64_t)27 * 64, 0, nullptr, 0, 0, r, nullptr, nullptr};
             size_t sh = sweep_lds_bytes<float>(0, a.D);
             int t1 = prof_begin(c, RSV_K_ILU_FWD);
             hipLaunchKernelGGL((k_sweep<0, float, NLoad<0, float>::v>), dim3(nw), dim3(64 * (1 + NLoad<0, float>::v)), sh, c->stream, a, s0,
@@ -819,7 +845,7 @@ struct Bilu0 : PcImpl {
             RSV_LAUNCH(c);
             SweepArgs b = sweep_args(nw);
             b.D = (int)sweep_ring_depth(c, 1, 1);
-            SweepSrc<float> s1{U32, (int64_t)27 * 64, 0, Dinv32, (int64_t)9 * 64, 0, nullptr, (const float *)ybuf};
+            SweepSrc<float> s1{U32, (int64_t)27 * 64, 0, Dinv32, (int64_t)9 * 64, 0, nullptr, (const float *)ybuf, zmap};
             sh = sweep_lds_bytes<float>(1, b.D);
             int t2 = prof_begin(c, RSV_K_ILU_BWD);
             hipLaunchKernelGGL((k_sweep<1, float, NLoad<1, float>::v>), dim3(nw), dim3(64 * (1 + NLoad<1, float>::v)), sh, c->stream, b, s1,
@@ -829,7 +855,7 @@ struct Bilu0 : PcImpl {
         } else {
             SweepArgs a = sweep_args(nw);
             a.D = (int)sweep_ring_depth(c, 0, 0);
-            SweepSrc<double> s0{Lf, (int64_t)27 * 64, 0, nullptr, 0, 0, r, nullptr};
+            SweepSrc<double> s0{Lf, (int64_t)27 * 64, 0, nullptr, 0, 0, r, nullptr, nullptr};
             size_t sh = sweep_lds_bytes<double>(0, a.D);
             int t1 = prof_begin(c, RSV_K_ILU_FWD);
             hipLaunchKernelGGL((k_sweep<0, double, NLoad<0, double>::v>), dim3(nw), dim3(64 * (1 + NLoad<0, double>::v)), sh, c->stream, a, s0,
@@ -840,7 +866,7 @@ struct Bilu0 : PcImpl {
             SweepArgs b = sweep_args(nw);
             b.D = (int)sweep_ring_depth(c, 1, 0);
             SweepSrc<double> s1{M->d_A, (int64_t)63 * 64, (int64_t)36 * 64, Dinv, (int64_t)9 * 64, 0, nullptr,
-                                (const double *)ybuf};
+                                (const double *)ybuf, zmap};
             sh = sweep_lds_bytes<double>(1, b.D);
             int t2 = prof_begin(c, RSV_K_ILU_BWD);
             hipLaunchKernelGGL((k_sweep<1, double, NLoad<1, double>::v>), dim3(nw), dim3(64 * (1 + NLoad<1, double>::v)), sh, c->stream, b, s1,
@@ -865,6 +891,12 @@ int64_t sweep_ring_depth(const rsv_ctx *c, int dir, int fp32)
 
 rsv_status bilu0_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell)
 {
+    return bilu0_create_boxed(A, p, 0, 0, nullptr, out, bad_cell);
+}
+
+rsv_status bilu0_create_boxed(rsv_matrix *A, const rsv_pc_params *p, int btx, int bty, const int32_t *zmap,
+                              PcImpl **out, int64_t *bad_cell)
+{
     rsv_ctx *c = A->g->ctx;
     Bilu0 *B = new (std::nothrow) Bilu0();
     if (!B) return set_err(c, RSV_ERR_OOM, "bilu0");
@@ -872,6 +904,13 @@ rsv_status bilu0_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int
     B->c = c;
     B->fp32 = (p->precision == RSV_FP32);
     B->pipelined = (p->pipelined != 0);
+    B->btx = btx;
+    B->bty = bty;
+    B->zmap = zmap;
+    if (zmap && !B->pipelined) {
+        delete B;
+        return set_err(c, RSV_ERR_ARG, "an output map needs the pipelined sweeps");
+    }
     rsv_status s = B->setup(bad_cell);
     if (s != RSV_OK) {
         delete B;

@@ -136,6 +136,7 @@ struct rsv_ctx {
     int lds_per_cu = 0;
     // kernel timing
     bool prof_on = false;
+    uint32_t prof_mask = 0xffffffffu;  // kernel classes recorded
     std::vector<hipEvent_t> prof_ev;   // pairs
     std::vector<int> prof_kind;        // per pair
     int prof_used = 0;                 // events recorded (2 per pair)
@@ -247,6 +248,12 @@ rsv_status scal_set(rsv_ctx *c, int k0, const double *vals, int n);
 
 // ------------------------------------------------------------------ preconditioners
 rsv_status bilu0_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
+// BILU0 of a grid made of independent boxes of btx x bty tiles (all couplings
+// between boxes zero): the pipelined sweeps exchange faces only inside a box.
+// zmap (optional, device, [nslot], not owned): the apply writes the result of
+// slot s to slot zmap[s] of its output (nothing when -1) instead of slot s.
+rsv_status bilu0_create_boxed(rsv_matrix *A, const rsv_pc_params *p, int btx, int bty, const int32_t *zmap,
+                              PcImpl **out, int64_t *bad_cell);
 rsv_status ras_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
 // base: the BILU0 preconditioner a learned_mode 1 network corrects (not owned)
 rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, PcImpl *base);

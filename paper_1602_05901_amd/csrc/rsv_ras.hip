@@ -6,7 +6,23 @@
 // r to Omega_s, solves with the local factors and writes back only the cells
 // s owns (restricted prolongation, no atomics, no averaging).
 //
-// GPU mapping: one workgroup per subdomain.  Omega_s's cells are listed by
+// Two GPU mappings compute the same local solves.
+//
+// Boxed (the default, `pipelined`): each subdomain's extended box (its box
+// grown by `overlap` cells per side, clipped to the grid) is padded to whole
+// 8x8 tiles and placed in an SX x SY x SZ array of boxes that forms one
+// auxiliary grid (boxes stacked in z share tile columns: longer columns, fewer
+// tiles, less of each column spent on the tile's diagonal ramp).  The local matrix is stored there with every coupling that leaves
+// Omega_s set to zero; padded cells outside Omega_s get an identity diagonal
+// and no couplings.  The block-diagonal ILU(0) of that grid is exactly the
+// set of local ILU(0)s (the natural order inside a box is the global order),
+// and its pipelined tile sweeps exchange faces only inside a box, so every
+// subdomain advances at once, each tile's data streamed by its loader waves.
+// The apply gathers r into the auxiliary grid and runs both sweeps there; the
+// backward sweep stores each cell's result into z only from the box that owns
+// the cell (an index map delivered with the sweep's operands).
+//
+// Per subdomain: one workgroup per subdomain.  Omega_s's cells are listed by
 // hyperplane i+j+k (ascending global index inside a plane); all local lower
 // neighbours of a cell lie on the previous hyperplane, so a workgroup walks
 // the planes with one barrier between planes.  Factors are stored
@@ -436,11 +452,216 @@ struct Ras : PcImpl {
     }
 };
 
+
+// ---------------------------------------------------------------- boxed mapping
+
+struct BoxDev {
+    int32_t nsub, SX, SZ, BXp, BYp, EZ, ov;
+    const int32_t *box;   // [nsub][9]: core x0,x1,y0,y1,z0,z1; extended-box origin ex,ey,ez
+};
+
+__host__ __device__ inline int box_dist(int v, int lo, int hi) { return v < lo ? lo - v : (v >= hi ? v - hi + 1 : 0); }
+
+// Omega_s: cells within graph distance ov of the core box
+__host__ __device__ inline bool in_omega(const int32_t *q, int x, int y, int z, int ov)
+{
+    return box_dist(x, q[0], q[1]) + box_dist(y, q[2], q[3]) + box_dist(z, q[4], q[5]) <= ov;
+}
+
+// The global cell that auxiliary cell (X, Y, k) stands for; false when it is
+// padding, outside the grid or outside Omega_s of its box s.
+__host__ __device__ inline bool aux_cell(const BoxDev &B, const int32_t *box, const Geo &g, int X, int Y, int k, int &s,
+                                         int &gx, int &gy, int &gz)
+{
+    const int bx = X / B.BXp, by = Y / B.BYp, bz = k / B.EZ;
+    s = (by * B.SX + bx) * B.SZ + bz;
+    if (s >= B.nsub) return false;
+    const int32_t *q = box + 9 * s;
+    gx = q[6] + X % B.BXp;
+    gy = q[7] + Y % B.BYp;
+    gz = q[8] + k % B.EZ;
+    if (gx >= g.nx || gy >= g.ny || gz >= g.nz) return false;
+    return in_omega(q, gx, gy, gz, B.ov);
+}
+
+// local matrix of every subdomain in the auxiliary grid
+__global__ __launch_bounds__(256) void k_rasb_build(Geo ga, Geo g, BoxDev B, const double *__restrict__ A,
+                                                   double *__restrict__ Aa)
+{
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= ga.nslot) return;
+    int X, Y, k, s = 0, gx = 0, gy = 0, gz = 0;
+    const bool real = cell_of(ga, slot, X, Y, k);
+    const bool in = real && aux_cell(B, B.box, g, X, Y, k, s, gx, gy, gz);
+    const int64_t gsl = in ? slot_of(g, gx, gy, gz) : 0;
+    for (int d = 0; d < 7; ++d) {
+        bool keep = in;
+        if (in && d != 3) {
+            int di, dj, dk;
+            dir_off(d, di, dj, dk);
+            const int a = gx + di, b = gy + dj, e = gz + dk;
+            keep = a >= 0 && a < g.nx && b >= 0 && b < g.ny && e >= 0 && e < g.nz && in_omega(B.box + 9 * s, a, b, e, B.ov);
+        }
+        for (int e = 0; e < 9; ++e) {
+            const double id = (d == 3 && real && (e == 0 || e == 4 || e == 8)) ? 1.0 : 0.0;
+            Aa[aidx(slot, d * 9 + e)] = keep ? A[aidx(gsl, d * 9 + e)] : (in ? 0.0 : id);
+        }
+    }
+}
+
+// index maps of the auxiliary grid: gin[s] = the grid slot of the Omega cell
+// that auxiliary slot s holds (-1: none); gout[s] = the same when the cell's
+// own box is s's box (restricted prolongation), else -1
+__global__ __launch_bounds__(256) void k_rasb_maps(Geo ga, Geo g, BoxDev B, int32_t *__restrict__ gin,
+                                                  int32_t *__restrict__ gout)
+{
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= ga.nslot) return;
+    int X, Y, k, s, gx, gy, gz;
+    const bool in = cell_of(ga, slot, X, Y, k) && aux_cell(B, B.box, g, X, Y, k, s, gx, gy, gz);
+    const int32_t m = in ? (int32_t)slot_of(g, gx, gy, gz) : -1;
+    gin[slot] = m;
+    gout[slot] = (in && in_omega(B.box + 9 * s, gx, gy, gz, 0)) ? m : -1;
+}
+
+// restriction: r on Omega_s into each box (zero elsewhere)
+__global__ __launch_bounds__(256) void k_rasb_gather(int64_t nslot, const int32_t *__restrict__ gin,
+                                                    const double *__restrict__ r, double *__restrict__ ra)
+{
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= nslot) return;
+    const int32_t m = gin[slot];
+    const int64_t mm = m >= 0 ? m : 0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) ra[vidx(slot, p)] = m >= 0 ? r[vidx(mm, p)] : 0.0;
+}
+
+struct RasBoxed : PcImpl {
+    rsv_matrix *M = nullptr;
+    rsv_ctx *c = nullptr;
+    BoxDev B{};
+    std::vector<int32_t> h_box;
+    int32_t *d_box = nullptr;
+    rsv_grid *ga = nullptr;          // auxiliary grid of boxes
+    rsv_matrix Ma{};                 // local matrices in it
+    PcImpl *ilu = nullptr;           // its block-diagonal BILU0, writing z through gout
+    int32_t *gin = nullptr, *gout = nullptr;
+    double *ra = nullptr;
+    int64_t nbytes = 0;
+
+    ~RasBoxed() override
+    {
+        delete ilu;
+        dev_free(Ma.d_A);
+        dev_free(ra);
+        dev_free(gin);
+        dev_free(gout);
+        dev_free(d_box);
+        rsv_grid_destroy(ga);
+    }
+    int64_t bytes() const override { return nbytes + (ilu ? ilu->bytes() : 0); }
+
+    rsv_status alloc(void **p, size_t b)
+    {
+        rsv_status s = dev_alloc(c, p, b);
+        if (s == RSV_OK) nbytes += (int64_t)b;
+        return s;
+    }
+
+    rsv_status setup(const rsv_pc_params *p, int64_t *bad_cell)
+    {
+        const Geo &g = M->g->geo;
+        const int px = p->ras_px, py = p->ras_py, pz = p->ras_pz, ov = p->ras_overlap;
+        if (px < 1 || py < 1 || pz < 1 || px > g.nx || py > g.ny || pz > g.nz || ov < 0)
+            return set_err(c, RSV_ERR_ARG, "bad RAS partition");
+        const int nsub = px * py * pz;
+        h_box.assign((size_t)nsub * 9, 0);
+        int EX = 1, EY = 1, EZ = 1;
+        for (int s = 0; s < nsub; ++s) {
+            const int sx = s % px, sy = (s / px) % py, sz = s / (px * py);
+            int32_t *q = h_box.data() + 9 * s;
+            q[0] = (int32_t)split_start(sx, g.nx, px); q[1] = (int32_t)split_start(sx + 1, g.nx, px);
+            q[2] = (int32_t)split_start(sy, g.ny, py); q[3] = (int32_t)split_start(sy + 1, g.ny, py);
+            q[4] = (int32_t)split_start(sz, g.nz, pz); q[5] = (int32_t)split_start(sz + 1, g.nz, pz);
+            q[6] = std::max(0, q[0] - ov); q[7] = std::max(0, q[2] - ov); q[8] = std::max(0, q[4] - ov);
+            EX = std::max(EX, std::min(g.nx, q[1] + ov) - q[6]);
+            EY = std::max(EY, std::min(g.ny, q[3] + ov) - q[7]);
+            EZ = std::max(EZ, std::min(g.nz, q[5] + ov) - q[8]);
+        }
+        const int BXp = (EX + 7) / 8 * 8, BYp = (EY + 7) / 8 * 8;
+        // boxes per tile column: as many as keep at least four tiles per CU
+        const int64_t tpb = (int64_t)(BXp / 8) * (BYp / 8);
+        int SZ = 1;
+#ifdef RSV_RAS_STACK
+        SZ = std::min(nsub, RSV_RAS_STACK);
+#else
+        while (SZ < nsub && (int64_t)((nsub + 2 * SZ - 1) / (2 * SZ)) * tpb >= 4 * (int64_t)c->num_cu) SZ *= 2;
+#endif
+        const int nl = (nsub + SZ - 1) / SZ;
+        int SX = 1;
+        while (SX * SX < nl) ++SX;
+        const int SY = (nl + SX - 1) / SX;
+        B = BoxDev{nsub, SX, SZ, BXp, BYp, EZ, ov, nullptr};
+        if ((int64_t)SX * BXp > INT32_MAX / 2 || (int64_t)SY * BYp > INT32_MAX / 2 || (int64_t)SZ * EZ > INT32_MAX / 2)
+            return set_err(c, RSV_ERR_ARG, "RAS boxes too large");
+        rsv_status st = rsv_grid_create(c, SX * BXp, SY * BYp, SZ * EZ, RSV_BOTTOM_UP, &ga);
+        if (st != RSV_OK) return st;
+        const Geo &G = ga->geo;
+        st = alloc((void **)&d_box, h_box.size() * sizeof(int32_t));
+        if (st == RSV_OK) st = alloc((void **)&Ma.d_A, (size_t)(G.nslot / 64) * 63 * 64 * sizeof(double));
+        if (st == RSV_OK) st = alloc((void **)&ra, (size_t)ga->nv * sizeof(double));
+        if (st == RSV_OK) st = alloc((void **)&gin, (size_t)G.nslot * sizeof(int32_t));
+        if (st == RSV_OK) st = alloc((void **)&gout, (size_t)G.nslot * sizeof(int32_t));
+        if (st != RSV_OK) return st;
+        RSV_HIP(c, hipMemcpy(d_box, h_box.data(), h_box.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        B.box = d_box;
+        Ma.g = ga;
+        hipLaunchKernelGGL(k_rasb_build, dim3((unsigned)((G.nslot + 255) / 256)), dim3(256), 0, c->stream, G, g, B,
+                           M->d_A, Ma.d_A);
+        hipLaunchKernelGGL(k_rasb_maps, dim3((unsigned)((G.nslot + 255) / 256)), dim3(256), 0, c->stream, G, g, B,
+                           gin, gout);
+        RSV_LAUNCH(c);
+        int64_t bad = -1;
+        st = bilu0_create_boxed(&Ma, p, BXp / 8, BYp / 8, gout, &ilu, &bad);
+        if (st == RSV_ERR_ZERO_PIVOT && bad >= 0 && bad_cell) {
+            // the auxiliary row of the failing pivot, as the cell of the grid
+            const int X = (int)(bad % G.nx), Y = (int)((bad / G.nx) % G.ny), k = (int)(bad / ((int64_t)G.nx * G.ny));
+            int s, gx, gy, gz;
+            if (aux_cell(B, h_box.data(), g, X, Y, k, s, gx, gy, gz)) *bad_cell = row_of(g, gx, gy, gz);
+        }
+        return st;
+    }
+
+    rsv_status apply(const double *r, double *z) override
+    {
+        ProfScope ps(c, RSV_K_RAS);
+        const Geo &G = ga->geo;
+        hipLaunchKernelGGL(k_rasb_gather, dim3((unsigned)((G.nslot + 255) / 256)), dim3(256), 0, c->stream, G.nslot, gin,
+                           r, ra);
+        RSV_LAUNCH(c);
+        // the backward sweep stores each owned cell's result straight into z
+        return ilu->apply(ra, z);
+    }
+};
+
 }  // namespace
 
 rsv_status ras_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell)
 {
     rsv_ctx *c = A->g->ctx;
+    if (p->pipelined) {
+        RasBoxed *R = new (std::nothrow) RasBoxed();
+        if (!R) return set_err(c, RSV_ERR_OOM, "ras");
+        R->M = A;
+        R->c = c;
+        rsv_status s = R->setup(p, bad_cell);
+        if (s != RSV_OK) {
+            delete R;
+            return s;
+        }
+        *out = R;
+        return RSV_OK;
+    }
     Ras *R = new (std::nothrow) Ras();
     if (!R) return set_err(c, RSV_ERR_OOM, "ras");
     R->M = A;

@@ -86,6 +86,7 @@ _SIGS = {
     "rsv_conv3d_bwd": ([vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp], i32),
     "rsv_profile_enable": ([vp, i32], i32),
     "rsv_profile_read": ([vp, vp, vp], i32),
+    "rsv_profile_classes": ([vp, ctypes.c_uint32], i32),
     "rsv_device_info": ([vp, vp, i32], i32),
     "rsv_set_wait_limit": ([vp, ctypes.c_double], i32),
 }
@@ -153,7 +154,10 @@ class Context:
     def set_wait_limit(self, seconds):
         _check(self, lib().rsv_set_wait_limit(self.h, seconds))
 
-    def profile(self, on=True):
+    def profile(self, on=True, classes=None):
+        """classes: names from K_NAMES to record (None: all)."""
+        mask = 0xFFFFFFFF if classes is None else sum(1 << K_NAMES.index(k) for k in classes)
+        _check(self, lib().rsv_profile_classes(self.h, mask))
         _check(self, lib().rsv_profile_enable(self.h, 1 if on else 0))
 
     def profile_read(self):

@@ -207,6 +207,25 @@ def test_zero_pivot_reported(rsv, ctx):
     A.close(); g.close()
 
 
+@pytest.mark.parametrize("pipelined", [1, 0])
+def test_ras_zero_pivot_reported(rsv, ctx, pipelined):
+    """A zero diagonal block on the first cell of subdomain (1,1,1) (no overlap,
+    so the cell has no local lower neighbour): its local pivot is that block,
+    and the error names the cell by its row."""
+    dims = (8, 6, 4)
+    cfg = cfg_of(dims, seed=13)
+    B, _ = make(cfg)
+    B = B.copy()
+    row = (2 * 6 + 3) * 8 + 4   # cell (4, 3, 2): the corner of the core box of subdomain (1,1,1)
+    B[row, 3] = 0.0
+    g = rsv.Grid(ctx, *dims)
+    A = rsv.Matrix(g, dev(B))
+    with pytest.raises(rsv.RsvError) as e:
+        rsv.Precond(A, type=rsv.PC_RAS, ras_px=2, ras_py=2, ras_pz=2, ras_overlap=0, pipelined=pipelined)
+    assert e.value.status == rsv.ERR_ZERO_PIVOT and e.value.bad_cell == row
+    A.close(); g.close()
+
+
 def test_pattern_error(rsv, ctx):
     cfg = cfg_of((4, 4, 4), seed=14)
     B, _ = make(cfg)
@@ -227,15 +246,18 @@ def test_pattern_error(rsv, ctx):
                                            ((32, 32, 16), (4, 4, 4), 1)])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("shift", [2.0, 0.0])
-def test_ras_apply_parity(rsv, ctx, dims, parts, ov, prec, shift):
+@pytest.mark.parametrize("pipelined", [1, 0])
+def test_ras_apply_parity(rsv, ctx, dims, parts, ov, prec, shift, pipelined):
     """shift 2 is the reading the RAS workload uses (bar 1e-12).  The literal
     reading (shift 0) has pivot blocks up to ~1e4 worse conditioned; the GPU's
     cofactor 3x3 inverses and the oracle's pivoted-LU inverses then differ by
-    up to cond(D)*eps per pivot, so its bar is 1e-11."""
-    log("ras", dims, parts, ov, prec, shift)
+    up to cond(D)*eps per pivot, so its bar is 1e-11.  pipelined 1: the boxed
+    mapping (local matrices in an auxiliary grid of boxes, tiled sweeps);
+    0: one workgroup per subdomain, one barrier per hyperplane."""
+    log("ras", dims, parts, ov, prec, shift, pipelined)
     S = Sys(rsv, ctx, cfg_of(dims, seed=15, shift=shift))
     M = rsv.Precond(S.A, type=rsv.PC_RAS, ras_px=parts[0], ras_py=parts[1], ras_pz=parts[2], ras_overlap=ov,
-                    precision=prec)
+                    precision=prec, pipelined=pipelined)
     n = 3 * S.cfg.ncell
     r = I.test_vector(16, n)
     z = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -372,6 +394,31 @@ def test_C2_full_solve(rsv, ctx, method):
     check_solve(st, ref, xg, relres, its_band=(method != "bicgstab_bilu0"),
                 hist_steps=(6 if method == "bicgstab_bilu0" else 10))
     assert rel(xg, xt) <= 1e-5
+
+
+# ---------------------------------------------------------------- kernel timing
+
+def test_profile_classes(rsv, ctx):
+    """Only the selected kernel classes are timed; all of them by default."""
+    S = Sys(rsv, ctx, cfg_of((20, 20, 10), seed=21))
+    M = rsv.Precond(S.A, type=rsv.PC_BILU0)
+    n = 3 * S.cfg.ncell
+    r = dev(I.test_vector(22, n))
+    z = torch.zeros_like(r)
+    y = torch.zeros_like(r)
+    ctx.profile(True, classes=("ilu_fwd",))
+    M.apply(r, z)
+    S.A.spmv(z, y)
+    k = ctx.profile_read()
+    ctx.profile(False)
+    assert k["ilu_fwd"][1] == 1 and k["ilu_bwd"][1] == 0 and k["spmv"][1] == 0
+    ctx.profile(True)
+    M.apply(r, z)
+    S.A.spmv(z, y)
+    k = ctx.profile_read()
+    ctx.profile(False)
+    assert k["ilu_fwd"][1] == 1 and k["ilu_bwd"][1] == 1 and k["spmv"][1] == 1
+    M.close(); S.close()
 
 
 # ---------------------------------------------------------------- hang watchdog
