@@ -221,6 +221,9 @@ void rsv_destroy(rsv_ctx *c)
     (void)hipDeviceSynchronize();
     for (auto &e : c->prof_ev) (void)hipEventDestroy(e);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->h_spec) (void)hipHostFree(c->h_spec);
+    for (auto &e : c->spec_ev)
+        if (e) (void)hipEventDestroy(e);
     dev_free(c->d_scal);
     dev_free(c->d_partials);
     dev_free(c->d_tickets);

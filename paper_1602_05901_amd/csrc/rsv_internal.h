@@ -123,6 +123,8 @@ struct rsv_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     double *h_scal = nullptr;     // pinned, SC_COUNT
+    double *h_spec = nullptr;     // pinned, 2 x SC_COUNT: scalars copied without a stream sync
+    hipEvent_t spec_ev[2] = {nullptr, nullptr};
     double *d_scal = nullptr;     // device, SC_COUNT
     double *d_partials = nullptr; // device partial sums
     int64_t partials_cap = 0;     // doubles
@@ -244,6 +246,9 @@ rsv_status launch_nonfinite(rsv_ctx *c, int64_t n, const double *x, int k0);   /
 
 // scalars
 rsv_status scal_to_host(rsv_ctx *c, int k0, int n);   // sync copy d_scal[k0..k0+n) -> h_scal
+// async copy d_scal[k0..k0+n) -> h_spec[buf][k0..] and an event after it; scal_wait blocks on that event
+rsv_status scal_to_host_async(rsv_ctx *c, int buf, int k0, int n);
+rsv_status scal_wait(rsv_ctx *c, int buf);
 rsv_status scal_set(rsv_ctx *c, int k0, const double *vals, int n);
 
 // ------------------------------------------------------------------ preconditioners

@@ -344,10 +344,17 @@ __global__ __launch_bounds__(BS) void k_bicg_xr(int64_t n, double alpha, const d
 
 // ---------------------------------------------------------------- launchers
 
+#ifndef RSV_MVEC_BLOCKS
+#define RSV_MVEC_BLOCKS 4096
+#endif
+
 rsv_status partials_reserve(rsv_ctx *c, int64_t nd)
 {
     if (nd <= c->partials_cap) return RSV_OK;
-    // the stream may still read the old buffer
+    // Growing needs a stream sync (the stream may still read the old buffer),
+    // so grow rarely: at least 2 MiB (RSV_MVEC_BLOCKS blocks x 64 outputs) and
+    // at least twice the old size.
+    nd = std::max<int64_t>(nd, std::max<int64_t>((int64_t)RSV_MVEC_BLOCKS * 64, 2 * c->partials_cap));
     RSV_HIP(c, hipStreamSynchronize(c->stream));
     if (c->d_partials) dev_free(c->d_partials);
     c->d_partials = nullptr;
@@ -366,9 +373,6 @@ int vec_blocks(int64_t n)
 }
 
 // the multi-vector (CGS2) kernels (grid size chosen by measurement)
-#ifndef RSV_MVEC_BLOCKS
-#define RSV_MVEC_BLOCKS 4096
-#endif
 int mvec_blocks(int64_t n)
 {
     int64_t b = (n + BS - 1) / BS;
@@ -576,6 +580,24 @@ rsv_status scal_to_host(rsv_ctx *c, int k0, int n)
     RSV_HIP(c, hipMemcpyAsync(c->h_scal + k0, c->d_scal + k0, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
                               c->stream));
     RSV_HIP(c, hipStreamSynchronize(c->stream));
+    return RSV_OK;
+}
+
+rsv_status scal_to_host_async(rsv_ctx *c, int buf, int k0, int n)
+{
+    if (!c->h_spec) {
+        RSV_HIP(c, hipHostMalloc((void **)&c->h_spec, 2 * SC_COUNT * sizeof(double), hipHostMallocDefault));
+        for (int b = 0; b < 2; ++b) RSV_HIP(c, hipEventCreateWithFlags(&c->spec_ev[b], hipEventDisableTiming));
+    }
+    double *dst = c->h_spec + (size_t)buf * SC_COUNT;
+    RSV_HIP(c, hipMemcpyAsync(dst + k0, c->d_scal + k0, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    RSV_HIP(c, hipEventRecord(c->spec_ev[buf], c->stream));
+    return RSV_OK;
+}
+
+rsv_status scal_wait(rsv_ctx *c, int buf)
+{
+    RSV_HIP(c, hipEventSynchronize(c->spec_ev[buf]));
     return RSV_OK;
 }
 

@@ -149,7 +149,53 @@ static rsv_status gmres(Solve &S, PcImpl *P, PcImpl *FB, double theta, int m, in
         int jdone = 0;
         bool fb_rest = false;
         consecutive_fb = 0;
-        for (int j = 0; j < m; ++j) {
+        if (!flexible) {
+            // The host's work on step j (Givens rotation, convergence test)
+            // overlaps the device's step j + 1, which is enqueued before step
+            // j's scalars are awaited -- except when the estimate is within a
+            // factor 4 of the target, where that step would most likely be
+            // discarded.  A discarded step only wrote V[j + 2], the
+            // preconditioner's scratch and scalar slots no later step reads.
+            auto enqueue = [&](int j) -> rsv_status {
+                double *w = V + (int64_t)(j + 1) * n;
+                rsv_status e = pc_apply(c, P, n, V + (int64_t)j * n, zt);
+                if (e == RSV_OK) e = launch_spmv(c, *S.geo, S.M->d_A, SPMV_NORM, zt, w, nullptr, 0, 0, SC_W0);
+                if (e == RSV_OK) e = launch_mdot(c, n, V, n, j + 1, w, SC_H1);
+                if (e == RSV_OK) e = launch_upd_dot(c, n, V, n, j + 1, w, SC_H1, SC_H2);
+                if (e == RSV_OK) e = launch_upd_norm(c, n, V, n, j + 1, w, SC_H2, SC_HN);
+                if (e == RSV_OK) e = launch_scale_dev(c, n, w, SC_HN);
+                if (e == RSV_OK) e = scal_to_host_async(c, j & 1, 0, SC_H2 + j + 1);
+                return e;
+            };
+            double est = beta;
+            if ((s = enqueue(0)) != RSV_OK) return s;
+            std::vector<double> hcol(m + 2, 0.0);
+            for (int j = 0; j < m; ++j) {
+                const bool ahead = j + 1 < m && its + 1 < maxit && !S.ctl.met(0.25 * est);
+                if (ahead && (s = enqueue(j + 1)) != RSV_OK) return s;
+                if ((s = scal_wait(c, j & 1)) != RSV_OK) return s;
+                const double *hs = c->h_spec + (size_t)(j & 1) * SC_COUNT;
+                std::fill(hcol.begin(), hcol.end(), 0.0);
+                for (int i = 0; i <= j; ++i) hcol[i] = hs[SC_H1 + i] + hs[SC_H2 + i];
+                const double hn = std::sqrt(hs[SC_HN]);
+                const double w0 = std::sqrt(hs[SC_W0]);
+                hcol[j + 1] = hn;
+                bool finite = std::isfinite(hn) && std::isfinite(w0);
+                for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(hcol[i]);
+                if (!finite) return set_err(c, RSV_ERR_NAN, "non-finite Arnoldi column");
+                givens_step(j, hcol.data(), cs.data(), sn.data(), g.data());
+                for (int i = 0; i <= j + 1; ++i) Hc(j, i) = hcol[i];
+                const bool happy = (hn <= 1e-14 * w0);
+                ++its;
+                jdone = j + 1;
+                est = std::fabs(g[j + 1]);
+                if (S.record) S.hist->push_back(est / nb);
+                if (!std::isfinite(est)) return set_err(c, RSV_ERR_NAN, "non-finite residual estimate");
+                if (S.ctl.met(est) || its >= maxit || happy) break;
+                if (!ahead && j + 1 < m && (s = enqueue(j + 1)) != RSV_OK) return s;
+            }
+        }
+        for (int j = 0; flexible && j < m; ++j) {
             double *w = V + (int64_t)(j + 1) * n;
             double *z = flexible ? Z + (int64_t)j * n : zt;
             std::vector<double> cs_save(cs), sn_save(sn), g_save(g);
