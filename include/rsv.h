@@ -88,7 +88,9 @@ typedef struct rsv_pc_params {
     double theta;        /* LEARNED: fallback when a step's residual estimate exceeds theta * previous (default 0.99) */
     int32_t learned_mode;/* LEARNED: 0 (default) z = s N(r/s); 1 z = t + s N(r1/s) with t = BILU0^-1 r,
                           * r1 = r - A t, s = rms(r1): the network corrects what one BILU0 step leaves */
-    int32_t reserved[7];
+    int32_t ras_stack;   /* RAS, pipelined: subdomain boxes stacked per tile column of the auxiliary
+                          * grid (0, default: as many as keep four tiles per compute unit) */
+    int32_t reserved[6];
 } rsv_pc_params;
 
 /* Solver parameters; mirrors SOLVER (rtol, atol, maxit, restart). */

@@ -572,7 +572,7 @@ struct RasBoxed : PcImpl {
     {
         const Geo &g = M->g->geo;
         const int px = p->ras_px, py = p->ras_py, pz = p->ras_pz, ov = p->ras_overlap;
-        if (px < 1 || py < 1 || pz < 1 || px > g.nx || py > g.ny || pz > g.nz || ov < 0)
+        if (px < 1 || py < 1 || pz < 1 || px > g.nx || py > g.ny || pz > g.nz || ov < 0 || p->ras_stack < 0)
             return set_err(c, RSV_ERR_ARG, "bad RAS partition");
         const int nsub = px * py * pz;
         h_box.assign((size_t)nsub * 9, 0);
@@ -592,11 +592,10 @@ struct RasBoxed : PcImpl {
         // boxes per tile column: as many as keep at least four tiles per CU
         const int64_t tpb = (int64_t)(BXp / 8) * (BYp / 8);
         int SZ = 1;
-#ifdef RSV_RAS_STACK
-        SZ = std::min(nsub, RSV_RAS_STACK);
-#else
-        while (SZ < nsub && (int64_t)((nsub + 2 * SZ - 1) / (2 * SZ)) * tpb >= 4 * (int64_t)c->num_cu) SZ *= 2;
-#endif
+        if (p->ras_stack > 0)
+            SZ = std::min(nsub, p->ras_stack);
+        else
+            while (SZ < nsub && (int64_t)((nsub + 2 * SZ - 1) / (2 * SZ)) * tpb >= 4 * (int64_t)c->num_cu) SZ *= 2;
         const int nl = (nsub + SZ - 1) / SZ;
         int SX = 1;
         while (SX * SX < nl) ++SX;

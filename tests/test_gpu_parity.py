@@ -207,6 +207,31 @@ def test_zero_pivot_reported(rsv, ctx):
     A.close(); g.close()
 
 
+@pytest.mark.parametrize("dims,parts,ov,stack", [((13, 9, 5), (3, 2, 1), 1, 4), ((20, 20, 10), (2, 2, 2), 2, 3),
+                                                 ((16, 16, 8), (4, 4, 4), 1, 64), ((12, 10, 6), (2, 3, 1), 0, 2)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ras_boxes_stacked(rsv, ctx, dims, parts, ov, stack, prec):
+    """Boxed RAS with several subdomain boxes stacked per tile column (some
+    positions of the box array unused): same result as the oracle, and the
+    same as without stacking to rounding."""
+    log("ras stacked", dims, parts, ov, stack, prec)
+    S = Sys(rsv, ctx, cfg_of(dims, seed=17))
+    kw = dict(type=rsv.PC_RAS, ras_px=parts[0], ras_py=parts[1], ras_pz=parts[2], ras_overlap=ov, precision=prec)
+    n = 3 * S.cfg.ncell
+    r = I.test_vector(18, n)
+    out = []
+    for st in (stack, 1):
+        M = rsv.Precond(S.A, ras_stack=st, **kw)
+        z = torch.zeros(n, dtype=torch.float64, device="cuda")
+        M.apply(dev(r), z)
+        out.append(z.cpu().numpy())
+        M.close()
+    ref = O.RAS(S.Ao, dims, parts, ov).apply(r)
+    assert rel(out[0], ref) <= (1e-12 if prec == 0 else 1e-4)
+    assert rel(out[0], out[1]) <= (1e-14 if prec == 0 else 1e-6)
+    S.close()
+
+
 @pytest.mark.parametrize("pipelined", [1, 0])
 def test_ras_zero_pivot_reported(rsv, ctx, pipelined):
     """A zero diagonal block on the first cell of subdomain (1,1,1) (no overlap,
