@@ -11,6 +11,7 @@ preconditioner setup + solve.  Forms: GMRES(30) + RAS(4x4x4 subdomains,
 overlap 1, ILU(0) local solves: the paper's own solver configuration, the
 headline time-to-solve), BiCGSTAB + BILU0,
 GMRES(30) + BILU0 with FP64 factors, GMRES(30) + BILU0 with FP32 factors,
+GMRES(30) + RAS with FP32 local factors,
 and FGMRES(30) + the learned U-Net preconditioner (BILU0 fallback), whose
 network is trained first on C4-shaped systems (64x64x32, disjoint seeds;
 training time reported apart) or loaded (--net).
@@ -89,7 +90,7 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32")
+    ap.add_argument("--forms", default="gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32")
     ap.add_argument("--net", default=None, help="trained U-Net weights for the learned form")
     ap.add_argument("--learned-steps", type=int, default=1500,
                     help="without --net: Adam steps of training on C4 systems before the timed steps (0: no learned form)")
@@ -136,6 +137,8 @@ def main():
     forms_all = {
         "bicgstab_bilu0": (rsv.BICGSTAB, dict(type=rsv.PC_BILU0)),
         "gmres_ras64": (rsv.GMRES, dict(type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1)),
+        "gmres_ras64_fp32": (rsv.GMRES, dict(type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1,
+                                              precision=rsv.FP32)),
         "gmres_bilu0": (rsv.GMRES, dict(type=rsv.PC_BILU0)),
         "gmres_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_BILU0, precision=rsv.FP32)),
     }
