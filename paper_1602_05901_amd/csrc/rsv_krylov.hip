@@ -304,12 +304,22 @@ static rsv_status bicgstab(Solve &S, PcImpl *P, int64_t maxit, double *b, double
             if ((s = pc_apply(c, P, n, p, ph)) != RSV_OK) return s;
             if ((s = launch_spmv(c, *S.geo, S.M->d_A, SPMV_DOT1, ph, v, rh, 0, 0, SC_RV)) != RSV_OK) return s;
             if ((s = launch_bicg_s(c, n, r, v, s_, SC_RH, SC_RV, SC_SS)) != RSV_OK) return s;
-            if ((s = scal_to_host(c, SC_RR, SC_SS - SC_RR + 1)) != RSV_OK) return s;
-            const double rv = c->h_scal[SC_RV];
+            if ((s = scal_to_host_async(c, 0, SC_RR, SC_SS - SC_RR + 1)) != RSV_OK) return s;
+            // The second half's preconditioner apply and product depend only
+            // on s, so they are enqueued before the mid-iteration scalars are
+            // awaited (and discarded when ||s|| already meets the tolerance),
+            // except within a factor 4 of the target.
+            const bool ahead = !S.ctl.met(0.25 * nr);
+            if (ahead) {
+                if ((s = pc_apply(c, P, n, s_, sh)) != RSV_OK) return s;
+                if ((s = launch_spmv(c, *S.geo, S.M->d_A, SPMV_DOT2, sh, t, s_, 0, 0, SC_TS)) != RSV_OK) return s;
+            }
+            if ((s = scal_wait(c, 0)) != RSV_OK) return s;
+            const double rv = c->h_spec[SC_RV];
             if (!std::isfinite(rv)) return set_err(c, RSV_ERR_NAN, "non-finite rhat.v");
             if (rv == 0.0) { rc = RSV_BREAKDOWN; break; }
             alpha = rho_new / rv;
-            const double sn_ = std::sqrt(c->h_scal[SC_SS]);
+            const double sn_ = std::sqrt(c->h_spec[SC_SS]);
             if (S.ctl.met(sn_)) {
                 if ((s = launch_axpby(c, n, alpha, ph, 1.0, x)) != RSV_OK) return s;
                 ++its;
@@ -325,8 +335,10 @@ static rsv_status bicgstab(Solve &S, PcImpl *P, int64_t maxit, double *b, double
                 nr = tr;
                 continue;
             }
-            if ((s = pc_apply(c, P, n, s_, sh)) != RSV_OK) return s;
-            if ((s = launch_spmv(c, *S.geo, S.M->d_A, SPMV_DOT2, sh, t, s_, 0, 0, SC_TS)) != RSV_OK) return s;
+            if (!ahead) {
+                if ((s = pc_apply(c, P, n, s_, sh)) != RSV_OK) return s;
+                if ((s = launch_spmv(c, *S.geo, S.M->d_A, SPMV_DOT2, sh, t, s_, 0, 0, SC_TS)) != RSV_OK) return s;
+            }
             if ((s = launch_bicg_xr(c, n, alpha, 0.0, ph, sh, s_, t, rh, x, r, SC_RR)) != RSV_OK) return s;
             if ((s = scal_to_host(c, SC_RR, SC_TT - SC_RR + 1)) != RSV_OK) return s;
             const double tt = c->h_scal[SC_TT];
