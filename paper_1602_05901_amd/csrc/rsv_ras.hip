@@ -548,6 +548,7 @@ struct RasBoxed : PcImpl {
     int32_t *gin = nullptr, *gout = nullptr;
     double *ra = nullptr;
     int64_t nbytes = 0;
+    bool too_large = false;          // the boxes do not fit one auxiliary grid
 
     ~RasBoxed() override
     {
@@ -601,8 +602,13 @@ struct RasBoxed : PcImpl {
         while (SX * SX < nl) ++SX;
         const int SY = (nl + SX - 1) / SX;
         B = BoxDev{nsub, SX, SZ, BXp, BYp, EZ, ov, nullptr};
-        if ((int64_t)SX * BXp > INT32_MAX / 2 || (int64_t)SY * BYp > INT32_MAX / 2 || (int64_t)SZ * EZ > INT32_MAX / 2)
-            return set_err(c, RSV_ERR_ARG, "RAS boxes too large");
+        // the auxiliary grid must fit the tile-lane index range (3 * slots < 2^31);
+        // otherwise the caller falls back to the per-subdomain mapping
+        const int64_t aux_slots = (int64_t)SX * (BXp / 8) * SY * (BYp / 8) * SZ * EZ * 64;
+        if (3 * aux_slots >= ((int64_t)1 << 31)) {
+            too_large = true;
+            return set_err(c, RSV_ERR_ARG, "RAS boxes exceed the auxiliary grid's index range");
+        }
         rsv_status st = rsv_grid_create(c, SX * BXp, SY * BYp, SZ * EZ, RSV_BOTTOM_UP, &ga);
         if (st != RSV_OK) return st;
         const Geo &G = ga->geo;
@@ -654,12 +660,14 @@ rsv_status ras_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64
         R->M = A;
         R->c = c;
         rsv_status s = R->setup(p, bad_cell);
-        if (s != RSV_OK) {
-            delete R;
-            return s;
+        if (s == RSV_OK) {
+            *out = R;
+            return RSV_OK;
         }
-        *out = R;
-        return RSV_OK;
+        const bool fall_back = R->too_large;
+        delete R;
+        if (!fall_back) return s;
+        // too many or too large boxes for one auxiliary grid: per-subdomain mapping
     }
     Ras *R = new (std::nothrow) Ras();
     if (!R) return set_err(c, RSV_ERR_OOM, "ras");
