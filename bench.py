@@ -300,7 +300,8 @@ def main():
         t2 = time.perf_counter()
         cpu = {"value": round(t2 - t1, 3), "unit": "s", "cores": 1, "kind": "oracle",
                "sample": f"full {args.workload} {what} + {ro['its']} iterations, "
-                         f"relres {ro['relres']:.2e}), serial FP64 C on one host thread"}
+                         f"relres {ro['relres']:.2e}), serial FP64 C on one host thread "
+                         f"(the host has {os.cpu_count()} logical cores)"}
         log(f"oracle: {t2 - t1:.2f}s ({ro['its']} its)")
 
     value = summary[head]["solve_s"]
@@ -324,6 +325,14 @@ def main():
         "vs_plain_gmres_bilu0": ({f: round(summary[f]["solve_s"] / summary["gmres_bilu0"]["solve_s"], 3) for f in forms}
                                  if "gmres_bilu0" in summary else None),
         "learned_training": training,
+        # unknowns x iterations per second of the headline solve, beside the paper's
+        # closest published figure (scalar Poisson on a CPU cluster): context only
+        "unknown_iterations_per_s": round(3 * cfg.ncell * summary[head]["its"] / value, 1),
+        "paper_context": {"workload": "scalar 7-point Poisson, 3e9 unknowns, GMRES(30) + RAS(overlap 1, ILU(0)), "
+                                      "90 iterations (Poisson Equation example)",
+                          "hardware": "IBM Blue Gene/Q, 512 cores (PowerPC A2)",
+                          "solve_s": 606.33, "unknown_iterations_per_s": round(3e9 * 90 / 606.33, 1),
+                          "note": "solve time = overall - gridding - building - assemble of its 512-core row"},
         "ilu_apply_GBps": ilu_GBps,
         "spmv_GBps": spmv_GBps,
         "kernels": kernels,
