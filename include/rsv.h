@@ -187,6 +187,14 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
  * For LEARNED this applies the network (no fallback). */
 rsv_status rsv_precond_apply(rsv_precond *M, const double *r, double *z);
 void rsv_precond_destroy(rsv_precond *M);
+/* Diagnostics: the block ILU(0) factors of an FP64 BILU0 preconditioner
+ * (Preconditioners section, ILU(0) of the block matrix), copied to HOST
+ * arrays in block-row order: L[row][3][3][3], the unit-lower blocks
+ * L_ck = A_ck D_k^-1 toward the -z, -y, -x neighbours (zero where a
+ * neighbour is absent), and Dinv[row][3][3], the inverted pivot blocks.
+ * The caller owns both arrays (27 and 9 doubles per cell).  RSV_ERR_ARG for
+ * another preconditioner type or the FP32 form. */
+rsv_status rsv_precond_bilu0_factors(const rsv_precond *M, double *L, double *Dinv);
 
 /* ---------------------------------------------------------------- solver */
 

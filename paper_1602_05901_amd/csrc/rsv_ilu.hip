@@ -195,6 +195,20 @@ __global__ __launch_bounds__(BS) void k_bwd_plane(Geo g, const int32_t *__restri
     }
 }
 
+// factors of the real slots into block-row order: L[row][27], Dinv[row][9]
+__global__ __launch_bounds__(BS) void k_factors_to_rows(Geo g, const double *__restrict__ Lf,
+                                                        const double *__restrict__ Dinv, double *__restrict__ Lr,
+                                                        double *__restrict__ Dr)
+{
+    const int64_t slot = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (slot >= g.nslot) return;
+    int gx, gy, k;
+    if (!cell_of(g, slot, gx, gy, k)) return;
+    const int64_t row = row_of(g, gx, gy, k);
+    for (int e = 0; e < 27; ++e) Lr[row * 27 + e] = Lf[fidx(slot, e, 27)];
+    for (int e = 0; e < 9; ++e) Dr[row * 9 + e] = Dinv[fidx(slot, e, 9)];
+}
+
 // ---------------------------------------------------------------- pipelined tile-lane sweeps
 //
 // One workgroup per tile at a time: wave 0 computes, waves 1..NL stream the
@@ -668,6 +682,26 @@ struct Bilu0 : PcImpl {
         dev_free(trace);
     }
     int64_t bytes() const override { return nbytes; }
+
+    rsv_status bilu0_factors(double *L, double *D) override
+    {
+        if (fp32 || !Lf || !Dinv) return set_err(c, RSV_ERR_ARG, "factors are kept for the FP64 BILU0 form only");
+        const Geo &g = M->g->geo;
+        const int64_t nc = M->g->ncell;
+        double *buf = nullptr;
+        rsv_status s = dev_alloc(c, (void **)&buf, (size_t)nc * 36 * sizeof(double));
+        if (s != RSV_OK) return s;
+        hipLaunchKernelGGL(k_factors_to_rows, dim3((unsigned)((g.nslot + BS - 1) / BS)), dim3(BS), 0, c->stream, g, Lf,
+                           Dinv, buf, buf + nc * 27);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(L, buf, (size_t)nc * 27 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(D, buf + nc * 27, (size_t)nc * 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        dev_free(buf);
+        if (e != hipSuccess) return set_err(c, RSV_ERR_HIP, std::string("factor export: ") + hipGetErrorString(e));
+        return RSV_OK;
+    }
 
     rsv_status alloc(void **p, size_t b)
     {

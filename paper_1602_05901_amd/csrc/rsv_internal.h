@@ -181,6 +181,8 @@ struct PcImpl {
     // z = M^{-1} r on tile-lane vectors (length nv); no aliasing
     virtual rsv_status apply(const double *r_tl, double *z_tl) = 0;
     virtual int64_t bytes() const = 0;
+    // FP64 BILU0 only: the factors in block-row order into host arrays
+    virtual rsv_status bilu0_factors(double * /*L*/, double * /*Dinv*/) { return RSV_ERR_ARG; }
 };
 
 struct rsv_precond {

@@ -417,6 +417,13 @@ void rsv_precond_destroy(rsv_precond *P)
     delete P;
 }
 
+rsv_status rsv_precond_bilu0_factors(const rsv_precond *P, double *L, double *Dinv)
+{
+    if (!P || !L || !Dinv) return set_err(P ? P->A->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");
+    if (P->p.type != RSV_PC_BILU0) return set_err(P->A->g->ctx, RSV_ERR_ARG, "not a BILU0 preconditioner");
+    return P->impl->bilu0_factors(L, Dinv);
+}
+
 rsv_status rsv_precond_apply(rsv_precond *P, const double *r, double *z)
 {
     if (!P || !r || !z) return set_err(P ? P->A->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");

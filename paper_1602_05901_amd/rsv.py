@@ -68,6 +68,7 @@ _SIGS = {
     "rsv_pc_params_default": ([_P(PcParams)], None),
     "rsv_precond_setup": ([vp, _P(PcParams), _P(vp), _P(i64)], i32),
     "rsv_precond_apply": ([vp, vp, vp], i32),
+    "rsv_precond_bilu0_factors": ([vp, vp, vp], i32),
     "rsv_precond_destroy": ([vp], None),
     "rsv_solver_params_default": ([_P(SolverParams)], None),
     "rsv_solve": ([vp, vp, _P(SolverParams), vp, vp, _P(Stats)], i32),
@@ -267,6 +268,16 @@ class Precond:
     def apply(self, r, z):
         _check(self.ctx, lib().rsv_precond_apply(self.h, _ptr(r), _ptr(z)))
         return z
+
+    def bilu0_factors(self):
+        """(L [ncell, 3, 3, 3] toward -z, -y, -x; Dinv [ncell, 3, 3]) in block-row order
+        (FP64 BILU0 only)."""
+        import numpy as np
+        n = self.A.g.ncell
+        L = np.zeros((n, 3, 3, 3))
+        D = np.zeros((n, 3, 3))
+        _check(self.ctx, lib().rsv_precond_bilu0_factors(self.h, L.ctypes.data, D.ctypes.data))
+        return L, D
 
     def close(self):
         if self.h:

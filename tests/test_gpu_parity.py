@@ -140,6 +140,48 @@ def test_bilu0_apply_parity(rsv, ctx, dims, pipelined):
     M.close(); S.close()
 
 
+@pytest.mark.parametrize("dims", [(20, 20, 10), (13, 9, 5), (17, 3, 19), (1, 1, 7), (6, 1, 4)])
+@pytest.mark.parametrize("shift", [2.0, 0.0])
+def test_bilu0_factors_parity(rsv, ctx, dims, shift):
+    """The factors themselves: the unit-lower blocks against the oracle's
+    strict lower blocks and D^-1 against the inverse of the oracle's pivot
+    blocks (bar 1e-12; 1e-11 for the literal reading, whose pivots are worse
+    conditioned: cofactor and pivoted-LU inverses differ by cond(D) eps)."""
+    log("bilu0 factors", dims, shift)
+    S = Sys(rsv, ctx, cfg_of(dims, seed=4, shift=shift))
+    M = rsv.Precond(S.A, type=rsv.PC_BILU0)
+    L, Dinv = M.bilu0_factors()
+    rp, col, val = O.ILU(S.Ao).factors()
+    nx, ny, _ = dims
+    Lref = np.zeros_like(L)
+    Dref = np.zeros_like(Dinv)
+    for c in range(S.cfg.ncell):
+        for q in range(rp[c], rp[c + 1]):
+            m = col[q]
+            if m == c:
+                Dref[c] = np.linalg.inv(val[q])
+            elif m == c - nx * ny:
+                Lref[c, 0] = val[q]
+            elif m == c - nx:
+                Lref[c, 1] = val[q]
+            elif m == c - 1:
+                Lref[c, 2] = val[q]
+    tol = 1e-12 if shift == 2.0 else 1e-11
+    assert rel(L, Lref) <= tol and rel(Dinv, Dref) <= tol
+    M.close(); S.close()
+
+
+def test_bilu0_factors_rejects_other_forms(rsv, ctx):
+    S = Sys(rsv, ctx, cfg_of((8, 8, 4), seed=5))
+    for kw in (dict(type=rsv.PC_BILU0, precision=rsv.FP32), dict(type=rsv.PC_RAS, ras_px=2, ras_py=2, ras_pz=1)):
+        M = rsv.Precond(S.A, **kw)
+        with pytest.raises(rsv.RsvError) as e:
+            M.bilu0_factors()
+        assert e.value.status == rsv.ERR_ARG
+        M.close()
+    S.close()
+
+
 @pytest.mark.parametrize("dims", [(20, 20, 10), (17, 3, 19), (9, 16, 33)])
 def test_bilu0_pipelined_bitwise_equals_per_plane(rsv, ctx, dims):
     """The sync-free tiled wavefront against the one-launch-per-hyperplane
