@@ -273,7 +273,7 @@ class Precond:
         """(L [ncell, 3, 3, 3] toward -z, -y, -x; Dinv [ncell, 3, 3]) in block-row order
         (FP64 BILU0 only)."""
         import numpy as np
-        n = self.A.g.ncell
+        n = self.A.grid.ncell
         L = np.zeros((n, 3, 3, 3))
         D = np.zeros((n, 3, 3))
         _check(self.ctx, lib().rsv_precond_bilu0_factors(self.h, L.ctypes.data, D.ctypes.data))
