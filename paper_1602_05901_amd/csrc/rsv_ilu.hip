@@ -326,26 +326,56 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
     T *ring = (T *)smem;
     int32_t *tags = (int32_t *)(smem + (size_t)D * slot_elems * sizeof(T));
     int32_t *consumed = tags + D;
-    int32_t *tile_sh = consumed + 1;
-    int32_t *ftags = tile_sh + 1;   // per slot: step whose face values are in the slot (+1)
+    int32_t *tile_ring = consumed + 1;   // tile of the workgroup's k-th tile in entry k mod 4
+    int32_t *tile_tag = tile_ring + 4;   // k + 1 once entry k mod 4 holds the k-th tile
+    int32_t *ftags = tile_tag + 4;       // per slot: step whose face values are in the slot (+1)
     // exchange rows of the compute wave ([64][3] T) after the ring and its 64 tag words
     const uint32_t xch_off = (uint32_t)((size_t)D * slot_elems * sizeof(T) + 64 * sizeof(int32_t));
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
     int li, lj;
     lane_ij(L, li, lj);
     const int64_t frow = (int64_t)(nz + 7) * RW;
+    // Tiles come from an atomic ticket (-1 past the last tile).  The k-th tile
+    // of this workgroup is published by the first loader wave when it has
+    // issued its last step of tile k - 1 (so tiles are still claimed close to
+    // when a workgroup can take them up), and the loaders stream the next
+    // tile's first steps while the compute wave finishes the current one;
+    // there is no barrier between tiles.  Four entries: an entry is rewritten only after
+    // every wave has read it (no wave is more than one tile behind another,
+    // since the loaders run at most D < nsteps steps ahead of the compute wave).
+    auto take = [&]() -> int32_t {
+        const uint64_t tk = atomicAdd((unsigned long long *)a.ticket, 1ull) - a.ticket_base;
+        return (tk >= (uint64_t)NT) ? -1 : a.tile_order[DIR == 0 ? (int)tk : NT - 1 - (int)tk];
+    };
+    auto publish = [&](int k) {
+        const int32_t id = take();
+        __hip_atomic_store(&tile_ring[k & 3], id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __hip_atomic_store(&tile_tag[k & 3], k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     if (threadIdx.x == 0) *consumed = 0;
     for (int s = threadIdx.x; s < D; s += blockDim.x) tags[s] = ftags[s] = 0;
+    if (threadIdx.x < 4) tile_tag[threadIdx.x] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) publish(0);
     __syncthreads();
     int gstep = 0;   // running step count across tiles (tags are gstep + 1)
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const uint64_t tk = atomicAdd((unsigned long long *)a.ticket, 1ull) - a.ticket_base;
-            *tile_sh = (tk >= (uint64_t)NT) ? -1 : a.tile_order[DIR == 0 ? (int)tk : NT - 1 - (int)tk];
+    for (int k = 0;; ++k) {
+        if (__hip_atomic_load(&tile_tag[k & 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != k + 1) {
+            const uint64_t t0 = wall_clock64();
+            uint32_t n = 0;
+            bool gave_up = false;
+            while (__hip_atomic_load(&tile_tag[k & 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != k + 1) {
+                if (spin_guard(a.flags, t0, n, a.wait_limit)) {
+                    gave_up = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (gave_up) break;   // the error flag is set; every wave leaves
         }
-        __syncthreads();
-        const int T_ = *tile_sh;
-        __syncthreads();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int T_ = __hip_atomic_load(&tile_ring[k & 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (T_ < 0) break;
         const int tx = T_ % g.ntx, ty = T_ / g.ntx;
         const int64_t rowbase = (int64_t)T_ * nz;
@@ -499,6 +529,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 issue_data(A, t + 2 * NLOAD);
                 finish(B, t + NLOAD);
             }
+            if (wave == 1 && L == 0) publish(k + 1);
         } else {
             // ------------------------------------------------ compute wave
             const int d = li + lj;
@@ -636,7 +667,6 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             }
         }
         gstep += nsteps;
-        __syncthreads();
     }
 }
 
