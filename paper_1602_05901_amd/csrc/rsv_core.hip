@@ -231,12 +231,16 @@ void rsv_destroy(rsv_ctx *c)
     delete c;
 }
 
-rsv_status rsv_grid_create(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32_t ordering, rsv_grid **out)
+}  // extern "C"
+
+rsv_status grid_create_planes(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32_t ordering, int mx, int my,
+                              int mz, rsv_grid **out)
 {
     if (!c || !out) return set_err(c, RSV_ERR_ARG, "NULL argument");
     *out = nullptr;
     if (nx < 1 || ny < 1 || nz < 1) return set_err(c, RSV_ERR_ARG, "grid dimensions must be >= 1");
     if (ordering != RSV_BOTTOM_UP && ordering != RSV_TOP_DOWN) return set_err(c, RSV_ERR_ARG, "bad ordering");
+    if (mx < 1 || my < 1 || mz < 1) return set_err(c, RSV_ERR_ARG, "bad plane moduli");
     const int ntx = (nx + 7) / 8, nty = (ny + 7) / 8;
     const int64_t nslot = (int64_t)ntx * nty * nz * 64;
     if (nslot * 3 >= ((int64_t)1 << 31)) return set_err(c, RSV_ERR_ARG, "grid too large (3*padded cells must fit int32)");
@@ -246,20 +250,29 @@ rsv_status rsv_grid_create(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32
     g->geo = Geo{nx, ny, nz, ntx, nty, ordering, nslot};
     g->ncell = (int64_t)nx * ny * nz;
     g->nv = 3 * nslot;
-    g->nplanes = nx + ny + nz - 2;
-    // real slots bucketed by hyperplane i+j+k, ascending slot within a plane
+    g->nplanes = std::min(mx, nx) + std::min(my, ny) + std::min(mz, nz) - 2;
+    // real slots bucketed by plane (i mod mx) + (j mod my) + (k mod mz),
+    // ascending slot within a plane
     std::vector<int64_t> cnt(g->nplanes + 1, 0);
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) cnt[i + j + k + 1]++;
+            for (int i = 0; i < nx; ++i) cnt[i % mx + j % my + k % mz + 1]++;
     for (int p = 0; p < g->nplanes; ++p) cnt[p + 1] += cnt[p];
     g->plane_ptr = cnt;
     std::vector<int32_t> slots(g->ncell);
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int64_t s = 0; s < nslot; ++s) {
-        int gx, gy, k;
-        if (!cell_of(g->geo, s, gx, gy, k)) continue;
-        slots[fill[gx + gy + k]++] = (int32_t)s;
+    int li[64], lj[64];
+    for (int L = 0; L < 64; ++L) lane_ij(L, li[L], lj[L]);
+    int64_t s = 0;
+    for (int T = 0; T < ntx * nty; ++T) {
+        const int x0 = (T % ntx) * 8, y0 = (T / ntx) * 8;
+        for (int r = 0; r < nz; ++r)
+            for (int L = 0; L < 64; ++L, ++s) {
+                const int gx = x0 + li[L], gy = y0 + lj[L];
+                if (gx >= nx || gy >= ny) continue;
+                const int k = wrap_nz(r - li[L] - lj[L], nz);
+                slots[fill[gx % mx + gy % my + k % mz]++] = (int32_t)s;
+            }
     }
     rsv_status st = dev_alloc(c, (void **)&g->d_plane_slots, slots.size() * sizeof(int32_t));
     if (st != RSV_OK) { delete g; return st; }
@@ -271,6 +284,13 @@ rsv_status rsv_grid_create(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32
     }
     *out = g;
     return RSV_OK;
+}
+
+extern "C" {
+
+rsv_status rsv_grid_create(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32_t ordering, rsv_grid **out)
+{
+    return grid_create_planes(c, nx, ny, nz, ordering, nx, ny, nz, out);
 }
 
 void rsv_grid_destroy(rsv_grid *g)

@@ -253,6 +253,12 @@ rsv_status scal_to_host_async(rsv_ctx *c, int buf, int k0, int n);
 rsv_status scal_wait(rsv_ctx *c, int buf);
 rsv_status scal_set(rsv_ctx *c, int k0, const double *vals, int n);
 
+// A grid whose factorisation "hyperplanes" are (i mod mx) + (j mod my) + (k mod mz):
+// for a grid of independent boxes of mx x my x mz cells (rsv_grid_create: the
+// plain hyperplanes, mx = nx, my = ny, mz = nz).
+rsv_status grid_create_planes(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32_t ordering, int mx, int my,
+                              int mz, rsv_grid **out);
+
 // ------------------------------------------------------------------ preconditioners
 rsv_status bilu0_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
 // BILU0 of a grid made of independent boxes of btx x bty tiles (all couplings

@@ -609,7 +609,8 @@ struct RasBoxed : PcImpl {
             too_large = true;
             return set_err(c, RSV_ERR_ARG, "RAS boxes exceed the auxiliary grid's index range");
         }
-        rsv_status st = rsv_grid_create(c, SX * BXp, SY * BYp, SZ * EZ, RSV_BOTTOM_UP, &ga);
+        // factorisation planes inside each box (the boxes share no couplings)
+        rsv_status st = grid_create_planes(c, SX * BXp, SY * BYp, SZ * EZ, RSV_BOTTOM_UP, BXp, BYp, EZ, &ga);
         if (st != RSV_OK) return st;
         const Geo &G = ga->geo;
         st = alloc((void **)&d_box, h_box.size() * sizeof(int32_t));
