@@ -90,7 +90,8 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32")
+    ap.add_argument("--forms", default="gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,"
+                                          "gmres_ras64_dcgs2,gmres_bilu0_dcgs2")
     ap.add_argument("--net", default=None, help="trained U-Net weights for the learned form")
     ap.add_argument("--learned-steps", type=int, default=1500,
                     help="without --net: Adam steps of training on C4 systems before the timed steps (0: no learned form)")
@@ -142,6 +143,9 @@ def main():
         "gmres_bilu0": (rsv.GMRES, dict(type=rsv.PC_BILU0)),
         "gmres_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_BILU0, precision=rsv.FP32)),
     }
+    # the same GMRES forms with the delayed second Gram-Schmidt pass
+    for f in ("gmres_ras64", "gmres_bilu0"):
+        forms_all[f + "_dcgs2"] = forms_all[f]
     forms = [f for f in args.forms.split(",") if f]
     net = None
     lnk32 = None
@@ -197,7 +201,8 @@ def main():
             if prof:
                 # two events per recorded launch: only the classes the roofline needs
                 ctx.profile(True, classes=("spmv", "ilu_fwd", "ilu_bwd"))
-            st = rsv.solve(A, M, b, x, method=method, restart=30, tol=1e-8, maxit=10000)
+            st = rsv.solve(A, M, b, x, method=method, restart=30, tol=1e-8, maxit=10000,
+                           ortho=(rsv.DCGS2 if name.endswith("_dcgs2") else rsv.CGS2))
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             if prof:

@@ -66,6 +66,17 @@ typedef enum { RSV_FP64 = 0, RSV_FP32 = 1 } rsv_precision;
 
 typedef enum { RSV_GMRES = 0, RSV_BICGSTAB = 1, RSV_FGMRES = 2 } rsv_method;
 
+/* Orthogonalisation of the GMRES Arnoldi vectors.  RSV_CGS2: classical
+ * Gram-Schmidt applied twice at every step (three passes over the basis).
+ * RSV_DCGS2: the same two classical passes with the second one delayed by a
+ * step (Bielich, Langou, Thomas, Swirydowicz, Yamazaki, Boman, Parallel
+ * Computing 2022): one pass computes V^T [v_j, w], the next corrects v_j and
+ * projects w (two passes over the basis, one reduction per step); the
+ * Hessenberg column of the previous step is corrected on the host.  Both give
+ * the GMRES iterates of the Linear System / Solvers section up to rounding.
+ * FGMRES always uses RSV_CGS2. */
+typedef enum { RSV_CGS2 = 0, RSV_DCGS2 = 1 } rsv_ortho;
+
 typedef struct rsv_ctx rsv_ctx;
 typedef struct rsv_grid rsv_grid;
 typedef struct rsv_matrix rsv_matrix;
@@ -102,7 +113,8 @@ typedef struct rsv_solver_params {
     double rtol;         /* optional, 0 = off: stop when ||r|| <= rtol * ||r0|| */
     double atol;         /* optional, 0 = off: stop when ||r|| <= atol */
     int32_t record_history;  /* 1: keep per-step residual estimates (rsv_solve_history) */
-    int32_t reserved[7];
+    int32_t ortho;       /* GMRES: rsv_ortho (default RSV_CGS2) */
+    int32_t reserved[6];
 } rsv_solver_params;
 
 typedef struct rsv_stats {

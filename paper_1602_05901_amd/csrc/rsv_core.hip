@@ -420,6 +420,7 @@ void rsv_solver_params_default(rsv_solver_params *p)
     p->restart = 30;
     p->tol = 1e-8;
     p->maxit = 10000;
+    p->ortho = RSV_CGS2;
 }
 
 }  // extern "C"

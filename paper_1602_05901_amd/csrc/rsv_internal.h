@@ -115,7 +115,8 @@ enum {
     SC_H1 = 16,      // 64 slots: first CGS pass coefficients
     SC_H2 = 80,      // 64 slots: second pass
     SC_Y = 144,      // 64 slots: least-squares solution
-    SC_COUNT = 256
+    SC_DP = 256,     // DCGS2: 2K dots of the combined pass (V_i . V_{K-1}, then V_i . w), then 3 step scalars
+    SC_COUNT = 400
 };
 
 struct rsv_ctx {
@@ -239,6 +240,11 @@ rsv_status launch_mdot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int 
 rsv_status launch_upd_dot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0);
 rsv_status launch_upd_norm(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0);
 rsv_status launch_combine(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, int ky, double *u, int accumulate);
+// DCGS2 step with K = j + 1 basis vectors V_0..V_j and w = V_{j+1}: the dots
+// V_i . [V_j, w] into d_scal[k0 .. k0 + 2K), then the combined update (V_j
+// corrected, w projected and normalised; four step scalars after the dots)
+rsv_status launch_dcgs_dots(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, const double *w, int k0);
+rsv_status launch_dcgs_update(rsv_ctx *c, int64_t n, double *V, int64_t ldv, int K, double *w, int kd);
 // BiCGSTAB fused vector updates
 rsv_status launch_bicg_p(rsv_ctx *c, int64_t n, const double *r, const double *v, double beta, double omega, double *p);
 rsv_status launch_bicg_s(rsv_ctx *c, int64_t n, const double *r, const double *v, double *s, int k_alpha_num, int k_alpha_den, int k0);

@@ -293,6 +293,101 @@ __global__ __launch_bounds__(BS) void k_combine(int64_t n, const double *__restr
     }
 }
 
+// DCGS2, first pass of step j (K = j + 1): partial dots V_i . V_{K-1} and
+// V_i . w for i < K in one read of the basis.  Block b writes its 2K sums
+// at partials[b * 2K]: the K dots with V_{K-1}, then the K dots with w.
+template <int KB>
+__global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double *__restrict__ V, int64_t ldv, int K,
+                                                  const double *__restrict__ w, double *__restrict__ partials)
+{
+    __shared__ double red[2 * KB * (BS / 64)];
+    double ap[KB], aw[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) ap[i] = aw[i] = 0.0;
+    const double *p = V + (int64_t)(K - 1) * ldv;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
+        double v[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) v[i] = V[vrow(i, K, ldv) + e];
+        const double pe = p[e], we = w[e];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+            ap[i] += v[i] * pe;
+            aw[i] += v[i] * we;
+        }
+    }
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+        if (i < K) {
+            const double x = wave_sum(ap[i]), y = wave_sum(aw[i]);
+            if ((threadIdx.x & 63) == 0) {
+                red[i * nw + wv] = x;
+                red[(K + i) * nw + wv] = y;
+            }
+        }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * K) {
+        double t = 0.0;
+        for (int q = 0; q < nw; ++q) t += red[threadIdx.x * nw + q];
+        partials[(int64_t)blockIdx.x * 2 * K + threadIdx.x] = t;
+    }
+}
+
+// DCGS2, second pass of step j (K = j + 1).  From the reduced dots d (s_i =
+// d[i], t_i = d[K + i]) and omega = ||w||^2, every thread forms the same step
+// scalars: beta = sqrt(d[j] - s.s) (1 at j = 0), u_j = (d[K + j] - s.t) / beta,
+// d2 = omega - t.t - u_j^2.  Then per element
+//     V_j <- (V_j - sum_{i<j} s_i V_i) / beta            (the delayed second pass on V_j)
+//     w   <- (w - sum_{i<j} t_i V_i - u_j V_j) / sqrt(d2) (the first pass on w, normalised)
+// with w <- 0 when d2 <= 64 eps omega (the norm is lost to rounding: breakdown).
+// Block 0 stores beta, u_j, d2, omega at d[2K ..].
+template <int KB>
+__global__ __launch_bounds__(BS) void k_dcgs_upd(int64_t n, double *__restrict__ V, int64_t ldv, int K,
+                                                 double *__restrict__ w, double *__restrict__ sc, int kd)
+{
+    const double *d = sc + kd;
+    const int j = K - 1;
+    double cs[KB], ct[KB];
+    double ss = 0.0, st = 0.0, tt = 0.0;
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+        cs[i] = (i < j) ? d[i] : 0.0;
+        ct[i] = (i < j) ? d[K + i] : 0.0;
+        ss += cs[i] * cs[i];
+        st += cs[i] * ct[i];
+        tt += ct[i] * ct[i];
+    }
+    const double omega = sc[SC_W0];
+    const double a = d[j] - ss;
+    const double beta = (j == 0 || !(a > 0.0)) ? 1.0 : sqrt(a);
+    const double ib = 1.0 / beta;
+    const double uj = (d[K + j] - st) * ib;
+    const double d2 = omega - (tt + uj * uj);
+    const double scale = (d2 > 64.0 * __DBL_EPSILON__ * omega) ? 1.0 / sqrt(d2) : 0.0;
+    double *p = V + (int64_t)j * ldv;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
+        double v[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) v[i] = V[vrow(i, K, ldv) + e];
+        double q = p[e], we = w[e];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+            q -= cs[i] * v[i];
+            we -= ct[i] * v[i];
+        }
+        q *= ib;
+        if (j > 0) p[e] = q;
+        w[e] = (we - uj * q) * scale;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[kd + 2 * K] = beta;
+        sc[kd + 2 * K + 1] = uj;
+        sc[kd + 2 * K + 2] = d2;
+        sc[kd + 2 * K + 3] = omega;
+    }
+}
+
 __global__ __launch_bounds__(BS) void k_bicg_p(int64_t n, const double *__restrict__ r, const double *__restrict__ v,
                                                double beta, double omega, double *__restrict__ p)
 {
@@ -539,6 +634,36 @@ rsv_status launch_combine(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, i
         KB_DISPATCH(K, L_CMB)
     }
 #undef L_CMB
+    RSV_LAUNCH(c);
+    return RSV_OK;
+}
+
+rsv_status launch_dcgs_dots(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, const double *w, int k0)
+{
+    if (K < 1 || K > KMAX || k0 + 2 * K + 4 > SC_COUNT) return set_err(c, RSV_ERR_ARG, "dcgs K");
+    const int nb = mvec_blocks(n);
+    rsv_status s = partials_reserve(c, (int64_t)nb * 2 * K);
+    if (s != RSV_OK) return s;
+#define L_DD(KB) hipLaunchKernelGGL(k_dcgs_dots<KB>, dim3(nb), dim3(BS), 0, c->stream, n, V, ldv, K, w, c->d_partials)
+    {
+        ProfScope ps(c, RSV_K_ORTHO);
+        KB_DISPATCH(K, L_DD)
+    }
+#undef L_DD
+    RSV_LAUNCH(c);
+    return launch_reduce(c, nb, 2 * K, k0);
+}
+
+rsv_status launch_dcgs_update(rsv_ctx *c, int64_t n, double *V, int64_t ldv, int K, double *w, int kd)
+{
+    if (K < 1 || K > KMAX || kd + 2 * K + 4 > SC_COUNT) return set_err(c, RSV_ERR_ARG, "dcgs K");
+    const int nb = mvec_blocks(n);
+#define L_DU(KB) hipLaunchKernelGGL(k_dcgs_upd<KB>, dim3(nb), dim3(BS), 0, c->stream, n, V, ldv, K, w, c->d_scal, kd)
+    {
+        ProfScope ps(c, RSV_K_ORTHO);
+        KB_DISPATCH(K, L_DU)
+    }
+#undef L_DU
     RSV_LAUNCH(c);
     return RSV_OK;
 }

@@ -4,7 +4,9 @@
 //
 // GMRES(m): right preconditioned (Saad & Schultz 1986), classical
 // Gram-Schmidt applied twice (CGS2) on the device with fused multi-dot /
-// update kernels, Givens rotations on the host (at most 61 scalars per step).
+// update kernels, or the same two passes with the second delayed by a step
+// (DCGS2: one reduction and two reads of the basis per step), Givens
+// rotations on the host (at most 61 scalars per step).
 // BiCGSTAB: right preconditioned (van der Vorst 1992), fused vector updates
 // and dot products.  The reported residual is always recomputed in FP64 as
 // ||b - A x|| / ||b||.  Vectors live in the tile-lane layout for the whole
@@ -115,7 +117,7 @@ static rsv_status true_resid(Solve &S, const double *b, const double *x, double 
 }
 
 static rsv_status gmres(Solve &S, PcImpl *P, PcImpl *FB, double theta, int m, int64_t maxit, bool flexible,
-                        double *b, double *x, double *pool)
+                        bool dcgs, double *b, double *x, double *pool)
 {
     rsv_ctx *c = S.c;
     const int64_t n = S.n;
@@ -149,7 +151,82 @@ static rsv_status gmres(Solve &S, PcImpl *P, PcImpl *FB, double theta, int m, in
         int jdone = 0;
         bool fb_rest = false;
         consecutive_fb = 0;
-        if (!flexible) {
+        if (!flexible && dcgs) {
+            // DCGS2.  Step j leaves V[j] final and V[j + 1] once projected
+            // and normalised (tentative); its Hessenberg column is tentative
+            // until step j + 1 has measured how far V[j + 1] was from the
+            // span of V[0..j] (dots s = V[0..j]^T V[j + 1]).  With
+            // V[j + 1] = sum_i s_i V_i + beta q_{j+1}, the final column j is
+            // h + gamma s on rows 0..j and gamma beta on row j + 1, and the
+            // product of the tentative vector projects as
+            // A M^-1 q_{j+1} = (w - Q Hbar s) / beta, so its column is
+            // (u - Hbar s) / beta with u = Q^T w.  The convergence test of a
+            // step uses its tentative column; a stopping step keeps it (its
+            // basis vectors V[0..j] are all final).  Speculation as for CGS2:
+            // a discarded step writes only V[j + 1], V[j + 2] and scratch.
+            auto enqueue = [&](int j) -> rsv_status {
+                double *w = V + (int64_t)(j + 1) * n;
+                rsv_status e = pc_apply(c, P, n, V + (int64_t)j * n, zt);
+                if (e == RSV_OK) e = launch_spmv(c, *S.geo, S.M->d_A, SPMV_NORM, zt, w, nullptr, 0, 0, SC_W0);
+                if (e == RSV_OK) e = launch_dcgs_dots(c, n, V, n, j + 1, w, SC_DP);
+                if (e == RSV_OK) e = launch_dcgs_update(c, n, V, n, j + 1, w, SC_DP);
+                if (e == RSV_OK) e = scal_to_host_async(c, j & 1, SC_DP, 2 * (j + 1) + 4);
+                return e;
+            };
+            std::vector<double> Hraw((size_t)(m + 1) * m, 0.0), ht(m + 2, 0.0), hc(m + 2, 0.0);
+            std::vector<double> cs_t(m + 1), sn_t(m + 1), g_t(m + 2);
+            auto Hr = [&](int col, int row) -> double & { return Hraw[(size_t)col * (m + 1) + row]; };
+            double gam_prev = 0.0, est = beta;
+            if ((s = enqueue(0)) != RSV_OK) return s;
+            for (int j = 0; j < m; ++j) {
+                const bool ahead = j + 1 < m && its + 1 < maxit && !S.ctl.met(0.25 * est);
+                if (ahead && (s = enqueue(j + 1)) != RSV_OK) return s;
+                if ((s = scal_wait(c, j & 1)) != RSV_OK) return s;
+                const int K = j + 1;
+                const double *d = c->h_spec + (size_t)(j & 1) * SC_COUNT + SC_DP;
+                const double bj = d[2 * K], uj = d[2 * K + 1], d2 = d[2 * K + 2], om = d[2 * K + 3];
+                bool finite = std::isfinite(bj) && std::isfinite(uj) && std::isfinite(d2) && std::isfinite(om);
+                for (int i = 0; i < 2 * K; ++i) finite = finite && std::isfinite(d[i]);
+                if (!finite) return set_err(c, RSV_ERR_NAN, "non-finite Arnoldi column");
+                if (j >= 1) {
+                    // column j - 1 becomes final; rotate it with the final rotations
+                    for (int i = 0; i < j; ++i) Hr(j - 1, i) = ht[i] + gam_prev * d[i];
+                    Hr(j - 1, j) = gam_prev * bj;
+                    std::fill(hc.begin(), hc.end(), 0.0);
+                    for (int i = 0; i <= j; ++i) hc[i] = Hr(j - 1, i);
+                    givens_step(j - 1, hc.data(), cs.data(), sn.data(), g.data());
+                    for (int i = 0; i <= j; ++i) Hc(j - 1, i) = hc[i];
+                }
+                const bool happy = !(d2 > 64.0 * 2.220446049250313e-16 * om);
+                const double gam = happy ? 0.0 : std::sqrt(d2) / bj;
+                std::fill(ht.begin(), ht.end(), 0.0);
+                for (int k = 0; k <= j; ++k) {
+                    double a = (k < j) ? d[K + k] : uj;
+                    for (int i = 0; i < j; ++i) a -= Hr(i, k) * d[i];
+                    ht[k] = a / bj;
+                }
+                ht[j + 1] = gam;
+                hc = ht;
+                cs_t = cs;
+                sn_t = sn;
+                g_t = g;
+                givens_step(j, hc.data(), cs_t.data(), sn_t.data(), g_t.data());
+                ++its;
+                jdone = j + 1;
+                est = std::fabs(g_t[j + 1]);
+                if (S.record) S.hist->push_back(est / nb);
+                if (!std::isfinite(est)) return set_err(c, RSV_ERR_NAN, "non-finite residual estimate");
+                if (S.ctl.met(est) || its >= maxit || happy || j + 1 == m) {
+                    for (int i = 0; i <= j + 1; ++i) Hc(j, i) = hc[i];
+                    cs = cs_t;
+                    sn = sn_t;
+                    g = g_t;
+                    break;
+                }
+                gam_prev = gam;
+                if (!ahead && (s = enqueue(j + 1)) != RSV_OK) return s;
+            }
+        } else if (!flexible) {
             // The host's work on step j (Givens rotation, convergence test)
             // overlaps the device's step j + 1, which is enqueued before step
             // j's scalars are awaited -- except when the estimate is within a
@@ -461,6 +538,7 @@ rsv_status rsv_solve(rsv_matrix *A, rsv_precond *P, const rsv_solver_params *p, 
         return st->status = set_err(c, RSV_ERR_ARG, "restart must be in [1, 60]");
     if (p->method != RSV_GMRES && p->method != RSV_FGMRES && p->method != RSV_BICGSTAB)
         return st->status = set_err(c, RSV_ERR_ARG, "bad method");
+    if (p->ortho != RSV_CGS2 && p->ortho != RSV_DCGS2) return st->status = set_err(c, RSV_ERR_ARG, "bad ortho");
     if (p->maxit < 0 || !(p->tol >= 0.0)) return st->status = set_err(c, RSV_ERR_ARG, "bad tol/maxit");
     PcImpl *impl = P ? P->impl : nullptr;
     if (P && P->p.type == RSV_PC_LEARNED && p->method != RSV_FGMRES)
@@ -504,7 +582,8 @@ rsv_status rsv_solve(rsv_matrix *A, rsv_precond *P, const rsv_solver_params *p, 
     } else {
         const bool flex = (p->method == RSV_FGMRES);
         PcImpl *fb = (P && P->fallback) ? P->fallback : impl;
-        rc = gmres(S, impl, fb, P ? P->p.theta : 0.99, m, p->maxit, flex, bt, xt, pool);
+        rc = gmres(S, impl, fb, P ? P->p.theta : 0.99, m, p->maxit, flex, !flex && p->ortho == RSV_DCGS2, bt, xt,
+                   pool);
     }
     if (rc < 0) return st->status = rc;
     s = launch_tl_to_nat(c, A->g->geo, xt, x, 1.0, 0.0);

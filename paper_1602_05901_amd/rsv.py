@@ -20,6 +20,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 PC_NONE, PC_BILU0, PC_RAS, PC_LEARNED = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 GMRES, BICGSTAB, FGMRES = 0, 1, 2
+CGS2, DCGS2 = 0, 1
 
 vp, i32, i64, dbl, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
 
@@ -32,7 +33,7 @@ class PcParams(ctypes.Structure):
 
 class SolverParams(ctypes.Structure):
     _fields_ = [("method", i32), ("restart", i32), ("tol", dbl), ("maxit", i64), ("rtol", dbl), ("atol", dbl),
-                ("record_history", i32), ("reserved", i32 * 7)]
+                ("record_history", i32), ("ortho", i32), ("reserved", i32 * 6)]
 
 
 class Stats(ctypes.Structure):

@@ -367,13 +367,14 @@ def test_ras_apply_parity(rsv, ctx, dims, parts, ov, prec, shift, pipelined):
 
 # ---------------------------------------------------------------- solves
 
-def run_solve(rsv, ctx, cfg, pc, method, oracle_pc, restart=30, maxit=5000, tol=1e-8, **pkw):
+def run_solve(rsv, ctx, cfg, pc, method, oracle_pc, restart=30, maxit=5000, tol=1e-8, ortho=0, **pkw):
     S = Sys(rsv, ctx, cfg)
     xt = I.x_true(cfg)
     b = dev(S.Ao.spmv(xt))   # the oracle's b: both sides solve the same system
     M = rsv.Precond(S.A, type=pc, **pkw) if pc != rsv.PC_NONE else None
     x = torch.zeros_like(b)
-    st = rsv.solve(S.A, M, b, x, method=method, restart=restart, tol=tol, maxit=maxit, record_history=1)
+    st = rsv.solve(S.A, M, b, x, method=method, restart=restart, tol=tol, maxit=maxit, record_history=1,
+                   ortho=ortho)
     xg = x.cpu().numpy()
     bo = b.cpu().numpy()
     relres = np.linalg.norm(bo - S.Ao.spmv(xg)) / np.linalg.norm(bo)
@@ -478,7 +479,67 @@ def test_exact_preconditioner_one_step(rsv, ctx):
         assert st["status"] == 0 and st["its"] == 1 and relres <= 1e-10
 
 
-@pytest.mark.parametrize("method", ["bicgstab_bilu0", "gmres_ras"])
+# ---------------------------------------------------------------- DCGS2
+# The delayed second pass changes only the rounding of the Arnoldi process:
+# the iterates are the GMRES iterates, so the oracle's CGS2 GMRES is the
+# reference, with the same bars as above.
+
+@pytest.mark.parametrize("seed", [0, 3, 7])
+@pytest.mark.parametrize("restart", [30, 5, 1])
+def test_gmres_dcgs2_bilu0_C1(rsv, ctx, seed, restart):
+    cfg = I.preset("C1", seed=seed)
+    st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_BILU0, rsv.GMRES, O.ILU, restart=restart,
+                                        ortho=rsv.DCGS2)
+    check_solve(st, ref, xg, relres)
+
+
+def test_gmres_dcgs2_ras_small(rsv, ctx):
+    cfg = I.GenConfig(32, 32, 16, I.LNK_LAYERED, 2.0, 1.5, 2.0, 4, 1e3, 1.0, 0)
+    st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_RAS, rsv.GMRES,
+                                        lambda A: O.RAS(A, (32, 32, 16), (4, 4, 4), 1), ortho=rsv.DCGS2)
+    check_solve(st, ref, xg, relres)
+
+
+def test_gmres_dcgs2_fp32_factors(rsv, ctx):
+    cfg = I.GenConfig(32, 32, 16, I.LNK_IID, 3.0, 0.0, 2.0, 0, 1e3, 1.0, 0)
+    st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_BILU0, rsv.GMRES, lambda A: (O.ILU(A), "fp32"),
+                                        precision=rsv.FP32, ortho=rsv.DCGS2)
+    check_solve(st, ref, xg, relres, hist_rtol=1e-5)
+
+
+def test_gmres_dcgs2_unpreconditioned_and_edges(rsv, ctx):
+    """No preconditioner (many steps per cycle, slow decay), b = 0, maxit
+    exhaustion at a step inside a cycle, the exact preconditioner (the second
+    vector vanishes: breakdown after one step), and a bad ortho value."""
+    cfg = cfg_of((6, 5, 4), seed=17)
+    S = Sys(rsv, ctx, cfg)
+    n = 3 * cfg.ncell
+    b = dev(I.test_vector(18, n))
+    bo = b.cpu().numpy()
+    x = torch.zeros_like(b)
+    st = rsv.solve(S.A, None, b, x, method=rsv.GMRES, restart=30, tol=1e-10, maxit=2000, ortho=rsv.DCGS2,
+                   record_history=1)
+    assert st["status"] == 0
+    assert np.linalg.norm(bo - S.Ao.spmv(x.cpu().numpy())) / np.linalg.norm(bo) <= 1e-10
+    ref = O.gmres(S.Ao, bo, pc=None, m=30, tol=1e-10, maxit=2000, hist=True)
+    assert abs(st["its"] - ref["its"]) <= max(2, 0.05 * ref["its"])
+    assert np.allclose(st["hist"][:20], ref["hist"][:20], rtol=1e-8, atol=0)
+    x = dev(np.ones(n))
+    st = rsv.solve(S.A, None, torch.zeros(n, dtype=torch.float64, device="cuda"), x, method=rsv.GMRES,
+                   ortho=rsv.DCGS2)
+    assert st["status"] == 0 and float(x.abs().max()) == 0.0
+    x = torch.zeros_like(b)
+    st = rsv.solve(S.A, None, b, x, method=rsv.GMRES, restart=5, tol=1e-14, maxit=7, ortho=rsv.DCGS2)
+    assert st["status"] == rsv.NOT_CONVERGED and st["its"] == 7 and st["final_relres"] > 0
+    with pytest.raises(rsv.RsvError):
+        rsv.solve(S.A, None, b, x, method=rsv.GMRES, ortho=2)
+    S.close()
+    cfg = cfg_of((40, 1, 1), seed=19, sigma=2.0)
+    st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_BILU0, rsv.GMRES, O.ILU, tol=1e-10, ortho=rsv.DCGS2)
+    assert st["status"] == 0 and st["its"] == 1 and relres <= 1e-10
+
+
+@pytest.mark.parametrize("method", ["bicgstab_bilu0", "gmres_ras", "gmres_ras_dcgs2"])
 def test_C2_full_solve(rsv, ctx, method):
     """The C2 workload at full size, as the benchmark runs it."""
     cfg = I.preset("C2", seed=0)
@@ -487,7 +548,8 @@ def test_C2_full_solve(rsv, ctx, method):
         st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_BILU0, rsv.BICGSTAB, O.ILU)
     else:
         st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_RAS, rsv.GMRES,
-                                            lambda A: O.RAS(A, (128, 128, 64), (4, 4, 4), 1))
+                                            lambda A: O.RAS(A, (128, 128, 64), (4, 4, 4), 1),
+                                            ortho=(rsv.DCGS2 if method.endswith("dcgs2") else rsv.CGS2))
     check_solve(st, ref, xg, relres, its_band=(method != "bicgstab_bilu0"),
                 hist_steps=(6 if method == "bicgstab_bilu0" else 10))
     assert rel(xg, xt) <= 1e-5
