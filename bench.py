@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,"
-                                          "gmres_ras64_dcgs2,gmres_bilu0_dcgs2")
+                                          "gmres_ras64_dcgs2,gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2")
     ap.add_argument("--net", default=None, help="trained U-Net weights for the learned form")
     ap.add_argument("--learned-steps", type=int, default=1500,
                     help="without --net: Adam steps of training on C4 systems before the timed steps (0: no learned form)")
@@ -144,7 +144,7 @@ def main():
         "gmres_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_BILU0, precision=rsv.FP32)),
     }
     # the same GMRES forms with the delayed second Gram-Schmidt pass
-    for f in ("gmres_ras64", "gmres_bilu0"):
+    for f in ("gmres_ras64", "gmres_bilu0", "gmres_ras64_fp32"):
         forms_all[f + "_dcgs2"] = forms_all[f]
     forms = [f for f in args.forms.split(",") if f]
     net = None
