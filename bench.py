@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,"
-                                          "gmres_ras64_dcgs2,gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2")
+                                          "gmres_ras64_dcgs2,gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64")
     ap.add_argument("--net", default=None, help="trained U-Net weights for the learned form")
     ap.add_argument("--learned-steps", type=int, default=1500,
                     help="without --net: Adam steps of training on C4 systems before the timed steps (0: no learned form)")
@@ -140,6 +140,7 @@ def main():
         "gmres_ras64": (rsv.GMRES, dict(type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1)),
         "gmres_ras64_fp32": (rsv.GMRES, dict(type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1,
                                               precision=rsv.FP32)),
+        "bicgstab_ras64": (rsv.BICGSTAB, dict(type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1)),
         "gmres_bilu0": (rsv.GMRES, dict(type=rsv.PC_BILU0)),
         "gmres_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_BILU0, precision=rsv.FP32)),
     }

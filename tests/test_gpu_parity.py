@@ -430,6 +430,20 @@ def test_gmres_ras_small(rsv, ctx):
     check_solve(st, ref, xg, relres)
 
 
+def test_bicgstab_ras_small(rsv, ctx):
+    cfg = I.GenConfig(32, 32, 16, I.LNK_LAYERED, 2.0, 1.5, 2.0, 4, 1e3, 1.0, 0)
+    st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_RAS, rsv.BICGSTAB,
+                                        lambda A: O.RAS(A, (32, 32, 16), (4, 4, 4), 1))
+    check_solve(st, ref, xg, relres, its_band=False, hist_steps=6)
+
+
+def test_bicgstab_fp32_factors(rsv, ctx):
+    cfg = I.GenConfig(32, 32, 16, I.LNK_IID, 3.0, 0.0, 2.0, 0, 1e3, 1.0, 0)
+    st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_BILU0, rsv.BICGSTAB, lambda A: (O.ILU(A), "fp32"),
+                                        precision=rsv.FP32)
+    check_solve(st, ref, xg, relres, its_band=False, hist_steps=4, hist_rtol=1e-5)
+
+
 def test_gmres_fp32_factors(rsv, ctx):
     cfg = I.GenConfig(32, 32, 16, I.LNK_IID, 3.0, 0.0, 2.0, 0, 1e3, 1.0, 0)
     st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_BILU0, rsv.GMRES, lambda A: (O.ILU(A), "fp32"),
