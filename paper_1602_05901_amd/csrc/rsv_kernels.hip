@@ -364,7 +364,7 @@ __global__ __launch_bounds__(BS) void k_dcgs_upd(int64_t n, double *__restrict__
     const double ib = 1.0 / beta;
     const double uj = (d[K + j] - st) * ib;
     const double d2 = omega - (tt + uj * uj);
-    const double scale = (d2 > 64.0 * __DBL_EPSILON__ * omega) ? 1.0 / sqrt(d2) : 0.0;
+    const double scale = (d2 > DCGS_LOST * omega) ? 1.0 / sqrt(d2) : 0.0;
     double *p = V + (int64_t)j * ldv;
     for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS) {
         double v[KB];

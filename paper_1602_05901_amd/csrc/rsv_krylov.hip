@@ -197,7 +197,7 @@ static rsv_status gmres(Solve &S, PcImpl *P, PcImpl *FB, double theta, int m, in
                     givens_step(j - 1, hc.data(), cs.data(), sn.data(), g.data());
                     for (int i = 0; i <= j; ++i) Hc(j - 1, i) = hc[i];
                 }
-                const bool happy = !(d2 > 64.0 * 2.220446049250313e-16 * om);
+                const bool happy = !(d2 > DCGS_LOST * om);
                 const double gam = happy ? 0.0 : std::sqrt(d2) / bj;
                 std::fill(ht.begin(), ht.end(), 0.0);
                 for (int k = 0; k <= j; ++k) {

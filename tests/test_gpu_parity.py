@@ -538,6 +538,14 @@ def test_gmres_dcgs2_unpreconditioned_and_edges(rsv, ctx):
     ref = O.gmres(S.Ao, bo, pc=None, m=30, tol=1e-10, maxit=2000, hist=True)
     assert abs(st["its"] - ref["its"]) <= max(2, 0.05 * ref["its"])
     assert np.allclose(st["hist"][:20], ref["hist"][:20], rtol=1e-8, atol=0)
+    # the longest cycle (60 basis vectors: the widest multi-vector kernels)
+    x = torch.zeros_like(b)
+    st = rsv.solve(S.A, None, b, x, method=rsv.GMRES, restart=60, tol=1e-10, maxit=2000, ortho=rsv.DCGS2,
+                   record_history=1)
+    ref = O.gmres(S.Ao, bo, pc=None, m=60, tol=1e-10, maxit=2000, hist=True)
+    assert st["status"] == 0 and abs(st["its"] - ref["its"]) <= max(2, 0.05 * ref["its"])
+    assert np.linalg.norm(bo - S.Ao.spmv(x.cpu().numpy())) / np.linalg.norm(bo) <= 1e-10
+    assert np.allclose(st["hist"][:40], ref["hist"][:40], rtol=1e-8, atol=0)
     x = dev(np.ones(n))
     st = rsv.solve(S.A, None, torch.zeros(n, dtype=torch.float64, device="cuda"), x, method=rsv.GMRES,
                    ortho=rsv.DCGS2)
