@@ -247,6 +247,10 @@ def main():
         kms = {k: sum(r["kernels_" + form][k][0] for r in res) for k in rsv.K_NAMES}
         kcnt = {k: sum(r["kernels_" + form][k][1] for r in res) for k in rsv.K_NAMES}
         ab = dict(ab_global)
+        if forms_all[form][0] != rsv.BICGSTAB:
+            # GMRES products (y = A z with ||y||^2) read no third vector; the few
+            # residual launches per solve that do read b are counted the same
+            ab["spmv"] = ab_global["spmv_plain"]
         if forms_all[form][1].get("type") == rsv.PC_RAS:
             # the sweeps of this form are the local RAS sweeps
             pk = forms_all[form][1]
