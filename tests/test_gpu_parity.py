@@ -577,6 +577,70 @@ def test_C2_full_solve(rsv, ctx, method):
     assert rel(xg, xt) <= 1e-5
 
 
+# ---------------------------------------------------------------- the larger workloads at full size
+
+def test_C3_fp32_form_full(rsv, ctx):
+    """The precision workload (256x256x128, ln k ~ N(0,3)) at full size, as the
+    benchmark launches it: the FP32-factor BILU0 apply against the oracle's
+    FP32 sweeps; then GMRES(30) with FP32 factors and with FP64 factors, each
+    checked by a residual the oracle recomputes on the host, and the two
+    solutions against each other."""
+    cfg = I.preset("C3", seed=0)
+    log("C3 full", cfg.nx, cfg.ny, cfg.nz)
+    S = Sys(rsv, ctx, cfg)
+    n = 3 * cfg.ncell
+    r = I.test_vector(31, n)
+    M32 = rsv.Precond(S.A, type=rsv.PC_BILU0, precision=rsv.FP32)
+    z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    M32.apply(dev(r), z)
+    F = O.ILU(S.Ao)
+    assert rel(z.cpu().numpy(), F.apply(r, fp32=True)) <= 2e-6
+    del F
+    xt = I.x_true(cfg)
+    bo = S.Ao.spmv(xt)
+    b = dev(bo)
+    xs = {}
+    for name, M in (("fp32", M32), ("fp64", rsv.Precond(S.A, type=rsv.PC_BILU0))):
+        x = torch.zeros_like(b)
+        st = rsv.solve(S.A, M, b, x, method=rsv.GMRES, restart=30, tol=1e-8, maxit=5000)
+        xs[name] = x.cpu().numpy()
+        relres = np.linalg.norm(bo - S.Ao.spmv(xs[name])) / np.linalg.norm(bo)
+        log("C3", name, "its", st["its"], "relres (host)", relres, "err vs x_true", rel(xs[name], xt))
+        assert st["status"] == 0 and relres <= 1e-8
+        assert abs(st["final_relres"] - relres) <= 1e-3 * relres + 1e-15
+        M.close()
+    assert rel(xs["fp32"], xs["fp64"]) <= 1e-6
+    S.close()
+
+
+def test_C5_full(rsv, ctx):
+    """The largest workload (512x512x128, 100.7 M unknowns, channelised
+    permeability) at full size: every SpMV output against the oracle, and the
+    GMRES(30) + BILU0 solve checked by a residual the oracle recomputes."""
+    cfg = I.preset("C5", seed=0)
+    log("C5 full", cfg.nx, cfg.ny, cfg.nz)
+    S = Sys(rsv, ctx, cfg)
+    n = 3 * cfg.ncell
+    x = I.test_vector(41, n)
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    S.A.spmv(dev(x), y)
+    ref = S.Ao.spmv(x)
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    del x, y, ref
+    xt = I.x_true(cfg)
+    bo = S.Ao.spmv(xt)
+    b = dev(bo)
+    M = rsv.Precond(S.A, type=rsv.PC_BILU0)
+    xg = torch.zeros_like(b)
+    st = rsv.solve(S.A, M, b, xg, method=rsv.GMRES, restart=30, tol=1e-8, maxit=5000)
+    xh = xg.cpu().numpy()
+    relres = np.linalg.norm(bo - S.Ao.spmv(xh)) / np.linalg.norm(bo)
+    log("C5 its", st["its"], "relres (host)", relres, "err vs x_true", rel(xh, xt))
+    assert st["status"] == 0 and relres <= 1e-8
+    assert abs(st["final_relres"] - relres) <= 1e-3 * relres + 1e-15
+    M.close(); S.close()
+
+
 # ---------------------------------------------------------------- kernel timing
 
 def test_profile_classes(rsv, ctx):
