@@ -11,32 +11,75 @@ namespace {
 constexpr int BS = 256;          // threads per block for streaming kernels
 constexpr int RED_T = 1024;      // threads of the final reduction
 
-// Sum of v over the 64 lanes of a wave (butterfly; every lane gets the sum).
-__device__ inline double wave_sum(double v)
+// One stage of the halving reduction of H pairs of per-lane values: lanes
+// whose bit `off` is set keep the upper half, the others the lower half, and
+// each adds its partner's copy of the half it keeps; then the next stage.
+template <int H>
+__device__ __forceinline__ void halve(double *acc, int lane, int off)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    if constexpr (H >= 1) {
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const double lo = acc[i], hi = acc[i + H];
+            acc[i] = (upper ? hi : lo) + __shfl_xor(upper ? lo : hi, off, 64);
+        }
+        halve<H / 2>(acc, lane, off >> 1);
+    }
 }
 
-// Sums of K per-thread values over the block, one barrier for all K: each
-// wave reduces its K values by butterflies, the waves' results meet in LDS
-// (red[K][nw]) and thread i < K adds them in wave order.  Writes out[i].
+constexpr int pow2_at_least(int k) { return k <= 1 ? 1 : 2 * pow2_at_least((k + 1) / 2); }
+constexpr int log2_exact(int p) { return p <= 1 ? 0 : 1 + log2_exact(p / 2); }
+
+// Wave part of a block sum of the first K of KB per-lane values (KB <= 64):
+// value i summed over the wave's 64 lanes goes to red[(base + i) * nw + wave].
+// The values (padded with zeros to P, a power of two) are halved over log2 P
+// stages, so each shuffle moves a value that is still needed (P - 1 shuffles
+// instead of 6 per value), and the remaining 64 / P lanes holding a value
+// finish with plain butterflies.  Every value meets its partners in the same
+// pairwise tree as a butterfly (a + b and b + a are the same double), so the
+// sums equal the butterfly's bit for bit.
 template <int KB>
-__device__ inline void block_sums(const double *acc, int K, double *red, double *out)
+__device__ inline void wave_sums_to(const double *acc_in, int K, double *red, int base)
 {
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    constexpr int P = pow2_at_least(KB);
+    constexpr int S = log2_exact(P);
+    constexpr int off = 32 >> S;   // butterfly distance left after the halving (0 when P = 64)
+    static_assert(P <= 64, "at most 64 values per lane");
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double acc[P];
 #pragma unroll
-    for (int i = 0; i < KB; ++i)
-        if (i < K) {
-            const double v = wave_sum(acc[i]);
-            if ((threadIdx.x & 63) == 0) red[i * nw + w] = v;
-        }
-    __syncthreads();
-    if ((int)threadIdx.x < K) {
+    for (int i = 0; i < P; ++i) acc[i] = (i < KB) ? acc_in[i] : 0.0;
+    halve<P / 2>(acc, lane, 32);
+    double v = acc[0];
+#pragma unroll
+    for (int o = off; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    int idx = 0;   // the value this lane now holds
+#pragma unroll
+    for (int st = 0; st < S; ++st)
+        if (lane & (32 >> st)) idx += (P / 2) >> st;
+    if ((lane & (off ? 2 * off - 1 : 0)) == 0 && idx < K) red[(base + idx) * nw + w] = v;
+}
+
+// Block part, after a barrier: thread i < nout adds the waves' sums in wave order.
+__device__ inline void block_finish(int nout, const double *red, double *out)
+{
+    const int nw = blockDim.x >> 6;
+    if ((int)threadIdx.x < nout) {
         double t = 0.0;
         for (int q = 0; q < nw; ++q) t += red[threadIdx.x * nw + q];
         out[threadIdx.x] = t;
     }
+}
+
+// Sums of K per-thread values over the block, one barrier for all K (red holds
+// KB * waves doubles).  Writes out[i], i < K.
+template <int KB>
+__device__ inline void block_sums(const double *acc, int K, double *red, double *out)
+{
+    wave_sums_to<KB>(acc, K, red, 0);
+    __syncthreads();
+    block_finish(K, red, out);
 }
 
 // Sum of v over the block (deterministic butterfly + fixed-order LDS pass);
@@ -316,22 +359,10 @@ __global__ __launch_bounds__(BS) void k_dcgs_dots(int64_t n, const double *__res
             aw[i] += v[i] * we;
         }
     }
-    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int i = 0; i < KB; ++i)
-        if (i < K) {
-            const double x = wave_sum(ap[i]), y = wave_sum(aw[i]);
-            if ((threadIdx.x & 63) == 0) {
-                red[i * nw + wv] = x;
-                red[(K + i) * nw + wv] = y;
-            }
-        }
+    wave_sums_to<KB>(ap, K, red, 0);
+    wave_sums_to<KB>(aw, K, red, K);
     __syncthreads();
-    if ((int)threadIdx.x < 2 * K) {
-        double t = 0.0;
-        for (int q = 0; q < nw; ++q) t += red[threadIdx.x * nw + q];
-        partials[(int64_t)blockIdx.x * 2 * K + threadIdx.x] = t;
-    }
+    block_finish(2 * K, red, partials + (int64_t)blockIdx.x * 2 * K);
 }
 
 // DCGS2, second pass of step j (K = j + 1).  From the reduced dots d (s_i =
