@@ -479,8 +479,10 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     // Backward FP64 sweep (three loaders): rows become valid in step
                     // order, so first wait (in LDS) until the previous step has been
                     // delivered; then only the loader of the oldest pending step
-                    // polls device memory, with exponential backoff.  (Measured:
-                    // the first is faster forward, the second backward.)
+                    // polls device memory, with exponential backoff up to four
+                    // 512-cycle sleeps.  (Measured: the first is faster forward,
+                    // the second backward; a cap of 16 sleeps made the C2
+                    // backward sweep 4 % slower.)
                     const uint64_t t0 = wall_clock64();
                     uint32_t n = 0;
                     constexpr bool serial = NLOAD < 7;
@@ -501,7 +503,7 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                             __builtin_amdgcn_s_sleep(2);
                         } else {
                             for (int q = 0; q < backoff; ++q) __builtin_amdgcn_s_sleep(8);
-                            backoff = backoff < 16 ? 2 * backoff : 16;
+                            backoff = backoff < 4 ? 2 * backoff : 4;
                         }
                     }
                 }
