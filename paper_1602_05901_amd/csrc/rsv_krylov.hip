@@ -543,9 +543,7 @@ rsv_status rsv_solve(rsv_matrix *A, rsv_precond *P, const rsv_solver_params *p, 
     PcImpl *impl = P ? P->impl : nullptr;
     if (P && P->p.type == RSV_PC_LEARNED && p->method != RSV_FGMRES)
         return st->status = set_err(c, RSV_ERR_ARG, "the learned preconditioner needs FGMRES");
-    if (p->method == RSV_FGMRES && !(P && P->fallback) && P && P->p.type != RSV_PC_LEARNED) {
-        // FGMRES with a fixed preconditioner: the fallback is the preconditioner itself
-    }
+    // FGMRES with a fixed preconditioner uses that preconditioner as its own fallback
     const int nvec = (p->method == RSV_BICGSTAB) ? 10 : (p->method == RSV_FGMRES ? 2 * m + 5 : m + 5);
     rsv_status s = ws_reserve(A, nvec);
     if (s != RSV_OK) return st->status = s;

@@ -444,6 +444,77 @@ def test_bicgstab_fp32_factors(rsv, ctx):
     check_solve(st, ref, xg, relres, its_band=False, hist_steps=4, hist_rtol=1e-5)
 
 
+@pytest.mark.parametrize("method,ortho", [("gmres", 0), ("gmres", 1), ("bicgstab", 0)])
+def test_nonzero_initial_guess(rsv, ctx, method, ortho):
+    """x holds x0 on entry: the solve continues from it (the true residual of
+    x0 starts the iteration), against the oracle started from the same x0."""
+    cfg = I.preset("C1", seed=4)
+    S = Sys(rsv, ctx, cfg)
+    xt = I.x_true(cfg)
+    bo = S.Ao.spmv(xt)
+    x0 = xt + 0.1 * I.test_vector(44, 3 * cfg.ncell)
+    M = rsv.Precond(S.A, type=rsv.PC_BILU0)
+    x = dev(x0)
+    meth = rsv.GMRES if method == "gmres" else rsv.BICGSTAB
+    st = rsv.solve(S.A, M, dev(bo), x, method=meth, restart=30, tol=1e-8, maxit=1000, ortho=ortho,
+                   record_history=1)
+    if method == "gmres":
+        ref = O.gmres(S.Ao, bo, pc=O.ILU(S.Ao), x0=x0, m=30, tol=1e-8, maxit=1000, hist=True)
+    else:
+        ref = O.bicgstab(S.Ao, bo, pc=O.ILU(S.Ao), x0=x0, tol=1e-8, maxit=1000, hist=True)
+    xg = x.cpu().numpy()
+    relres = np.linalg.norm(bo - S.Ao.spmv(xg)) / np.linalg.norm(bo)
+    # the first history entry is the residual of x0
+    assert abs(st["hist"][0] - np.linalg.norm(bo - S.Ao.spmv(x0)) / np.linalg.norm(bo)) <= 1e-12
+    check_solve(st, ref, xg, relres, its_band=(method == "gmres"), hist_steps=(10 if method == "gmres" else 6))
+    M.close(); S.close()
+
+
+def test_stop_tests_rtol_atol(rsv, ctx):
+    """The optional stop tests: ||r|| <= rtol ||r0|| and ||r|| <= atol, each
+    checked on the recomputed residual; with tol = 0 only they can stop."""
+    cfg = I.preset("C1", seed=6)
+    S = Sys(rsv, ctx, cfg)
+    xt = I.x_true(cfg)
+    bo = S.Ao.spmv(xt)
+    x0 = xt + 0.01 * I.test_vector(45, 3 * cfg.ncell)
+    r0 = np.linalg.norm(bo - S.Ao.spmv(x0))
+    M = rsv.Precond(S.A, type=rsv.PC_BILU0)
+    for method in (rsv.GMRES, rsv.BICGSTAB):
+        for kw, bound in ((dict(rtol=1e-6), 1e-6 * r0), (dict(atol=1e-7 * r0), 1e-7 * r0)):
+            x = dev(x0)
+            st = rsv.solve(S.A, M, dev(bo), x, method=method, tol=0.0, maxit=1000, **kw)
+            rn = np.linalg.norm(bo - S.Ao.spmv(x.cpu().numpy()))
+            assert st["status"] == 0 and rn <= bound * (1 + 1e-6), (method, kw, rn, bound)
+            assert rn > 1e-3 * bound   # stopped by this test, not run on to rounding level
+    M.close(); S.close()
+
+
+def test_caller_stream(rsv, ctx):
+    """A context bound to a caller's stream (rsv_set_stream) gives the same
+    bits as one on torch's current stream."""
+    cfg = I.preset("C1", seed=8)
+    B, Ao = make(cfg)
+    xt = I.x_true(cfg)
+    b = dev(Ao.spmv(xt))
+    Bd = dev(B)
+    out = []
+    s2 = torch.cuda.Stream()
+    for stream in (None, s2.cuda_stream):
+        torch.cuda.synchronize()
+        c = rsv.Context(0, stream=stream)
+        g = rsv.Grid(c, cfg.nx, cfg.ny, cfg.nz)
+        A = rsv.Matrix(g, Bd)
+        M = rsv.Precond(A, type=rsv.PC_RAS, ras_px=2, ras_py=2, ras_pz=2, ras_overlap=1)
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        st = rsv.solve(A, M, b, x, method=rsv.GMRES, tol=1e-8)
+        torch.cuda.synchronize()
+        out.append((st["its"], x.cpu().numpy()))
+        M.close(); A.close(); g.close(); c.close()
+    assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
+
+
 def test_gmres_fp32_factors(rsv, ctx):
     cfg = I.GenConfig(32, 32, 16, I.LNK_IID, 3.0, 0.0, 2.0, 0, 1e3, 1.0, 0)
     st, ref, xg, xt, relres = run_solve(rsv, ctx, cfg, rsv.PC_BILU0, rsv.GMRES, lambda A: (O.ILU(A), "fp32"),
