@@ -184,7 +184,8 @@ void rsv_matrix_destroy(rsv_matrix *A);
 /* y = alpha*A*x + beta*y (Algebraic Operations: y = alpha A x + beta y);
  * x, y device vectors of length 3*ncell (must not alias). */
 rsv_status rsv_spmv(rsv_matrix *A, double alpha, const double *x, double beta, double *y);
-/* Device bytes held by the matrix and everything built on it (diagnostics). */
+/* Device bytes held by the matrix and its solver workspace (diagnostics;
+ * preconditioners are separate objects and not counted). */
 int64_t rsv_matrix_device_bytes(const rsv_matrix *A);
 
 /* ---------------------------------------------------------------- preconditioner */

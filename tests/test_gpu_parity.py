@@ -101,6 +101,49 @@ def test_spmv_C2_full(rsv, ctx):
     S.close()
 
 
+def test_assemble_from_host_and_update(rsv, ctx):
+    """Host blocks assemble to the same matrix as device blocks; new values
+    on the same grid (the next Newton step) replace the old ones, and a
+    preconditioner set up afterwards factors the new matrix; the device bytes
+    held grow by the solver workspace once the matrix has been solved with."""
+    cfg = cfg_of((13, 9, 5), seed=23)
+    B1, Ao1 = make(cfg)
+    cfg2 = cfg_of((13, 9, 5), seed=24, sigma=2.0)
+    B2, Ao2 = make(cfg2)
+    g = rsv.Grid(ctx, 13, 9, 5)
+    Ah = rsv.Matrix(g, np.ascontiguousarray(B1), where=rsv.MEM_HOST)
+    Ad = rsv.Matrix(g, dev(B1))
+    n = 3 * cfg.ncell
+    x = dev(I.test_vector(46, n))
+    yh = torch.zeros_like(x)
+    yd = torch.zeros_like(x)
+    Ah.spmv(x, yh)
+    Ad.spmv(x, yd)
+    assert torch.equal(yh, yd)
+    b0 = Ad.device_bytes
+    Ad.update(dev(B2))
+    Ah.update(np.ascontiguousarray(B2), where=rsv.MEM_HOST)
+    Ad.spmv(x, yd)
+    Ah.spmv(x, yh)
+    assert torch.equal(yh, yd)
+    assert rel(yd.cpu().numpy(), Ao2.spmv(x.cpu().numpy())) <= 1e-12
+    M = rsv.Precond(Ad, type=rsv.PC_BILU0)
+    r = I.test_vector(47, n)
+    z = torch.zeros_like(x)
+    M.apply(dev(r), z)
+    assert rel(z.cpu().numpy(), O.ILU(Ao2).apply(r)) <= 1e-12
+    assert b0 >= 63 * 8 * cfg.ncell
+    rsv.solve(Ad, M, yd, torch.zeros_like(x), method=rsv.GMRES, restart=30, tol=1e-8)
+    assert Ad.device_bytes >= b0 + 35 * 3 * 8 * cfg.ncell   # m + 5 vectors of the GMRES workspace
+    M.close(); Ah.close(); Ad.close(); g.close()
+
+
+def test_device_info(rsv, ctx):
+    info = ctx.device_info()
+    assert info["num_cu"] >= 1 and info["lds_per_workgroup"] >= 64 * 1024
+    assert info["sweep_ring_fwd"] >= 2 and info["sweep_ring_bwd"] >= 2
+
+
 def test_spmv_top_down_ordering(rsv, ctx):
     """TOP_DOWN numbering is a row permutation: same operator on permuted vectors."""
     cfg = cfg_of((6, 5, 4), seed=3)
