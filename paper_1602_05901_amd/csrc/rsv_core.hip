@@ -377,27 +377,7 @@ rsv_status rsv_matrix_update(rsv_matrix *M, const double *blocks, int32_t where)
     return assemble_values(M, blocks, where);
 }
 
-int64_t rsv_matrix_device_bytes(const rsv_matrix *M);   // defined with the solver workspace
-
-rsv_status rsv_spmv(rsv_matrix *M, double alpha, const double *x, double beta, double *y)
-{
-    if (!M || !x || !y) return set_err(M ? M->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");
-    rsv_grid *g = M->g;
-    rsv_ctx *c = g->ctx;
-    double *xt = nullptr, *yt = nullptr;
-    rsv_status s = dev_alloc(c, (void **)&xt, (size_t)g->nv * sizeof(double));
-    if (s == RSV_OK) s = dev_alloc(c, (void **)&yt, (size_t)g->nv * sizeof(double));
-    if (s == RSV_OK) s = launch_nat_to_tl(c, g->geo, x, xt);
-    if (s == RSV_OK) s = launch_spmv(c, g->geo, M->d_A, SPMV_Y, xt, yt, nullptr, 1.0, 0.0, 0);
-    if (s == RSV_OK) s = launch_tl_to_nat(c, g->geo, yt, y, alpha, beta);
-    if (s == RSV_OK) {
-        hipError_t e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) s = set_err(c, RSV_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
-    }
-    dev_free(xt);
-    dev_free(yt);
-    return s;
-}
+// rsv_spmv and rsv_matrix_device_bytes are defined with the solver workspace
 
 void rsv_pc_params_default(rsv_pc_params *p)
 {

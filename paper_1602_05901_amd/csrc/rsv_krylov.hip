@@ -501,6 +501,25 @@ rsv_status rsv_precond_bilu0_factors(const rsv_precond *P, double *L, double *Di
     return P->impl->bilu0_factors(L, Dinv);
 }
 
+rsv_status rsv_spmv(rsv_matrix *M, double alpha, const double *x, double beta, double *y)
+{
+    if (!M || !x || !y) return set_err(M ? M->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");
+    rsv_ctx *c = M->g->ctx;
+    // the tile-lane copies of x and A x live in the solver workspace (no allocation per call)
+    rsv_status s = ws_reserve(M, 2);
+    if (s != RSV_OK) return s;
+    const int64_t n = M->g->nv;
+    double *xt = M->ws->pool, *yt = M->ws->pool + n;
+    s = launch_nat_to_tl(c, M->g->geo, x, xt);
+    if (s == RSV_OK) s = launch_spmv(c, M->g->geo, M->d_A, SPMV_Y, xt, yt, nullptr, 1.0, 0.0, 0);
+    if (s == RSV_OK) s = launch_tl_to_nat(c, M->g->geo, yt, y, alpha, beta);
+    if (s == RSV_OK) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) s = set_err(c, RSV_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
+    }
+    return s;
+}
+
 rsv_status rsv_precond_apply(rsv_precond *P, const double *r, double *z)
 {
     if (!P || !r || !z) return set_err(P ? P->A->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");

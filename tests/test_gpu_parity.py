@@ -134,7 +134,7 @@ def test_assemble_from_host_and_update(rsv, ctx):
     assert rel(z.cpu().numpy(), O.ILU(Ao2).apply(r)) <= 1e-12
     assert b0 >= 63 * 8 * cfg.ncell
     rsv.solve(Ad, M, yd, torch.zeros_like(x), method=rsv.GMRES, restart=30, tol=1e-8)
-    assert Ad.device_bytes >= b0 + 35 * 3 * 8 * cfg.ncell   # m + 5 vectors of the GMRES workspace
+    assert Ad.device_bytes >= (63 + 35 * 3) * 8 * cfg.ncell   # + m + 5 vectors of the GMRES workspace
     M.close(); Ah.close(); Ad.close(); g.close()
 
 
