@@ -101,7 +101,10 @@ typedef struct rsv_pc_params {
                           * r1 = r - A t, s = rms(r1): the network corrects what one BILU0 step leaves */
     int32_t ras_stack;   /* RAS, pipelined: subdomain boxes stacked per tile column of the auxiliary
                           * grid (0, default: as many as keep four tiles per compute unit) */
-    int32_t reserved[6];
+    int32_t ras_group;   /* RAS, pipelined: boxes placed side by side in groups of ras_group x ras_group,
+                          * each group padded to whole 8 x 8 tiles (0, default: 1, each box padded alone;
+                          * at most 16; made smaller when the boxes of a layer do not fill a group) */
+    int32_t reserved[5];
 } rsv_pc_params;
 
 /* Solver parameters; mirrors SOLVER (rtol, atol, maxit, restart). */

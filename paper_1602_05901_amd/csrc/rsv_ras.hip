@@ -8,16 +8,20 @@
 //
 // Two GPU mappings compute the same local solves.
 //
-// Boxed (the default, `pipelined`): each subdomain's extended box (its box
-// grown by `overlap` cells per side, clipped to the grid) is padded to whole
-// 8x8 tiles and placed in an SX x SY x SZ array of boxes that forms one
-// auxiliary grid (boxes stacked in z share tile columns: longer columns, fewer
-// tiles, less of each column spent on the tile's diagonal ramp).  The local matrix is stored there with every coupling that leaves
-// Omega_s set to zero; padded cells outside Omega_s get an identity diagonal
-// and no couplings.  The block-diagonal ILU(0) of that grid is exactly the
-// set of local ILU(0)s (the natural order inside a box is the global order),
-// and its pipelined tile sweeps exchange faces only inside a box, so every
-// subdomain advances at once, each tile's data streamed by its loader waves.
+// Boxed (the default, `pipelined`): the subdomains' extended boxes (a box
+// grown by `overlap` cells per side, clipped to the grid) are placed side by
+// side in groups of G x G, each group padded to whole 8x8 tiles, in an array
+// of boxes that forms one auxiliary grid (boxes stacked in z share tile
+// columns: longer columns, fewer tiles, less of each column spent on the
+// tile's diagonal ramp).  The local matrix is stored there with every
+// coupling that leaves Omega_s set to zero; cells outside every Omega_s get an
+// identity diagonal and no couplings.  The block-diagonal ILU(0) of that grid
+// is exactly the set of local ILU(0)s (the natural order inside a box is the
+// global order, and boxes share no couplings), and its pipelined tile sweeps
+// exchange faces only inside a group, so every group advances at once, each
+// tile's data streamed by its loader waves.  G = 1 pads every box alone; a
+// larger G wastes less padding but chains the boxes of a group through the
+// tiles they share.
 // The apply gathers r into the auxiliary grid and runs both sweeps there; the
 // backward sweep stores each cell's result into z only from the box that owns
 // the cell (an index map delivered with the sweep's operands).
@@ -455,8 +459,13 @@ struct Ras : PcImpl {
 
 // ---------------------------------------------------------------- boxed mapping
 
+// Placement of the subdomain boxes in the auxiliary grid.  Boxes sit in
+// groups of G x G, side by side at a pitch of BW (BH) cells, each group padded
+// to whole 8 x 8 tiles (GXp x GYp cells); SX box columns (a multiple of G) per
+// row, SZ boxes stacked per tile column, EZ layers each.  A box's slot in the
+// arrangement is s = (by * SX + bx) * SZ + bz.
 struct BoxDev {
-    int32_t nsub, SX, SZ, BXp, BYp, EZ, ov;
+    int32_t nsub, SX, SZ, G, BW, BH, GXp, GYp, EZ, ov;
     const int32_t *box;   // [nsub][9]: core x0,x1,y0,y1,z0,z1; extended-box origin ex,ey,ez
 };
 
@@ -473,12 +482,15 @@ __host__ __device__ inline bool in_omega(const int32_t *q, int x, int y, int z, 
 __host__ __device__ inline bool aux_cell(const BoxDev &B, const int32_t *box, const Geo &g, int X, int Y, int k, int &s,
                                          int &gx, int &gy, int &gz)
 {
-    const int bx = X / B.BXp, by = Y / B.BYp, bz = k / B.EZ;
+    const int gxi = X / B.GXp, xx = X - gxi * B.GXp, bi = xx / B.BW;
+    const int gyi = Y / B.GYp, yy = Y - gyi * B.GYp, bj = yy / B.BH;
+    if (bi >= B.G || bj >= B.G) return false;   // group padding
+    const int bx = gxi * B.G + bi, by = gyi * B.G + bj, bz = k / B.EZ;
     s = (by * B.SX + bx) * B.SZ + bz;
     if (s >= B.nsub) return false;
     const int32_t *q = box + 9 * s;
-    gx = q[6] + X % B.BXp;
-    gy = q[7] + Y % B.BYp;
+    gx = q[6] + (xx - bi * B.BW);
+    gy = q[7] + (yy - bj * B.BH);
     gz = q[8] + k % B.EZ;
     if (gx >= g.nx || gy >= g.ny || gz >= g.nz) return false;
     return in_omega(q, gx, gy, gz, B.ov);
@@ -573,7 +585,8 @@ struct RasBoxed : PcImpl {
     {
         const Geo &g = M->g->geo;
         const int px = p->ras_px, py = p->ras_py, pz = p->ras_pz, ov = p->ras_overlap;
-        if (px < 1 || py < 1 || pz < 1 || px > g.nx || py > g.ny || pz > g.nz || ov < 0 || p->ras_stack < 0)
+        if (px < 1 || py < 1 || pz < 1 || px > g.nx || py > g.ny || pz > g.nz || ov < 0 || p->ras_stack < 0 ||
+            p->ras_group < 0 || p->ras_group > 16)
             return set_err(c, RSV_ERR_ARG, "bad RAS partition");
         const int nsub = px * py * pz;
         h_box.assign((size_t)nsub * 9, 0);
@@ -589,28 +602,47 @@ struct RasBoxed : PcImpl {
             EY = std::max(EY, std::min(g.ny, q[3] + ov) - q[7]);
             EZ = std::max(EZ, std::min(g.nz, q[5] + ov) - q[8]);
         }
-        const int BXp = (EX + 7) / 8 * 8, BYp = (EY + 7) / 8 * 8;
-        // boxes per tile column: as many as keep at least four tiles per CU
-        const int64_t tpb = (int64_t)(BXp / 8) * (BYp / 8);
+        // boxes per tile column (SZ) and per group side (G); a group of G x G boxes
+        // padded to whole tiles wastes less than G^2 boxes padded one by one
+        auto arrange = [&](int sz, int gg, int &ngx, int &ngy) {
+            const int nl = (nsub + sz - 1) / sz;
+            const int ng = (nl + gg * gg - 1) / (gg * gg);
+            ngx = 1;
+            while (ngx * ngx < ng) ++ngx;
+            ngy = (ng + ngx - 1) / ngx;
+        };
+        int grp = p->ras_group > 0 ? p->ras_group : 1;
+        auto fit = [&](int sz, int gg) {     // no group larger than the boxes of one layer fill
+            const int nl = (nsub + sz - 1) / sz;
+            while (gg > 1 && gg * gg > nl) --gg;
+            return gg;
+        };
+        auto tiles = [&](int sz, int gg) {   // tiles of the filled groups
+            const int nl = (nsub + sz - 1) / sz;
+            gg = fit(sz, gg);
+            return (int64_t)((nl + gg * gg - 1) / (gg * gg)) * ((gg * EX + 7) / 8) * ((gg * EY + 7) / 8);
+        };
+        // as many boxes per tile column as keep at least four tiles per CU
         int SZ = 1;
         if (p->ras_stack > 0)
             SZ = std::min(nsub, p->ras_stack);
         else
-            while (SZ < nsub && (int64_t)((nsub + 2 * SZ - 1) / (2 * SZ)) * tpb >= 4 * (int64_t)c->num_cu) SZ *= 2;
-        const int nl = (nsub + SZ - 1) / SZ;
-        int SX = 1;
-        while (SX * SX < nl) ++SX;
-        const int SY = (nl + SX - 1) / SX;
-        B = BoxDev{nsub, SX, SZ, BXp, BYp, EZ, ov, nullptr};
+            while (SZ < nsub && tiles(2 * SZ, grp) >= 4 * (int64_t)c->num_cu) SZ *= 2;
+        grp = fit(SZ, grp);
+        int ngx, ngy;
+        arrange(SZ, grp, ngx, ngy);
+        const int GXp = (grp * EX + 7) / 8 * 8, GYp = (grp * EY + 7) / 8 * 8;
+        const int SX = ngx * grp;
+        B = BoxDev{nsub, SX, SZ, grp, EX, EY, GXp, GYp, EZ, ov, nullptr};
         // the auxiliary grid must fit the tile-lane index range (3 * slots < 2^31);
         // otherwise the caller falls back to the per-subdomain mapping
-        const int64_t aux_slots = (int64_t)SX * (BXp / 8) * SY * (BYp / 8) * SZ * EZ * 64;
+        const int64_t aux_slots = (int64_t)ngx * (GXp / 8) * ngy * (GYp / 8) * SZ * EZ * 64;
         if (3 * aux_slots >= ((int64_t)1 << 31)) {
             too_large = true;
             return set_err(c, RSV_ERR_ARG, "RAS boxes exceed the auxiliary grid's index range");
         }
         // factorisation planes inside each box (the boxes share no couplings)
-        rsv_status st = grid_create_planes(c, SX * BXp, SY * BYp, SZ * EZ, RSV_BOTTOM_UP, BXp, BYp, EZ, &ga);
+        rsv_status st = grid_create_planes(c, ngx * GXp, ngy * GYp, SZ * EZ, RSV_BOTTOM_UP, GXp, GYp, EZ, &ga);
         if (st != RSV_OK) return st;
         const Geo &G = ga->geo;
         st = alloc((void **)&d_box, h_box.size() * sizeof(int32_t));
@@ -628,7 +660,7 @@ struct RasBoxed : PcImpl {
                            gin, gout);
         RSV_LAUNCH(c);
         int64_t bad = -1;
-        st = bilu0_create_boxed(&Ma, p, BXp / 8, BYp / 8, gout, &ilu, &bad);
+        st = bilu0_create_boxed(&Ma, p, GXp / 8, GYp / 8, gout, &ilu, &bad);
         if (st == RSV_ERR_ZERO_PIVOT && bad >= 0 && bad_cell) {
             // the auxiliary row of the failing pivot, as the cell of the grid
             const int X = (int)(bad % G.nx), Y = (int)((bad / G.nx) % G.ny), k = (int)(bad / ((int64_t)G.nx * G.ny));

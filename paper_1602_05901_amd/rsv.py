@@ -28,7 +28,8 @@ vp, i32, i64, dbl, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes
 class PcParams(ctypes.Structure):
     _fields_ = [("type", i32), ("precision", i32), ("ras_px", i32), ("ras_py", i32), ("ras_pz", i32),
                 ("ras_overlap", i32), ("iluk_level", i32), ("pipelined", i32), ("net", vp), ("lnk", vp),
-                ("theta", dbl), ("learned_mode", i32), ("ras_stack", i32), ("reserved", i32 * 6)]
+                ("theta", dbl), ("learned_mode", i32), ("ras_stack", i32), ("ras_group", i32),
+                ("reserved", i32 * 5)]
 
 
 class SolverParams(ctypes.Structure):

@@ -347,6 +347,42 @@ def test_ras_boxes_stacked(rsv, ctx, dims, parts, ov, stack, prec):
     S.close()
 
 
+@pytest.mark.parametrize("dims,parts,ov", [((20, 20, 10), (2, 2, 2), 1), ((13, 9, 5), (3, 2, 1), 1),
+                                           ((16, 16, 8), (4, 4, 4), 1), ((12, 10, 6), (2, 3, 1), 0),
+                                           ((32, 32, 16), (4, 4, 4), 1), ((33, 29, 11), (4, 3, 2), 2)])
+@pytest.mark.parametrize("group", [2, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ras_box_groups(rsv, ctx, dims, parts, ov, group, prec):
+    """Boxes packed side by side in groups (ras_group): the same local solves
+    as the oracle's, and the same as one box per group to rounding (the
+    boxes of a group share tiles but no couplings)."""
+    log("ras groups", dims, parts, ov, group, prec)
+    S = Sys(rsv, ctx, cfg_of(dims, seed=19))
+    kw = dict(type=rsv.PC_RAS, ras_px=parts[0], ras_py=parts[1], ras_pz=parts[2], ras_overlap=ov, precision=prec)
+    n = 3 * S.cfg.ncell
+    r = I.test_vector(20, n)
+    out = []
+    for gr in (group, 1):
+        M = rsv.Precond(S.A, ras_group=gr, **kw)
+        z = torch.zeros(n, dtype=torch.float64, device="cuda")
+        M.apply(dev(r), z)
+        out.append(z.cpu().numpy())
+        M.close()
+    ref = O.RAS(S.Ao, dims, parts, ov).apply(r)
+    assert rel(out[0], ref) <= (1e-12 if prec == 0 else 1e-4)
+    assert rel(out[0], out[1]) <= (1e-14 if prec == 0 else 1e-6)
+    S.close()
+
+
+def test_ras_group_bad_value(rsv, ctx):
+    S = Sys(rsv, ctx, cfg_of((8, 8, 4), seed=2))
+    for bad in (-1, 17):
+        with pytest.raises(rsv.RsvError) as e:
+            rsv.Precond(S.A, type=rsv.PC_RAS, ras_px=2, ras_py=2, ras_pz=1, ras_group=bad)
+        assert e.value.status == rsv.ERR_ARG
+    S.close()
+
+
 @pytest.mark.parametrize("pipelined", [1, 0])
 def test_ras_zero_pivot_reported(rsv, ctx, pipelined):
     """A zero diagonal block on the first cell of subdomain (1,1,1) (no overlap,
