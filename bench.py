@@ -314,6 +314,23 @@ def main():
                          f"(the host has {os.cpu_count()} logical cores)"}
         log(f"oracle: {t2 - t1:.2f}s ({ro['its']} its)")
 
+    # the runtime's device-to-device copy rate beside the vendor peak, for context
+    # (1 GiB read + 1 GiB written, median of five, outside the timed steps)
+    csrc = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    ct = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cdst.copy_(csrc)
+        e1.record()
+        torch.cuda.synchronize()
+        ct.append(e0.elapsed_time(e1) * 1e-3)
+    copy_GBps = round(2 * csrc.numel() * 8 / float(np.median(ct)) / 1e9, 1)
+    del csrc, cdst
+    roofline["d2d_copy_GBps"] = copy_GBps
+
     value = summary[head]["solve_s"]
     line = {
         "metric": "time-to-solve to 1e-8 FP64 rel. residual (s), SpMV/ILU HBM GB/s; learned/FP32 vs plain",
