@@ -1,0 +1,216 @@
+"""GPU parity at the full sizes of the precision workload (256x256x128,
+25.2 M unknowns, ln k ~ N(0,3)) and of the large workload (512x512x128,
+100.7 M unknowns, channelised permeability), in the launch configuration
+the benchmark uses, for every preconditioner form each workload names.
+
+The oracle cannot afford a whole solve at these sizes inside a test, so each
+form is checked three ways:
+  * the GPU solve to 1e-8, with the relative residual of the returned x
+    recomputed on the host by the oracle's SpMV (<= 1e-8, and the reported
+    one within 1e-3 of it);
+  * the first ten residual estimates of the GPU's GMRES(30) against the
+    oracle's (<= 1e-8 relative; 1e-5 with FP32 factors, whose sweeps differ
+    from the oracle's FP32 sweeps at FP32 rounding);
+  * the GMRES iterate after exactly ten steps against the oracle's iterate
+    after ten steps (<= 1e-6 relative; 1e-4 with FP32 factors).
+The FP32-factor form's error against the FP64 result is logged and bounded.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1602_05901_amd import inputs as I  # noqa: E402
+import oracle as O  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+K_HIST = 10
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def rsv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_05901_amd import rsv as R
+    R.lib()
+    return R
+
+
+@pytest.fixture(scope="module")
+def ctx(rsv):
+    c = rsv.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+class Big:
+    """One full-size system, generated once, held by both sides."""
+
+    def __init__(self, rsv, ctx, name):
+        t0 = time.time()
+        self.cfg = cfg = I.preset(name, seed=0)
+        self.lnk = I.lnk(cfg)
+        self.B = I.blocks(cfg, self.lnk)
+        self.xt = I.x_true(cfg)
+        log(f"{name}: generated in {time.time() - t0:.1f}s")
+        t0 = time.time()
+        self.Ao = O.BCSR.from_stencil(cfg.nx, cfg.ny, cfg.nz, self.B)
+        self.bo = self.Ao.spmv(self.xt)
+        log(f"{name}: oracle matrix in {time.time() - t0:.1f}s")
+        self.g = rsv.Grid(ctx, cfg.nx, cfg.ny, cfg.nz)
+        self.A = rsv.Matrix(self.g, dev(self.B))
+        self.b = dev(self.bo)
+        self.n = 3 * cfg.ncell
+
+    def relres(self, x):
+        return float(np.linalg.norm(self.bo - self.Ao.spmv(x)) / np.linalg.norm(self.bo))
+
+    def close(self):
+        self.A.close()
+        self.g.close()
+
+
+def gpu_solve(rsv, S, M, method, **kw):
+    x = torch.zeros_like(S.b)
+    st = rsv.solve(S.A, M, S.b, x, method=method, restart=30, **kw)
+    torch.cuda.synchronize()
+    return st, x.cpu().numpy()
+
+
+def check_form(rsv, S, name, M, oracle_pc, hist_rtol, xk_tol):
+    """Full solve, history prefix and ten-step iterate of one GMRES(30) form;
+    returns the solution."""
+    t0 = time.time()
+    st, x = gpu_solve(rsv, S, M, rsv.GMRES, tol=1e-8, maxit=5000, record_history=1)
+    rr = S.relres(x)
+    log(f"  {name}: its {st['its']} relres (oracle SpMV) {rr:.3e} reported {st['final_relres']:.3e} "
+        f"err vs x_true {rel(x, S.xt):.2e} ({time.time() - t0:.1f}s)")
+    assert st["status"] == rsv.OK and rr <= 1e-8
+    assert abs(st["final_relres"] - rr) <= 1e-3 * rr + 1e-15
+    st10, x10 = gpu_solve(rsv, S, M, rsv.GMRES, tol=0.0, maxit=K_HIST)
+    assert st10["its"] == K_HIST
+    t0 = time.time()
+    ref = O.gmres(S.Ao, S.bo, pc=oracle_pc, m=K_HIST, tol=0.0, maxit=K_HIST, hist=True)
+    log(f"  {name}: oracle {K_HIST} steps in {time.time() - t0:.1f}s")
+    h, hr = st["hist"][:K_HIST + 1], ref["hist"][:K_HIST + 1]
+    log(f"  {name}: history max rel diff {np.max(np.abs(h - hr) / hr):.2e}, "
+        f"x after {K_HIST} steps rel diff {rel(x10, ref['x']):.2e}")
+    assert len(h) == K_HIST + 1 and np.allclose(h, hr, rtol=hist_rtol, atol=0)
+    assert rel(x10, ref["x"]) <= xk_tol
+    return x
+
+
+# ---------------------------------------------------------------- 256x256x128, FP64 and FP32 factors, RAS
+
+@pytest.fixture(scope="module")
+def c3(rsv, ctx):
+    S = Big(rsv, ctx, "C3")
+    yield S
+    S.close()
+
+
+def test_C3_fp32_apply_every_entry(rsv, ctx, c3):
+    r = I.test_vector(31, c3.n)
+    M = rsv.Precond(c3.A, type=rsv.PC_BILU0, precision=rsv.FP32)
+    z = torch.zeros(c3.n, dtype=torch.float64, device="cuda")
+    M.apply(dev(r), z)
+    F = O.ILU(c3.Ao)
+    ref = F.apply(r, fp32=True)
+    zc = z.cpu().numpy()
+    assert np.max(np.abs(zc - ref)) <= 2e-6 * np.max(np.abs(ref))
+    log(f"  C3 FP32 apply vs FP64 oracle apply: {rel(zc, F.apply(r)):.2e}")
+    M.close()
+
+
+def test_C3_forms_against_oracle(rsv, ctx, c3):
+    F = O.ILU(c3.Ao)
+    xs = {}
+    M = rsv.Precond(c3.A, type=rsv.PC_BILU0)
+    xs["fp64"] = check_form(rsv, c3, "C3 GMRES+BILU0 FP64", M, F, 1e-8, 1e-6)
+    M.close()
+    M = rsv.Precond(c3.A, type=rsv.PC_BILU0, precision=rsv.FP32)
+    xs["fp32"] = check_form(rsv, c3, "C3 GMRES+BILU0 FP32 factors", M, (F, "fp32"), 1e-5, 1e-4)
+    M.close()
+    del F
+    err = rel(xs["fp32"], xs["fp64"])
+    log(f"  C3 FP32-factor solution vs FP64 solution: {err:.2e}")
+    assert err <= 1e-6
+    R = O.RAS(c3.Ao, (256, 256, 128), (4, 4, 4), 1)
+    M = rsv.Precond(c3.A, type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1)
+    check_form(rsv, c3, "C3 GMRES+RAS(4x4x4)", M, R, 1e-8, 1e-6)
+    M.close()
+
+
+def test_C3_release(c3):
+    c3.close()
+    del c3.Ao, c3.B
+
+
+# ---------------------------------------------------------------- 512x512x128, all three preconditioner forms
+
+@pytest.fixture(scope="module")
+def c5(rsv, ctx):
+    S = Big(rsv, ctx, "C5")
+    yield S
+    S.close()
+
+
+def test_C5_spmv_every_output(rsv, ctx, c5):
+    x = I.test_vector(41, c5.n)
+    y = torch.zeros(c5.n, dtype=torch.float64, device="cuda")
+    c5.A.spmv(dev(x), y)
+    ref = c5.Ao.spmv(x)
+    assert np.max(np.abs(y.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_C5_plain_and_fp32_forms_against_oracle(rsv, ctx, c5):
+    F = O.ILU(c5.Ao)
+    xs = {}
+    M = rsv.Precond(c5.A, type=rsv.PC_BILU0)
+    xs["fp64"] = check_form(rsv, c5, "C5 GMRES+BILU0 FP64", M, F, 1e-8, 1e-6)
+    M.close()
+    M = rsv.Precond(c5.A, type=rsv.PC_BILU0, precision=rsv.FP32)
+    xs["fp32"] = check_form(rsv, c5, "C5 GMRES+BILU0 FP32 factors", M, (F, "fp32"), 1e-5, 1e-4)
+    M.close()
+    err = rel(xs["fp32"], xs["fp64"])
+    log(f"  C5 FP32-factor solution vs FP64 solution: {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_C5_learned_form(rsv, ctx, c5):
+    """FGMRES(30) with the U-Net (briefly trained on 64x64x32 systems with the
+    library's own kernels) and the BILU0 fallback: reaches 1e-8 by the
+    oracle's recomputed residual."""
+    from paper_1602_05901_amd import train as T
+    net = rsv.Net(ctx, seed=0)
+    sy = T.System(ctx, I.preset("C4", seed=1000))
+    R, E, _ = T.harvest(ctx, sy)
+    T.train(ctx, net, [(sy.g, R, E, sy.lnk)], 200, batch=8, lr=1e-3, seed=0)
+    sy.close()
+    M = rsv.Precond(c5.A, type=rsv.PC_LEARNED, net=net, lnk=dev(c5.lnk.astype(np.float32)))
+    t0 = time.time()
+    st, x = gpu_solve(rsv, c5, M, rsv.FGMRES, tol=1e-8, maxit=5000)
+    rr = c5.relres(x)
+    log(f"  C5 FGMRES+U-Net: its {st['its']} fallbacks {st['fallbacks']} relres (oracle SpMV) {rr:.3e} "
+        f"err vs x_true {rel(x, c5.xt):.2e} ({time.time() - t0:.1f}s)")
+    assert st["status"] == rsv.OK and rr <= 1e-8
+    assert abs(st["final_relres"] - rr) <= 1e-3 * rr + 1e-15
+    M.close(); net.close()

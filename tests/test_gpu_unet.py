@@ -350,3 +350,79 @@ def test_learned_mode1_is_bilu0_step_plus_network_correction(rsv, ctx):
     with pytest.raises(rsv.RsvError):
         rsv.Precond(A, type=rsv.PC_LEARNED, net=net, lnk=l32, learned_mode=2)
     M1.close(); B.close(); A.close(); g.close(); net.close()
+
+
+# ---------------------------------------------------------------- FGMRES decisions with accepted and rejected columns
+
+def _robust_decisions(Ao, b, pc_of, F, theta, m=30, tol=1e-8, maxit=500):
+    """The oracle's FGMRES decisions (its, fallbacks) with the network map
+    pc_of(pert, seed), and whether they survive +-1% per-entry perturbations
+    of the network's output (five times the GPU/oracle network difference the
+    forward parity test allows): only then can the GPU's be required to be
+    equal."""
+    outs = [O.fgmres(Ao, b, pc=pc_of(pert, seed), fallback=F, theta=theta, m=m, tol=tol, maxit=maxit)
+            for pert, seed in ((0.0, 0), (1e-2, 1), (1e-2, 2), (-1e-2, 3))]
+    keys = {(o["its"], o["fallbacks"]) for o in outs}
+    return outs[0], len(keys) == 1
+
+
+def _perturbed(f, pert, seed):
+    rng = np.random.default_rng(seed)
+
+    def g(v):
+        z = f(v)
+        return z * (1.0 + pert * rng.choice([-1.0, 1.0], len(z))) if pert else z
+    return g
+
+
+@pytest.mark.parametrize("mode,thetas", [(0, (0.75, 0.8)), (1, (0.9,))])
+def test_fgmres_mixed_decisions_match_oracle(rsv, ctx, mode, thetas):
+    """A network that is accepted on some FGMRES columns and rejected on
+    others: the identity-weight network (z = v up to BF16 rounding, an
+    unpreconditioned column) in mode 0, and the same weights as the
+    correction of one BILU0 step in mode 1 (z = t + s N((v - A t)/s),
+    t = BILU0^-1 v), whose oracle counterpart is composed here from the
+    oracle's ILU(0), SpMV and U-Net.  The oracle's decisions are first shown
+    to be stable under +-1% output perturbations; then the GPU's iteration
+    and fallback counts must equal them and its solution the oracle's."""
+    from cases import identity_unet
+    dims = (12, 12, 8)
+    cfg = I.GenConfig(*dims, I.LNK_IID, 1.0, 0.0, 2.0, 0, 1e3, 1.0, 5)
+    lnk = I.lnk(cfg)
+    B = I.blocks(cfg, lnk)
+    Ao = O.BCSR.from_stencil(*dims, B)
+    b = Ao.spmv(I.x_true(cfg))
+    F = O.ILU(Ao)
+    p = identity_unet()
+
+    def net_map(v):
+        if mode == 0:
+            return U.apply(p, v, lnk, dims, emulate=True)
+        t = F.apply(v)
+        return t + U.apply(p, v - Ao.spmv(t), lnk, dims, emulate=True)
+
+    g = rsv.Grid(ctx, *dims)
+    A = rsv.Matrix(g, dev(B))
+    net = rsv.Net(ctx)
+    net.set_params(p.astype(np.float32))
+    checked = 0
+    for theta in thetas:
+        ref, stable = _robust_decisions(Ao, b, lambda pert, seed: _perturbed(net_map, pert, seed), F, theta)
+        log("  mode", mode, "theta", theta, "oracle its", ref["its"], "fallbacks", ref["fallbacks"], "stable", stable)
+        if not stable:
+            continue
+        assert ref["rc"] == O.OK and 0 < ref["fallbacks"] < ref["its"]     # both decisions occur
+        M = rsv.Precond(A, type=rsv.PC_LEARNED, net=net, lnk=dev(lnk.astype(np.float32)), theta=theta,
+                        learned_mode=mode)
+        x = torch.zeros(3 * cfg.ncell, dtype=torch.float64, device="cuda")
+        st = rsv.solve(A, M, dev(b), x, method=rsv.FGMRES, restart=30, tol=1e-8, maxit=500)
+        log("  gpu its", st["its"], "fallbacks", st["fallbacks"])
+        assert st["status"] == rsv.OK
+        assert (st["its"], st["fallbacks"]) == (ref["its"], ref["fallbacks"])
+        xg = x.cpu().numpy()
+        assert np.linalg.norm(b - Ao.spmv(xg)) / np.linalg.norm(b) <= 1e-8
+        assert rel(xg, ref["x"]) <= 1e-6
+        M.close()
+        checked += 1
+    assert checked >= 1
+    A.close(); g.close(); net.close()

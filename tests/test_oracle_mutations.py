@@ -1,0 +1,76 @@
+"""Mutation checks for the oracle's pins: each case plants one plausible slip
+in a copy of the oracle's C sources (never in the sources themselves),
+builds that copy on the CPU, and runs the pin that should catch it in a
+subprocess that loads the broken build (ORACLE_LIB).  The pin must fail;
+the unmodified copy built the same way must pass the same pins.  No GPU.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORC = os.path.join(ROOT, "oracle")
+PINS = "tests/test_oracle_pins_branches.py"
+
+# (id, file, text in the oracle, replacement, pins that must fail)
+MUTATIONS = [
+    ("adam_bias_exponent", "unet.c", "pow(b1, (double)t)", "b1",
+     [PINS + "::test_adam_constant_gradient_steps_2_and_3", PINS + "::test_adam_three_different_gradients_closed_form"]),
+    ("adam_second_moment_exponent", "unet.c", "pow(b2, (double)t)", "b2",
+     [PINS + "::test_adam_constant_gradient_steps_2_and_3"]),
+    ("fgmres_no_cycle_handover", "oracle.c", "if (consecutive_fb >= 3) fb_rest = 1;", "",
+     [PINS + "::test_fgmres_three_rejections_hand_the_cycle_to_the_fallback"]),
+    ("fgmres_no_reset_on_accept", "oracle.c",
+     "if (used_fb) { st->fallbacks++; consecutive_fb++; } else consecutive_fb = 0;",
+     "if (used_fb) { st->fallbacks++; consecutive_fb++; }",
+     [PINS + "::test_fgmres_acceptance_resets_the_consecutive_count"]),
+    ("bicgstab_no_omega_exit", "oracle.c", "if (omega == 0.0) { rc = ORC_BREAKDOWN; break; }", "",
+     [PINS + "::test_bicgstab_breakdown_exits[omega0]"]),
+    ("bicgstab_no_rv_exit", "oracle.c",
+     "if (rv == 0.0 || !isfinite(rv)) { rc = isfinite(rv) ? ORC_BREAKDOWN : ORC_ERR_NAN; break; }",
+     "if (!isfinite(rv)) { rc = ORC_ERR_NAN; break; }",
+     [PINS + "::test_bicgstab_breakdown_exits[rv0]"]),
+]
+
+
+def _build(tmp, mutation=None):
+    src = os.path.join(tmp, "src")
+    os.makedirs(src, exist_ok=True)
+    for f in ("oracle.c", "unet.c", "oracle.h"):
+        shutil.copy(os.path.join(ORC, f), src)
+    if mutation is not None:
+        _, fname, old, new, _ = mutation
+        path = os.path.join(src, fname)
+        text = open(path).read()
+        assert text.count(old) == 1, f"mutation site not unique in {fname}: {old!r}"
+        open(path, "w").write(text.replace(old, new))
+    lib = os.path.join(tmp, "liboracle_mut.so")
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", lib,
+                    os.path.join(src, "oracle.c"), os.path.join(src, "unet.c"), "-lm"], check=True)
+    return lib
+
+
+def _run_pins(lib, nodes):
+    env = dict(os.environ, ORACLE_LIB=lib)
+    return subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider", *nodes],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+
+
+def test_unmutated_copy_passes_the_pins(tmp_path):
+    lib = _build(str(tmp_path))
+    nodes = sorted({n for m in MUTATIONS for n in m[4]})
+    r = _run_pins(lib, nodes)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("mutation", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_catches_mutation(tmp_path, mutation):
+    lib = _build(str(tmp_path), mutation)
+    r = _run_pins(lib, mutation[4])
+    # exit code 1: the tests ran and at least one failed (not a crash or a
+    # collection error)
+    assert r.returncode == 1, r.stdout[-2000:]
+    assert "failed" in r.stdout

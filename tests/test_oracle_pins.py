@@ -454,7 +454,7 @@ def test_bicgstab_dense_agreement_and_exact_pc():
 
 
 def test_bicgstab_manufactured_C1():
-    cfg = I.preset("C1", seed=1)
+    cfg = I.preset("C1", seed=1, m_shift=2.0)
     A = O.BCSR.from_stencil(cfg.nx, cfg.ny, cfg.nz, I.blocks(cfg))
     xt = I.x_true(cfg)
     b = A.spmv(xt)
@@ -466,7 +466,7 @@ def test_bicgstab_manufactured_C1():
 # ---------------------------------------------------------------- FGMRES
 
 def test_fgmres_with_fixed_pc_equals_gmres():
-    cfg = I.preset("C1", seed=2)
+    cfg = I.preset("C1", seed=2, m_shift=2.0)
     A = O.BCSR.from_stencil(cfg.nx, cfg.ny, cfg.nz, I.blocks(cfg))
     F = O.ILU(A)
     b = A.spmv(I.x_true(cfg))

@@ -132,3 +132,22 @@ def test_adam_first_step_closed_form():
     # bias-corrected first step: p -= lr * g / (|g| + eps)
     assert np.allclose(p1, p0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_identity_weights_give_the_identity_map():
+    """A closed-form special case of the whole network: with the weights of
+    cases.identity_unet the map is relu(x) - relu(-x) = x on each residual
+    channel, so z = s N(v/s) returns v up to the BF16 rounding of v/s (unit
+    roundoff 2^-8 for an 8-bit significand) when emulating BF16, and exactly v in FP64."""
+    from cases import identity_unet
+    dims = (8, 8, 4)
+    V = 8 * 8 * 4
+    p = identity_unet()
+    v = rnd(3 * V, 21) * 5.0
+    lnk = rnd(V, 22)
+    z = U.apply(p, v, lnk, dims, emulate=False)
+    assert np.allclose(z, v, rtol=1e-14, atol=1e-15)
+    ze = U.apply(p, v, lnk, dims, emulate=True)
+    assert np.all(np.abs(ze - v) <= 2.0 ** -8 * np.abs(v) * (1 + 1e-6))
+    # a wrong sign on the negative branch would give relu(x) + relu(-x) = |x|
+    assert np.max(np.abs(ze - np.abs(v))) > 1.0
