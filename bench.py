@@ -3,18 +3,19 @@
 MI355X, with the dominant kernel's achieved HBM bandwidth against the roofline
 and the CPU oracle timed beside it.
 
-Workload (default C2): 128x128x64 cells (3,145,728 unknowns), layered
-log-normal permeability (layer mean ~ N(0,1.5), cell noise ~ N(0,2)), four
-source cells, b = A x_true, x0 = 0, tol 1e-8 on the recomputed FP64 relative
-residual.  One step = assemble the block matrix, then for each solver form:
-preconditioner setup + solve.  Forms: GMRES(30) + RAS(4x4x4 subdomains,
-overlap 1, ILU(0) local solves: the paper's own solver configuration, the
-headline time-to-solve), BiCGSTAB + BILU0,
-GMRES(30) + BILU0 with FP64 factors, GMRES(30) + BILU0 with FP32 factors,
-GMRES(30) + RAS with FP32 local factors,
-and FGMRES(30) + the learned U-Net preconditioner (BILU0 fallback), whose
-network is trained first on C4-shaped systems (64x64x32, disjoint seeds;
-training time reported apart) or loaded (--net).
+Workload (default C5, the largest single-GPU configuration): 512x512x128
+cells (100,663,296 unknowns), channelised permeability (bands of k = 1e3 in
+k = 1 plus N(0,0.5) log noise), eight source cells, b = A x_true, x0 = 0,
+tol 1e-8 on the recomputed FP64 relative residual.  One step = re-assemble
+the block matrix from device blocks, then for each of the workload's three
+preconditioner forms: setup + solve.  Forms: GMRES(30) + block ILU(0) with
+FP64 factors (the headline time-to-solve), GMRES(30) + block ILU(0) with FP32
+factors and sweeps, and FGMRES(30) + the learned U-Net preconditioner (BILU0
+fallback), whose network is trained first on 64x64x32 systems (disjoint
+seeds; training time reported apart) or loaded (--net).  BiCGSTAB + BILU0
+and GMRES(30) + RAS(4x4x4) run once each after the timed steps.  Kernel
+timings come from one more, untimed step with HIP events on the solver
+stream.  --workload C2 gives the 128x128x64 workload with its own forms.
 
 Prints one JSON line.
 """
@@ -82,20 +83,114 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# per workload: the forms of one timed step (the first is the headline) and
+# the forms run once after the timed steps
+WORKLOAD_FORMS = {
+    "C5": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64"),
+    "C3": ("gmres_bilu0,gmres_bilu0_fp32", "gmres_ras64"),
+    "C2": ("gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,gmres_ras64_dcgs2,"
+           "gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64", ""),
+    "C4": ("gmres_bilu0,gmres_bilu0_fp32", ""),
+    "C1": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64"),
+}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_baseline(cfg, Ao, bo, t_build, head_form, its_gpu, restart=30, full_limit_cells=4_000_000, k_sample=3):
+    """The serial FP64 oracle on one host thread, on the same system.
+
+    Up to full_limit_cells cells the whole solve of the headline form is
+    timed.  Beyond that (the 512x512x128 workload: minutes of CPU time per
+    solve), a bounded sample is timed -- the ILU(0) setup, one product, one
+    preconditioner apply and a k_sample-step GMRES(30) run -- and the time to
+    solve is projected for the GPU's iteration count with the per-step cost
+    model t_M + t_A + c (j + 1) (apply, product, and c per basis vector of the
+    two Gram-Schmidt passes at step j of a cycle; per cycle one residual
+    product, one apply and one basis combination, c/4 per vector)."""
+    import oracle as O
+    method, pk = head_form
+    host = {"cpu_model": cpu_model(), "host_logical_cores": os.cpu_count()}
+    if cfg.ncell <= full_limit_cells:
+        t1 = time.perf_counter()
+        if pk.get("type") == 2:
+            F = O.RAS(Ao, (cfg.nx, cfg.ny, cfg.nz), (pk["ras_px"], pk["ras_py"], pk["ras_pz"]), pk["ras_overlap"])
+            what = "GMRES(30)+RAS(%dx%dx%d, overlap %d)" % (pk["ras_px"], pk["ras_py"], pk["ras_pz"], pk["ras_overlap"])
+        else:
+            F = O.ILU(Ao)
+            what = "GMRES(30)+BILU0" if method == 0 else "BiCGSTAB+BILU0"
+        if method == 1:
+            ro = O.bicgstab(Ao, bo, pc=F, tol=1e-8, maxit=10000)
+        else:
+            ro = O.gmres(Ao, bo, pc=F, m=restart, tol=1e-8, maxit=10000)
+        t2 = time.perf_counter()
+        log(f"oracle: {t2 - t1:.2f}s ({ro['its']} its)")
+        return {"value": round(t2 - t1, 3), "unit": "s", "cores": 1, "kind": "oracle",
+                "sample": f"the whole {what} solve (setup and {ro['its']} iterations, relres {ro['relres']:.2e}) "
+                          f"of the same system, serial FP64 C on one host thread; the oracle's matrix build "
+                          f"from the blocks ({t_build:.1f}s) is not counted", **host}
+    assert method == 0 and pk.get("type") == 1, "the projection models GMRES + BILU0"
+    t1 = time.perf_counter()
+    F = O.ILU(Ao)
+    t_setup = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    w = Ao.spmv(bo)
+    t_A = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    F.apply(w)
+    t_M = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    ro = O.gmres(Ao, bo, pc=F, m=restart, tol=0.0, maxit=k_sample)
+    T_k = time.perf_counter() - t1
+    # T_k = t_A + sum_{j<k}(t_M + t_A + c(j+1)) + (t_M + c k/4) + t_A
+    k = k_sample
+    c = max(0.0, (T_k - 2 * t_A - t_M - k * (t_M + t_A)) / (k * (k + 1) / 2 + k / 4))
+    proj = t_setup + t_A
+    left = its_gpu
+    while left > 0:
+        L = min(restart, left)
+        proj += sum(t_M + t_A + c * (j + 1) for j in range(L)) + t_M + c * L / 4 + t_A
+        left -= L
+    sample_s = t_setup + t_A + t_M + T_k
+    log(f"oracle sample: setup {t_setup:.1f}s, product {t_A:.2f}s, apply {t_M:.2f}s, "
+        f"{k_sample} GMRES steps {T_k:.1f}s (c = {c:.3f}s per basis vector); projection {proj:.1f}s")
+    return {"value": round(proj, 2), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"projected time to solve for {its_gpu} GMRES(30)+BILU0 steps from a timed sample on "
+                       f"the same system ({sample_s:.1f}s of CPU work): ILU(0) setup {t_setup:.2f}s, one block "
+                       f"product {t_A:.3f}s, one ILU(0) apply {t_M:.3f}s, and a {k_sample}-step GMRES(30) run "
+                       f"{T_k:.2f}s giving {c:.4f}s per basis vector of the two Gram-Schmidt passes; per step "
+                       f"t_M + t_A + c(j+1), per cycle one residual product, one apply and c/4 per vector of the "
+                       f"basis combination; serial FP64 C on one host thread, the oracle's matrix build from "
+                       f"the blocks ({t_build:.1f}s) not counted"),
+            "sample_s": round(sample_s, 2), "setup_s": round(t_setup, 3), "product_s": round(t_A, 4),
+            "apply_s": round(t_M, 4), "gmres_steps": k_sample, "gmres_steps_s": round(T_k, 3),
+            "per_basis_vector_s": round(c, 5), **host}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--workload", default="C5")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,"
-                                          "gmres_ras64_dcgs2,gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64")
+    ap.add_argument("--forms", default=None, help="forms of a timed step, comma separated (first = headline)")
+    ap.add_argument("--extra-forms", default=None, help="forms run once after the timed steps")
     ap.add_argument("--net", default=None, help="trained U-Net weights for the learned form")
     ap.add_argument("--learned-steps", type=int, default=1500,
                     help="without --net: Adam steps of training on C4 systems before the timed steps (0: no learned form)")
     ap.add_argument("--learned-seeds", default="1000-1015")
+    ap.add_argument("--theta", type=float, default=0.99, help="the learned form's fallback threshold")
+    ap.add_argument("--no-profile", action="store_true", help="skip the untimed kernel-timing step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with one device-to-device copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -112,12 +207,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    cfg = I.preset(args.workload, seed=args.seed)
+    wl = args.workload.upper()
+    cfg = I.preset(wl, seed=args.seed)
+    dforms, dextra = WORKLOAD_FORMS.get(wl, ("gmres_bilu0", ""))
+    forms = [f for f in (args.forms if args.forms is not None else dforms).split(",") if f]
+    extra = [f for f in (args.extra_forms if args.extra_forms is not None else dextra).split(",") if f]
     t0 = time.time()
     lnk = I.lnk(cfg)
     B = I.blocks(cfg, lnk)
     xt = I.x_true(cfg)
-    log(f"generated {args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} in {time.time() - t0:.1f}s")
+    log(f"generated {wl} {cfg.nx}x{cfg.ny}x{cfg.nz} in {time.time() - t0:.1f}s")
     Bd = torch.from_numpy(B).to(dev)
     xtd = torch.from_numpy(xt).to(dev)
     ctx = rsv.Context(0)
@@ -135,28 +234,26 @@ def main():
     A.spmv(xtd, b)          # manufactured right-hand side, on the GPU
     torch.cuda.synchronize()
 
+    ras = dict(ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1)
     forms_all = {
         "bicgstab_bilu0": (rsv.BICGSTAB, dict(type=rsv.PC_BILU0)),
-        "gmres_ras64": (rsv.GMRES, dict(type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1)),
-        "gmres_ras64_fp32": (rsv.GMRES, dict(type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1,
-                                              precision=rsv.FP32)),
-        "bicgstab_ras64": (rsv.BICGSTAB, dict(type=rsv.PC_RAS, ras_px=4, ras_py=4, ras_pz=4, ras_overlap=1)),
+        "gmres_ras64": (rsv.GMRES, dict(type=rsv.PC_RAS, **ras)),
+        "gmres_ras64_fp32": (rsv.GMRES, dict(type=rsv.PC_RAS, precision=rsv.FP32, **ras)),
+        "bicgstab_ras64": (rsv.BICGSTAB, dict(type=rsv.PC_RAS, **ras)),
         "gmres_bilu0": (rsv.GMRES, dict(type=rsv.PC_BILU0)),
         "gmres_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_BILU0, precision=rsv.FP32)),
     }
     # the same GMRES forms with the delayed second Gram-Schmidt pass
     for f in ("gmres_ras64", "gmres_bilu0", "gmres_ras64_fp32"):
         forms_all[f + "_dcgs2"] = forms_all[f]
-    forms = [f for f in args.forms.split(",") if f]
     net = None
-    lnk32 = None
     training = None
     if args.net or args.learned_steps > 0:
         net = rsv.Net(ctx)
         if args.net:
             net.load(args.net)
         else:
-            # train on C4-shaped systems (disjoint seeds), reported apart from the solves
+            # train on 64x64x32 systems (disjoint seeds), reported apart from the solves
             from paper_1602_05901_amd import train as T
             t0 = time.perf_counter()
             a, z = (int(v) for v in args.learned_seeds.split("-"))
@@ -179,12 +276,38 @@ def main():
                 d[4].close()
             del data
         lnk32 = torch.from_numpy(lnk.astype(np.float32)).to(dev)
-        forms_all["fgmres_learned"] = (rsv.FGMRES, dict(type=rsv.PC_LEARNED, net=net, lnk=lnk32))
+        forms_all["fgmres_learned"] = (rsv.FGMRES, dict(type=rsv.PC_LEARNED, net=net, lnk=lnk32, theta=args.theta))
         forms.append("fgmres_learned")
 
     hbm_peak = [0]   # device memory in use (all allocations, torch and the library) after each solve
 
-    def step(profile_headline=False):
+    def run_form(name, profile=False, keep_x=False):
+        method, pkw = forms_all[name]
+        t1 = time.perf_counter()
+        M = rsv.Precond(A, **pkw)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        x = torch.zeros_like(b)
+        if profile:
+            ctx.profile(True, classes=("spmv", "ilu_fwd", "ilu_bwd", "ortho"))
+        st = rsv.solve(A, M, b, x, method=method, restart=30, tol=1e-8, maxit=10000,
+                       ortho=(rsv.DCGS2 if name.endswith("_dcgs2") else rsv.CGS2))
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        kern = None
+        if profile:
+            kern = ctx.profile_read()
+            ctx.profile(False)
+        free_b, total_b = torch.cuda.mem_get_info()
+        hbm_peak[0] = max(hbm_peak[0], total_b - free_b)
+        err = float(torch.linalg.norm(x - xtd) / torch.linalg.norm(xtd))
+        out = {"setup_s": t2 - t1, "solve_s": t3 - t2, "its": st["its"], "relres": st["final_relres"],
+               "status": st["status"], "err_vs_xtrue": err, "fallbacks": st["fallbacks"]}
+        M.close()
+        assert st["status"] == rsv.OK and st["final_relres"] <= 1e-8, (name, st)
+        return out, kern, (x if keep_x else None)
+
+    def step():
         out = {}
         torch.cuda.synchronize()
         ta = time.perf_counter()
@@ -192,30 +315,7 @@ def main():
         torch.cuda.synchronize()
         out["assemble_s"] = time.perf_counter() - ta
         for name in forms:
-            method, pkw = forms_all[name]
-            prof = profile_headline and (name == forms[0] or name == "bicgstab_bilu0")
-            t1 = time.perf_counter()
-            M = rsv.Precond(A, **pkw)
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            x = torch.zeros_like(b)
-            if prof:
-                # two events per recorded launch: only the classes the roofline needs
-                ctx.profile(True, classes=("spmv", "ilu_fwd", "ilu_bwd"))
-            st = rsv.solve(A, M, b, x, method=method, restart=30, tol=1e-8, maxit=10000,
-                           ortho=(rsv.DCGS2 if name.endswith("_dcgs2") else rsv.CGS2))
-            torch.cuda.synchronize()
-            t3 = time.perf_counter()
-            if prof:
-                out["kernels_" + name] = ctx.profile_read()
-                ctx.profile(False)
-            free_b, total_b = torch.cuda.mem_get_info()
-            hbm_peak[0] = max(hbm_peak[0], total_b - free_b)
-            err = float(torch.linalg.norm(x - xtd) / torch.linalg.norm(xtd))
-            out[name] = {"setup_s": t2 - t1, "solve_s": t3 - t2, "its": st["its"], "relres": st["final_relres"],
-                         "status": st["status"], "err_vs_xtrue": err, "fallbacks": st["fallbacks"]}
-            M.close()
-            assert st["status"] == rsv.OK and st["final_relres"] <= 1e-8, (name, st)
+            out[name] = run_form(name)[0]
         return out
 
     for w in range(args.warmup):
@@ -225,7 +325,7 @@ def main():
     res = []
     tt = time.perf_counter()
     for s in range(args.steps):
-        r = step(profile_headline=True)
+        r = step()
         res.append(r)
         log(f"step {s}: " + ", ".join(f"{k} {r[k]['solve_s'] * 1e3:.1f}ms/{r[k]['its']}its" for k in forms))
     torch.cuda.synchronize()
@@ -238,14 +338,33 @@ def main():
     summary = {f: {"solve_s": med(f, "solve_s"), "setup_s": med(f, "setup_s"), "its": res[-1][f]["its"],
                    "relres": res[-1][f]["relres"], "err_vs_xtrue": res[-1][f]["err_vs_xtrue"],
                    "fallbacks": res[-1][f]["fallbacks"]} for f in forms}
-    # live kernel timing (HIP events on the solver stream), per profiled form
+
+    # -------- after the timed steps: kernel timing, the FP64 oracle's view of each
+    # result, and the forms run once
     ab_global = algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz)
     ab_ras = None
+    kernels_by_form = {}
+    xs = {}
+    if not args.no_profile:
+        for f in forms:
+            o, kern, x = run_form(f, profile=True, keep_x=True)
+            kernels_by_form[f] = kern
+            xs[f] = x.cpu().numpy()
+            del x
+    solves_once = {}
+    for f in extra:
+        o, kern, x = run_form(f, profile=not args.no_profile, keep_x=True)
+        solves_once[f] = o
+        kernels_by_form[f] = kern
+        xs[f] = x.cpu().numpy()
+        del x
+        log(f"{f}: {o['solve_s'] * 1e3:.1f}ms/{o['its']}its")
 
     def kernel_table(form):
         nonlocal ab_ras
-        kms = {k: sum(r["kernels_" + form][k][0] for r in res) for k in rsv.K_NAMES}
-        kcnt = {k: sum(r["kernels_" + form][k][1] for r in res) for k in rsv.K_NAMES}
+        kr = kernels_by_form[form]
+        kms = {k: kr[k][0] for k in rsv.K_NAMES}
+        kcnt = {k: kr[k][1] for k in rsv.K_NAMES}
         ab = dict(ab_global)
         if forms_all[form][0] != rsv.BICGSTAB:
             # GMRES products (y = A z with ||y||^2) read no third vector; the few
@@ -257,62 +376,66 @@ def main():
             ab_ras = ras_algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz, (pk["ras_px"], pk["ras_py"], pk["ras_pz"]),
                                            pk["ras_overlap"])
             ab["ilu_fwd"], ab["ilu_bwd"] = ab_ras["ilu_fwd"], ab_ras["ilu_bwd"]
-        tab = {k: {"avg_us": 1e3 * kms[k] / kcnt[k], "launches": kcnt[k],
+        tab = {k: {"avg_us": 1e3 * kms[k] / kcnt[k], "launches": kcnt[k], "total_ms": kms[k],
                    "GBps": (ab[k] / (kms[k] / kcnt[k] * 1e-3) / 1e9) if k in ab and k != "ilu_apply" else None}
                for k in rsv.K_NAMES if kcnt[k] > 0}
         return kms, kcnt, ab, tab
 
-    kms, kcnt, ab, kernels_head = kernel_table(head)
-    cand = [k for k in ("spmv", "ilu_fwd", "ilu_bwd") if kcnt[k] > 0]
-    dom = max(cand, key=lambda k: kms[k])
-    avg_ms = kms[dom] / kcnt[dom]
-    achieved = ab[dom] / (avg_ms * 1e-3) / 1e9
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tpath):
-        try:
-            tj = json.load(open(tpath))
-            if tj.get("workload") == args.workload:
-                traffic = tj["forms"][head]["kernels"][dom]["bytes_per_launch"]
-        except Exception:  # noqa: BLE001
-            traffic = None
-    roofline = {"bound": "hbm", "kernel": dom, "form": head, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": ab[dom], "avg_launch_us": round(avg_ms * 1e3, 2)}
-    # the global BILU0 and SpMV kernels, from the BiCGSTAB + BILU0 solves
-    kernels = None
-    ilu_GBps = spmv_GBps = None
-    if "bicgstab_bilu0" in forms:
-        bk_ms, bk_cnt, bab, kernels = kernel_table("bicgstab_bilu0")
-        if bk_cnt["ilu_fwd"]:
-            ilu_ms = (bk_ms["ilu_fwd"] + bk_ms["ilu_bwd"]) / bk_cnt["ilu_fwd"]
-            ilu_GBps = round(bab["ilu_apply"] / (ilu_ms * 1e-3) / 1e9, 1)
-        spmv_GBps = kernels.get("spmv", {}).get("GBps")
+    roofline = None
+    kernels = {}
+    if kernels_by_form:
+        kms, kcnt, ab, kernels_head = kernel_table(head)
+        kernels[head] = kernels_head
+        for f in kernels_by_form:
+            if f != head:
+                kernels[f] = kernel_table(f)[3]
+        cand = [k for k in ("spmv", "ilu_fwd", "ilu_bwd") if kcnt[k] > 0]
+        dom = max(cand, key=lambda k: kms[k])
+        avg_ms = kms[dom] / kcnt[dom]
+        achieved = ab[dom] / (avg_ms * 1e-3) / 1e9
+        traffic = None
+        tpath = os.path.join(ROOT, "profiles", "traffic.json")
+        if os.path.exists(tpath):
+            try:
+                tj = json.load(open(tpath))
+                traffic = tj["workloads"][wl]["forms"][head]["kernels"][dom]["bytes_per_launch"]
+            except Exception:  # noqa: BLE001
+                traffic = None
+        roofline = {"bound": "hbm", "kernel": dom, "form": head, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "algorithmic_bytes_per_launch": ab[dom],
+                    "avg_launch_us": round(avg_ms * 1e3, 2),
+                    "share_of_solve_kernel_time": {k: round(kms[k] / max(sum(kms.values()), 1e-30), 3)
+                                                   for k in ("spmv", "ilu_fwd", "ilu_bwd", "ortho")},
+                    "timing": "HIP events on the solver stream in one untimed solve after the timed steps"}
 
-    cpu = None
-    if not args.no_cpu_baseline:
+    # the FP64 oracle's product recomputes the relative residual of every
+    # returned solution; each solution is also compared with the FP64 one
+    oracle_view = None
+    Ao = bo = None
+    t_build = 0.0
+    if xs or not args.no_cpu_baseline:
         import oracle as O
-        os.environ.setdefault("OMP_NUM_THREADS", "1")
         t0 = time.perf_counter()
         Ao = O.BCSR.from_stencil(cfg.nx, cfg.ny, cfg.nz, B)
         bo = Ao.spmv(xt)
-        t1 = time.perf_counter()
-        method, pk = forms_all[head]
-        if pk.get("type") == rsv.PC_RAS:
-            F = O.RAS(Ao, (cfg.nx, cfg.ny, cfg.nz), (pk["ras_px"], pk["ras_py"], pk["ras_pz"]), pk["ras_overlap"])
-            ro = O.gmres(Ao, bo, pc=F, m=30, tol=1e-8, maxit=10000)
-            what = "GMRES(30)+RAS(%dx%dx%d, overlap %d) solve (RAS setup" % (pk["ras_px"], pk["ras_py"], pk["ras_pz"],
-                                                                          pk["ras_overlap"])
-        else:
-            F = O.ILU(Ao)
-            ro = O.bicgstab(Ao, bo, pc=F, tol=1e-8, maxit=10000)
-            what = "BiCGSTAB+BILU0 solve (ILU(0) setup"
-        t2 = time.perf_counter()
-        cpu = {"value": round(t2 - t1, 3), "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": f"full {args.workload} {what} + {ro['its']} iterations, "
-                         f"relres {ro['relres']:.2e}), serial FP64 C on one host thread "
-                         f"(the host has {os.cpu_count()} logical cores)"}
-        log(f"oracle: {t2 - t1:.2f}s ({ro['its']} its)")
+        t_build = time.perf_counter() - t0
+    if xs:
+        t0 = time.perf_counter()
+        nbo = float(np.linalg.norm(bo))
+        ref = xs.get("gmres_bilu0", xs[head])
+        oracle_view = {}
+        for f, x in xs.items():
+            oracle_view[f] = {"relres_by_oracle_spmv": float(np.linalg.norm(bo - Ao.spmv(x)) / nbo),
+                              "err_vs_fp64_gmres_bilu0_solution": float(np.linalg.norm(x - ref) / np.linalg.norm(ref))}
+        log(f"oracle residual check in {time.perf_counter() - t0:.1f}s: {oracle_view}")
+    xs.clear()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        os.environ.setdefault("OMP_NUM_THREADS", "1")
+        cpu = oracle_baseline(cfg, Ao, bo, t_build, forms_all[head], summary[head]["its"])
+    del Ao, bo
 
     # the runtime's device-to-device copy rate beside the vendor peak, for context
     # (1 GiB read + 1 GiB written, median of five, outside the timed steps)
@@ -329,7 +452,8 @@ def main():
         ct.append(e0.elapsed_time(e1) * 1e-3)
     copy_GBps = round(2 * csrc.numel() * 8 / float(np.median(ct)) / 1e9, 1)
     del csrc, cdst
-    roofline["d2d_copy_GBps"] = copy_GBps
+    if roofline is not None:
+        roofline["d2d_copy_GBps"] = copy_GBps
 
     value = summary[head]["solve_s"]
     line = {
@@ -345,12 +469,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} 3x3-block 7-point, "
-                               f"headline {head}, tol 1e-8", "unknowns": 3 * cfg.ncell,
-                   "forms": forms, "seed": args.seed},
+        "config": {"workload": f"{wl} {cfg.nx}x{cfg.ny}x{cfg.nz} 3x3-block 7-point, headline {head}, tol 1e-8",
+                   "unknowns": 3 * cfg.ncell, "forms": forms, "forms_once": extra, "seed": args.seed,
+                   "step": "re-assemble from device blocks, then setup + solve of every form in forms"},
         "solves": summary,
+        "solves_once": solves_once,
         "vs_plain_gmres_bilu0": ({f: round(summary[f]["solve_s"] / summary["gmres_bilu0"]["solve_s"], 3) for f in forms}
                                  if "gmres_bilu0" in summary else None),
+        "oracle_view": oracle_view,
         "learned_training": training,
         # unknowns x iterations per second of the headline solve, beside the paper's
         # closest published figure (scalar Poisson on a CPU cluster): context only
@@ -360,10 +486,7 @@ def main():
                           "hardware": "IBM Blue Gene/Q, 512 cores (PowerPC A2)",
                           "solve_s": 606.33, "unknown_iterations_per_s": round(3e9 * 90 / 606.33, 1),
                           "note": "solve time = overall - gridding - building - assemble of its 512-core row"},
-        "ilu_apply_GBps": ilu_GBps,
-        "spmv_GBps": spmv_GBps,
         "kernels": kernels,
-        "kernels_headline": kernels_head,
         "ras_local": ab_ras,
         "roofline": roofline,
         "cpu_baseline": cpu,
