@@ -187,6 +187,21 @@ void rsv_matrix_destroy(rsv_matrix *A);
 /* y = alpha*A*x + beta*y (Algebraic Operations: y = alpha A x + beta y);
  * x, y device vectors of length 3*ncell (must not alias). */
 rsv_status rsv_spmv(rsv_matrix *A, double alpha, const double *x, double beta, double *y);
+/* The same product for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the tile-lane staging copies of x and A x live in a fixed
+ * per-device scratch array of RSV_NOALLOC_SCRATCH_BYTES that the library
+ * holds from the first context on the device until the process ends, so no
+ * call allocates (rsv_spmv reserves the matrix's solver workspace instead).
+ * The grid must satisfy 2 x 3 x (padded cells) x 8 bytes <= the scratch size,
+ * i.e. 48 x ceil(nx/8) x ceil(ny/8) x 64 x nz <= RSV_NOALLOC_SCRATCH_BYTES
+ * (128x128x64 fits), else RSV_ERR_ARG and nothing runs.  Every call on a
+ * device shares that device's scratch: calls that overlap on one GPU (two
+ * streams, two host threads) race and must be ordered by the caller.  Each
+ * call writes all the scratch it reads, so nothing carries over between
+ * calls.  Synchronises the context's stream before returning, like rsv_spmv. */
+#define RSV_NOALLOC_SCRATCH_BYTES (64ll << 20)
+rsv_status rsv_spmv_noalloc(rsv_matrix *A, double alpha, const double *x, double beta, double *y);
 /* Device bytes held by the matrix and its solver workspace (diagnostics;
  * preconditioners are separate objects and not counted). */
 int64_t rsv_matrix_device_bytes(const rsv_matrix *A);

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 static thread_local std::string g_last_static_err;
@@ -50,6 +51,34 @@ rsv_status flags_check(rsv_ctx *c, int64_t *bad_cell)
     if (f[0] & FLAG_PATTERN) return set_err(c, RSV_ERR_PATTERN, "nonzero block toward a missing neighbour");
     if (f[0] & FLAG_NAN) return set_err(c, RSV_ERR_NAN, "non-finite matrix entry");
     if (f[0] & FLAG_PIVOT) return set_err(c, RSV_ERR_ZERO_PIVOT, "zero or near-singular 3x3 pivot");
+    return RSV_OK;
+}
+
+// ------------------------------------------------------------------ fixed scratch
+// The device memory of the entry points that allocate nothing: one
+// file-scope array, a copy of which each device holds from the first context
+// created on it until the process ends.  On the host the array's name is only
+// a stand-in, never a device address: host code uses the address that
+// hipGetSymbolAddress returns, looked up once per device (with that device
+// current) and kept per device.
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[MAX_DEVICES] = {};
+
+rsv_status scratch_lookup(rsv_ctx *c)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (c->device < 0 || c->device >= MAX_DEVICES) return set_err(c, RSV_ERR_ARG, "device ordinal beyond the scratch table");
+    if (!g_scratch_ptr[c->device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return set_err(c, RSV_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[c->device] = (double *)p;
+    }
+    c->d_scratch = g_scratch_ptr[c->device];
     return RSV_OK;
 }
 
@@ -198,6 +227,7 @@ rsv_status rsv_create(int32_t dev, rsv_ctx **out)
     if (s == RSV_OK && hipMemset(c->d_tickets, 0, 8 * sizeof(uint64_t)) != hipSuccess) s = RSV_ERR_HIP;
     if (s == RSV_OK && hipMemset(c->d_scal, 0, SC_COUNT * sizeof(double)) != hipSuccess) s = RSV_ERR_HIP;
     if (s == RSV_OK) s = flags_reset(c);
+    if (s == RSV_OK) s = scratch_lookup(c);   // device current: set above
     if (s != RSV_OK) {
         g_last_static_err = c->err.empty() ? "context allocation failed" : c->err;
         rsv_destroy(c);

@@ -134,6 +134,7 @@ struct rsv_ctx {
     uint64_t *d_tickets = nullptr;// tile ticket counters (8 counters)
     uint64_t ticket_base[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int32_t *d_flags = nullptr;   // [0] error flags, [1] bad cell (min)
+    double *d_scratch = nullptr;  // this device's fixed scratch (rsv_spmv_noalloc), not owned
     int num_cu = 256;
     int lds_max = 65536;               // dynamic LDS bytes a workgroup may use
     int lds_per_cu = 0;
@@ -245,6 +246,12 @@ rsv_status launch_combine(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, i
 // corrected, w projected and normalised; four step scalars after the dots)
 // DCGS2 breakdown threshold: a squared norm below this fraction of ||w||^2,
 // obtained as a difference of squares, is lost to rounding
+// Fixed per-device scratch of the entry points that allocate nothing
+// (RSV_NOALLOC_SCRATCH_BYTES in rsv.h), in doubles.
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = (int64_t)RSV_NOALLOC_SCRATCH_BYTES / 8;
+constexpr int MAX_DEVICES = 64;
+rsv_status scratch_lookup(rsv_ctx *c);
+
 constexpr double DCGS_LOST = 64.0 * 2.220446049250313e-16;   // 64 x DBL_EPSILON
 rsv_status launch_dcgs_dots(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, const double *w, int k0);
 rsv_status launch_dcgs_update(rsv_ctx *c, int64_t n, double *V, int64_t ldv, int K, double *w, int kd);

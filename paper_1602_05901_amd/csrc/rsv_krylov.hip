@@ -520,6 +520,29 @@ rsv_status rsv_spmv(rsv_matrix *M, double alpha, const double *x, double beta, d
     return s;
 }
 
+rsv_status rsv_spmv_noalloc(rsv_matrix *M, double alpha, const double *x, double beta, double *y)
+{
+    if (!M || !x || !y) return set_err(M ? M->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");
+    rsv_ctx *c = M->g->ctx;
+    const int64_t n = M->g->nv;
+    if (!c->d_scratch) return set_err(c, RSV_ERR_ARG, "no fixed scratch on this device");
+    if (2 * n > NOALLOC_SCRATCH_DOUBLES)
+        return set_err(c, RSV_ERR_ARG, "grid too large for the fixed scratch (" + std::to_string(16 * n) + " > " +
+                                           std::to_string((long long)RSV_NOALLOC_SCRATCH_BYTES) + " bytes)");
+    // the same kernels as rsv_spmv, on the fixed scratch: x is laid out into
+    // the first half (every slot written, absent cells as zero), A x into the
+    // second (every slot written), then read back into y
+    double *xt = c->d_scratch, *yt = c->d_scratch + n;
+    rsv_status s = launch_nat_to_tl(c, M->g->geo, x, xt);
+    if (s == RSV_OK) s = launch_spmv(c, M->g->geo, M->d_A, SPMV_Y, xt, yt, nullptr, 1.0, 0.0, 0);
+    if (s == RSV_OK) s = launch_tl_to_nat(c, M->g->geo, yt, y, alpha, beta);
+    if (s == RSV_OK) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) s = set_err(c, RSV_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
+    }
+    return s;
+}
+
 rsv_status rsv_precond_apply(rsv_precond *P, const double *r, double *z)
 {
     if (!P || !r || !z) return set_err(P ? P->A->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");

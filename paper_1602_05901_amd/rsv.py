@@ -66,6 +66,7 @@ _SIGS = {
     "rsv_matrix_update": ([vp, vp, i32], i32),
     "rsv_matrix_destroy": ([vp], None),
     "rsv_spmv": ([vp, dbl, vp, dbl, vp], i32),
+    "rsv_spmv_noalloc": ([vp, dbl, vp, dbl, vp], i32),
     "rsv_matrix_device_bytes": ([vp], i64),
     "rsv_pc_params_default": ([_P(PcParams)], None),
     "rsv_precond_setup": ([vp, _P(PcParams), _P(vp), _P(i64)], i32),
@@ -224,6 +225,11 @@ class Matrix:
 
     def spmv(self, x, y, alpha=1.0, beta=0.0):
         _check(self.ctx, lib().rsv_spmv(self.h, alpha, _ptr(x), beta, _ptr(y)))
+        return y
+
+    def spmv_noalloc(self, x, y, alpha=1.0, beta=0.0):
+        """The same product with the library's fixed per-device scratch (no allocation)."""
+        _check(self.ctx, lib().rsv_spmv_noalloc(self.h, alpha, _ptr(x), beta, _ptr(y)))
         return y
 
     @property
