@@ -189,7 +189,7 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=1500,
                     help="without --net: Adam steps of training on C4 systems before the timed steps (0: no learned form)")
     ap.add_argument("--learned-seeds", default="1000-1015")
-    ap.add_argument("--theta", type=float, default=0.99, help="the learned form's fallback threshold")
+    ap.add_argument("--theta", type=float, default=0.9, help="the learned form's fallback threshold")
     ap.add_argument("--no-profile", action="store_true", help="skip the untimed kernel-timing step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with one device-to-device copy of 1 GiB (calibrates HBM byte counters)")

@@ -96,7 +96,9 @@ typedef struct rsv_pc_params {
                           * per hyperplane, RAS one workgroup per subdomain (reference mappings) */
     rsv_net *net;        /* LEARNED: trained network (not owned) */
     const float *lnk;    /* LEARNED: DEVICE pointer, ln k per cell in block-row order (not copied; must outlive the precond) */
-    double theta;        /* LEARNED: fallback when a step's residual estimate exceeds theta * previous (default 0.99) */
+    double theta;        /* LEARNED: fallback when a step's residual estimate exceeds theta * previous (default 0.9, the
+                            best of 0.99 / 0.9 / 0.8 / 0.5 on 64 held-out 64x64x32 systems at which the
+                            network is still accepted on some columns) */
     int32_t learned_mode;/* LEARNED: 0 (default) z = s N(r/s); 1 z = t + s N(r1/s) with t = BILU0^-1 r,
                           * r1 = r - A t, s = rms(r1): the network corrects what one BILU0 step leaves */
     int32_t ras_stack;   /* RAS, pipelined: subdomain boxes stacked per tile column of the auxiliary
@@ -202,6 +204,11 @@ rsv_status rsv_spmv(rsv_matrix *A, double alpha, const double *x, double beta, d
  * calls.  Synchronises the context's stream before returning, like rsv_spmv. */
 #define RSV_NOALLOC_SCRATCH_BYTES (64ll << 20)
 rsv_status rsv_spmv_noalloc(rsv_matrix *A, double alpha, const double *x, double beta, double *y);
+/* y = alpha*x + beta*y on device vectors of length n (the vector update of
+ * the Algebraic Operations subsection), enqueued on the context's stream
+ * without a synchronisation; x and y may be the same vector.  beta = 0 does
+ * not read y.  Used, for example, to form training targets e = x_true - x. */
+rsv_status rsv_axpby(rsv_ctx *ctx, int64_t n, double alpha, const double *x, double beta, double *y);
 /* Device bytes held by the matrix and its solver workspace (diagnostics;
  * preconditioners are separate objects and not counted). */
 int64_t rsv_matrix_device_bytes(const rsv_matrix *A);

@@ -419,7 +419,7 @@ void rsv_pc_params_default(rsv_pc_params *p)
     p->ras_overlap = 1;
     p->iluk_level = 0;
     p->pipelined = 1;
-    p->theta = 0.99;
+    p->theta = 0.9;
 }
 
 void rsv_solver_params_default(rsv_solver_params *p)

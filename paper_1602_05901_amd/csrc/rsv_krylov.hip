@@ -520,6 +520,13 @@ rsv_status rsv_spmv(rsv_matrix *M, double alpha, const double *x, double beta, d
     return s;
 }
 
+rsv_status rsv_axpby(rsv_ctx *c, int64_t n, double alpha, const double *x, double beta, double *y)
+{
+    if (!c || !x || !y || n < 0) return set_err(c, RSV_ERR_ARG, "bad argument");
+    if (n == 0) return RSV_OK;
+    return launch_axpby(c, n, alpha, x, beta, y);
+}
+
 rsv_status rsv_spmv_noalloc(rsv_matrix *M, double alpha, const double *x, double beta, double *y)
 {
     if (!M || !x || !y) return set_err(M ? M->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");

@@ -67,6 +67,7 @@ _SIGS = {
     "rsv_matrix_destroy": ([vp], None),
     "rsv_spmv": ([vp, dbl, vp, dbl, vp], i32),
     "rsv_spmv_noalloc": ([vp, dbl, vp, dbl, vp], i32),
+    "rsv_axpby": ([vp, i64, dbl, vp, dbl, vp], i32),
     "rsv_matrix_device_bytes": ([vp], i64),
     "rsv_pc_params_default": ([_P(PcParams)], None),
     "rsv_precond_setup": ([vp, _P(PcParams), _P(vp), _P(i64)], i32),
@@ -181,6 +182,12 @@ class Context:
             self.close()
         except Exception:  # noqa: BLE001
             pass
+
+
+def axpby(ctx: "Context", alpha, x, beta, y):
+    """y = alpha x + beta y on device tensors (the library's vector update)."""
+    _check(ctx, lib().rsv_axpby(ctx.h, y.numel(), alpha, _ptr(x), beta, _ptr(y)))
+    return y
 
 
 class Grid:

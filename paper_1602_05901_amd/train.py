@@ -66,14 +66,17 @@ def harvest(ctx, sysm: System, every=5, restart=30, tol=1e-8, maxit=5000, mode=0
         x.zero_()
         if k > 0:
             rsv.solve(sysm.A, M, sysm.b, x, method=rsv.GMRES, restart=restart, tol=0.0, maxit=k)
+        # r = b - A x and e = x_true - x with the library's product and vector
+        # update (the clones only copy memory)
         r = sysm.b.clone()
         sysm.A.spmv(x, r, alpha=-1.0, beta=1.0)
-        e = sysm.xt - x
+        e = sysm.xt.clone()
+        rsv.axpby(ctx, -1.0, x, 1.0, e)
         if mode == 1:
             t = torch.zeros_like(r)
             M.apply(r, t)
             sysm.A.spmv(t, r, alpha=-1.0, beta=1.0)
-            e = e - t
+            rsv.axpby(ctx, -1.0, t, 1.0, e)
         rs.append(r)
         es.append(e)
     M.close()
@@ -143,8 +146,12 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--net-seed", type=int, default=0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--load", default=None, help="evaluate a saved network instead of training one")
     ap.add_argument("--thetas", default="", help="extra fallback thresholds to evaluate, comma separated")
     ap.add_argument("--mode", type=int, default=0, help="0: the network maps the residual; 1: it corrects one BILU0 step")
+    ap.add_argument("--eval-size", default="",
+                    help="nx,ny,nz of the held-out systems (the workload's recipe at another size)")
+    ap.add_argument("--theta", type=float, default=0.99, help="fallback threshold of the 'learned' runs")
     ap.add_argument("--maxit-alone", type=int, default=3000,
                     help="step limit for the network alone and for no preconditioner")
     args = ap.parse_args(argv)
@@ -158,7 +165,7 @@ def main(argv=None):
     ctx = rsv.Context(0)
     t0 = time.perf_counter()
     data, nits = [], []
-    for s in _seeds(args.seeds):
+    for s in ([] if args.load else _seeds(args.seeds)):
         sy = System(ctx, I.preset(args.workload, seed=s))
         R, E, K = harvest(ctx, sy, mode=args.mode)
         data.append((sy.g, R, E, sy.lnk))
@@ -166,22 +173,32 @@ def main(argv=None):
         sy._keep = sy
     t_h = time.perf_counter() - t0
     npairs = sum(d[1].shape[0] for d in data)
-    log(f"harvested {npairs} pairs from {len(data)} systems in {t_h:.1f}s (plain its {np.mean(nits):.1f})")
     net = rsv.Net(ctx, seed=args.net_seed)
     untrained = rsv.Net(ctx, seed=args.net_seed)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    losses = train(ctx, net, data, args.steps, args.batch, args.lr, seed=args.net_seed, log=log)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    if args.load:
+        net.load(args.load)
+        losses, t_train = [float("nan")], 0.0
+    else:
+        log(f"harvested {npairs} pairs from {len(data)} systems in {t_h:.1f}s (plain its {np.mean(nits):.1f})")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = train(ctx, net, data, args.steps, args.batch, args.lr, seed=args.net_seed, log=log)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
     if args.out:
         net.save(args.out)
     rows = []
     for s in _seeds(args.eval_seeds):
-        sy = System(ctx, I.preset(args.workload, seed=s))
-        row = {"seed": s}
+        cfg = I.preset(args.workload, seed=s)
+        if args.eval_size:
+            nx, ny, nz = (int(v) for v in args.eval_size.split(","))
+            cfg = cfg.replace(nx=nx, ny=ny, nz=nz)
+        sy = System(ctx, cfg)
+        row = {"seed": s, "grid": [cfg.nx, cfg.ny, cfg.nz]}
         md = args.mode
-        runs = [("plain", dict()), ("learned", dict(net=net, mode=md)), ("untrained", dict(net=untrained, mode=md)),
+        th = args.theta
+        runs = [("plain", dict()), ("learned", dict(net=net, mode=md, theta=th)),
+                ("untrained", dict(net=untrained, mode=md, theta=th)),
                 ("learned_only", dict(net=net, theta=float("inf"), maxit=args.maxit_alone, mode=md)),
                 ("no_preconditioner", dict(none=True, maxit=args.maxit_alone))]
         runs += [(f"learned_theta_{t}", dict(net=net, theta=t, mode=md)) for t in args.thetas]

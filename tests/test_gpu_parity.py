@@ -670,6 +670,23 @@ def test_unpreconditioned_and_edge_cases(rsv, ctx):
     S.close()
 
 
+def test_axpby(rsv, ctx):
+    """The library's vector update y = alpha x + beta y, per entry within
+    the rounding of one fused multiply-add; beta = 0 does not read y."""
+    n = 100003
+    x = I.test_vector(48, n)
+    y0 = I.test_vector(49, n)
+    y = dev(y0)
+    rsv.axpby(ctx, 0.5, dev(x), -2.0, y)
+    torch.cuda.synchronize()
+    ref = 0.5 * x - 2.0 * y0
+    assert_elementwise(y.cpu().numpy(), ref, 2.3e-16, 0.5 * np.abs(x) + 2.0 * np.abs(y0))
+    y = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    rsv.axpby(ctx, 3.0, dev(x), 0.0, y)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), 3.0 * x)
+
+
 def test_exact_preconditioner_one_step(rsv, ctx):
     """1-D grid: BILU0 is the exact LU, GMRES and BiCGSTAB converge in one step."""
     cfg = cfg_of((40, 1, 1), seed=19, sigma=2.0)
