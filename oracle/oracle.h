@@ -121,6 +121,13 @@ int     orc_unet_loss_grad(int c0, int c1, int c2, int nx, int ny, int nz, const
 double  orc_unet_prepare(int nx, int ny, int nz, const double *r, const double *lnk, double *x0);
 void    orc_adam(int64_t n, double *p, const double *g, double *m, double *v, int64_t t, double lr);
 
+/* ---- Hilbert space-filling-curve partition (hsfc.c) ---- */
+int orc_hsfc_key3(const double *c, int32_t levels, uint64_t *key);        /* c in [0,1]^3, levels 1..21 */
+int orc_hsfc_grid_keys(int32_t nx, int32_t ny, int32_t nz, int32_t levels, uint64_t *keys);
+int orc_hsfc_partition(int64_t n, const uint64_t *keys, int32_t nparts, int32_t *part);
+int orc_partition_quality(int32_t nx, int32_t ny, int32_t nz, const int32_t *part, int32_t nparts, double *q,
+                          int64_t *per_part);
+
 /* plain dense 3x3 helpers exposed for the pins */
 int orc_inv3(const double *a, double *ainv);  /* LU with partial pivoting; 0 ok, -4 singular */
 

@@ -14,6 +14,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORC = os.path.join(ROOT, "oracle")
 PINS = "tests/test_oracle_pins_branches.py"
+HP = "tests/test_oracle_hsfc_pins.py"
 
 # (id, file, text in the oracle, replacement, pins that must fail)
 MUTATIONS = [
@@ -29,6 +30,15 @@ MUTATIONS = [
      [PINS + "::test_fgmres_acceptance_resets_the_consecutive_count"]),
     ("bicgstab_no_omega_exit", "oracle.c", "if (omega == 0.0) { rc = ORC_BREAKDOWN; break; }", "",
      [PINS + "::test_bicgstab_breakdown_exits[omega0]"]),
+    ("hsfc_table_entry", "hsfc.c", "{0, 7, 3, 4, 1, 6, 2, 5},", "{0, 7, 4, 3, 1, 6, 2, 5},",
+     [HP + "::test_keys_are_a_bijection_and_consecutive_points_are_neighbours[2]"]),
+    ("hsfc_bit_order", "hsfc.c", "const int bit = 31 - l;", "const int bit = 32 - levels + l;",
+     [HP + "::test_level_one_order_and_nesting"]),
+    ("partition_rank_rounding", "hsfc.c", "part[v[r].idx] = (int32_t)((r * (int64_t)nparts) / n);",
+     "part[v[r].idx] = (int32_t)(((r + 1) * (int64_t)nparts - 1) / n);",
+     [HP + "::test_partition_is_the_equal_count_cut_of_the_curve"]),
+    ("quality_inner_faces_twice", "hsfc.c", "else if (m > c) f[p]++;", "else f[p]++;",
+     [HP + "::test_quality_against_brute_force"]),
     ("bicgstab_no_rv_exit", "oracle.c",
      "if (rv == 0.0 || !isfinite(rv)) { rc = isfinite(rv) ? ORC_BREAKDOWN : ORC_ERR_NAN; break; }",
      "if (!isfinite(rv)) { rc = ORC_ERR_NAN; break; }",
@@ -39,7 +49,7 @@ MUTATIONS = [
 def _build(tmp, mutation=None):
     src = os.path.join(tmp, "src")
     os.makedirs(src, exist_ok=True)
-    for f in ("oracle.c", "unet.c", "oracle.h"):
+    for f in ("oracle.c", "unet.c", "hsfc.c", "oracle.h"):
         shutil.copy(os.path.join(ORC, f), src)
     if mutation is not None:
         _, fname, old, new, _ = mutation
@@ -49,7 +59,8 @@ def _build(tmp, mutation=None):
         open(path, "w").write(text.replace(old, new))
     lib = os.path.join(tmp, "liboracle_mut.so")
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", lib,
-                    os.path.join(src, "oracle.c"), os.path.join(src, "unet.c"), "-lm"], check=True)
+                    os.path.join(src, "oracle.c"), os.path.join(src, "unet.c"), os.path.join(src, "hsfc.c"), "-lm"],
+                   check=True)
     return lib
 
 
