@@ -328,6 +328,40 @@ rsv_status rsv_profile_classes(rsv_ctx *ctx, uint32_t mask);
  * counts (HOST arrays of RSV_K_COUNT entries; either may be NULL). */
 rsv_status rsv_profile_read(rsv_ctx *ctx, double *ms, int64_t *launches);
 
+/* ---------------------------------------------------------------- Hilbert space-filling-curve partition */
+/* Space-filling Partitioning Method section.  Keys: each point of [0,1]^3 is
+ * scaled by 2^32 - 1 and truncated to three 32-bit coordinates; level l
+ * (l = 0 first) reads bit 31 - l of each coordinate (x weight 4, y 2, z 1)
+ * and walks the 24-state machine of the paper's ordering and orientation
+ * tables (the table-driven Hilbert order figures), giving one base-8 digit
+ * per level, most significant first: a key of 3*levels bits.
+ *
+ * rsv_hsfc_keys: n points, coords DEVICE [n][3] FP64 in [0,1], levels in
+ * [1, 21], keys DEVICE uint64 [n].  A coordinate outside [0,1] or not a
+ * number: RSV_ERR_ARG (its key is 0).  Synchronises the stream. */
+rsv_status rsv_hsfc_keys(rsv_ctx *ctx, int64_t n, const double *coords, int32_t levels, uint64_t *keys);
+/* Keys of the grid's cells, DEVICE uint64 [ncell] in block-row order, from
+ * the cell centroids ((i, j, k) + 1/2) / max(nx, ny, nz): the linear map of
+ * the grid into [0,1)^3 that keeps cells cubic (step 1 of Algorithm
+ * "Space-filling curve method"). */
+rsv_status rsv_grid_hsfc_keys(rsv_grid *g, int32_t levels, uint64_t *keys);
+/* The equal-count cut of the curve (step 3 of that algorithm): with the n
+ * keys (DEVICE, from rsv_*hsfc_keys with the same levels) in increasing
+ * order, equal keys by index, the entry of rank r goes to part
+ * floor(r * nparts / n); part DEVICE int32 [n].  n <= 2^31.  Allocates its
+ * sort buffers (24 n bytes plus histograms) for the call. */
+rsv_status rsv_hsfc_partition(rsv_ctx *ctx, int64_t n, const uint64_t *keys, int32_t levels, int32_t nparts,
+                              int32_t *part);
+/* Partition quality (Partition Quality subsection) of part (DEVICE int32
+ * [ncell] in block-row order, values in [0, nparts), nparts <= 16384): per
+ * part |G_i|, f_i (faces of its cells, each once), b_i (those shared with
+ * another part) and c_i (parts it shares a face with).  q (HOST [5]): load
+ * imbalance N_p max|G_i| / sum|G_i|, max b_i/f_i, the global surface index
+ * sum b_i / (sum f_i - sum b_i), the average (1/N_p) sum b_i/f_i, max c_i.
+ * per_part (HOST [nparts][4], nullable).  A part number out of range:
+ * RSV_ERR_ARG. */
+rsv_status rsv_partition_quality(rsv_grid *g, const int32_t *part, int32_t nparts, double *q, int64_t *per_part);
+
 #ifdef __cplusplus
 }
 #endif

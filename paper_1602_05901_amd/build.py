@@ -20,6 +20,7 @@ HIP_SOURCES = [
     "csrc/rsv_ras.hip",
     "csrc/rsv_krylov.hip",
     "csrc/rsv_unet.hip",
+    "csrc/rsv_hsfc.hip",
 ]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

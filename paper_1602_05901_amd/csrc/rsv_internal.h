@@ -241,17 +241,17 @@ rsv_status launch_mdot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int 
 rsv_status launch_upd_dot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0);
 rsv_status launch_upd_norm(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0);
 rsv_status launch_combine(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, int ky, double *u, int accumulate);
-// DCGS2 step with K = j + 1 basis vectors V_0..V_j and w = V_{j+1}: the dots
-// V_i . [V_j, w] into d_scal[k0 .. k0 + 2K), then the combined update (V_j
-// corrected, w projected and normalised; four step scalars after the dots)
-// DCGS2 breakdown threshold: a squared norm below this fraction of ||w||^2,
-// obtained as a difference of squares, is lost to rounding
 // Fixed per-device scratch of the entry points that allocate nothing
 // (RSV_NOALLOC_SCRATCH_BYTES in rsv.h), in doubles.
 constexpr int64_t NOALLOC_SCRATCH_DOUBLES = (int64_t)RSV_NOALLOC_SCRATCH_BYTES / 8;
 constexpr int MAX_DEVICES = 64;
 rsv_status scratch_lookup(rsv_ctx *c);
 
+// DCGS2 step with K = j + 1 basis vectors V_0..V_j and w = V_{j+1}: the dots
+// V_i . [V_j, w] into d_scal[k0 .. k0 + 2K), then the combined update (V_j
+// corrected, w projected and normalised; four step scalars after the dots)
+// DCGS2 breakdown threshold: a squared norm below this fraction of ||w||^2,
+// obtained as a difference of squares, is lost to rounding
 constexpr double DCGS_LOST = 64.0 * 2.220446049250313e-16;   // 64 x DBL_EPSILON
 rsv_status launch_dcgs_dots(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, const double *w, int k0);
 rsv_status launch_dcgs_update(rsv_ctx *c, int64_t n, double *V, int64_t ldv, int K, double *w, int kd);

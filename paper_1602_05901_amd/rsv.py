@@ -68,6 +68,10 @@ _SIGS = {
     "rsv_spmv": ([vp, dbl, vp, dbl, vp], i32),
     "rsv_spmv_noalloc": ([vp, dbl, vp, dbl, vp], i32),
     "rsv_axpby": ([vp, i64, dbl, vp, dbl, vp], i32),
+    "rsv_hsfc_keys": ([vp, i64, vp, i32, vp], i32),
+    "rsv_grid_hsfc_keys": ([vp, i32, vp], i32),
+    "rsv_hsfc_partition": ([vp, i64, vp, i32, i32, vp], i32),
+    "rsv_partition_quality": ([vp, vp, i32, vp, vp], i32),
     "rsv_matrix_device_bytes": ([vp], i64),
     "rsv_pc_params_default": ([_P(PcParams)], None),
     "rsv_precond_setup": ([vp, _P(PcParams), _P(vp), _P(i64)], i32),
@@ -190,6 +194,18 @@ def axpby(ctx: "Context", alpha, x, beta, y):
     return y
 
 
+def hsfc_keys(ctx: "Context", coords, levels, keys):
+    """Hilbert keys of points (coords: device [n, 3] float64 in [0,1]; keys: device int64 [n])."""
+    _check(ctx, lib().rsv_hsfc_keys(ctx.h, keys.numel(), _ptr(coords), levels, _ptr(keys)))
+    return keys
+
+
+def hsfc_partition(ctx: "Context", keys, levels, nparts, part):
+    """Equal-count cut of the curve (keys: device int64 [n]; part: device int32 [n])."""
+    _check(ctx, lib().rsv_hsfc_partition(ctx.h, keys.numel(), _ptr(keys), levels, nparts, _ptr(part)))
+    return part
+
+
 class Grid:
     def __init__(self, ctx: Context, nx, ny, nz, ordering=BOTTOM_UP):
         h = vp()
@@ -199,6 +215,19 @@ class Grid:
     @property
     def ncell(self):
         return lib().rsv_grid_ncell(self.h)
+
+    def hsfc_keys(self, levels, keys):
+        """Hilbert keys of the cells (device int64 [ncell], block-row order)."""
+        _check(self.ctx, lib().rsv_grid_hsfc_keys(self.h, levels, _ptr(keys)))
+        return keys
+
+    def partition_quality(self, part, nparts):
+        """(q[5], per_part [nparts, 4]) of a partition (device int32 [ncell])."""
+        import numpy as np
+        q = np.zeros(5)
+        per = np.zeros((nparts, 4), np.int64)
+        _check(self.ctx, lib().rsv_partition_quality(self.h, _ptr(part), nparts, q.ctypes.data, per.ctypes.data))
+        return q, per
 
     def cell_to_row(self, i, j, k):
         r = i64()
