@@ -175,6 +175,63 @@ def oracle_baseline(cfg, Ao, bo, t_build, head_form, its_gpu, restart=30, full_l
             "per_basis_vector_s": round(c, 5), **host}
 
 
+def hsfc_measure(rsv, ctx, g, dims, levels, nparts, reps=5, cpu=True):
+    """The Hilbert-curve partition of the grid (keys of the cell centroids,
+    the equal-count cut, the partition quality), timed with events around
+    each library call after one untimed pass; the oracle's keys and partition
+    of the same grid timed on one host thread beside it.  Algorithmic bytes:
+    keys write 8 B per cell; each 8-bit pass of the radix sort reads the keys
+    for its histogram (8 B), then reads key and index (12 B, 8 B on the first
+    pass) and writes them (12 B); the cut reads the indices and writes the
+    parts (8 B)."""
+    import numpy as np
+    import torch
+    n = g.ncell
+    keys = torch.zeros(n, dtype=torch.int64, device="cuda")
+    part = torch.zeros(n, dtype=torch.int32, device="cuda")
+    passes = (3 * levels + 7) // 8
+    t = {"keys": [], "partition": [], "quality": []}
+    for r in range(reps + 1):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        g.hsfc_keys(levels, keys)
+        e[1].record()
+        rsv.hsfc_partition(ctx, keys, levels, nparts, part)
+        e[2].record()
+        q, _ = g.partition_quality(part, nparts)
+        e[3].record()
+        torch.cuda.synchronize()
+        if r > 0:
+            t["keys"].append(e[0].elapsed_time(e[1]) * 1e-3)
+            t["partition"].append(e[1].elapsed_time(e[2]) * 1e-3)
+            t["quality"].append(e[2].elapsed_time(e[3]) * 1e-3)
+    med = {k: float(np.median(v)) for k, v in t.items()}
+    part_bytes = n * (passes * 8 + (passes * 24 - 4) + 8)
+    out = {"workload": f"Hilbert-curve partition of the {dims[0]}x{dims[1]}x{dims[2]} grid into {nparts} parts, "
+                       f"{levels} levels ({passes} radix passes)",
+           "keys_s": round(med["keys"], 6), "partition_s": round(med["partition"], 6),
+           "quality_s": round(med["quality"], 6),
+           "cells_per_s": round(n / (med["keys"] + med["partition"]), 1),
+           "quality": {"load_imbalance": q[0], "max_local_surface_index": q[1], "global_surface_index": q[2],
+                       "average_surface_index": q[3], "max_connectivity": int(q[4])},
+           "roofline": {"bound": "hbm", "kernel": "partition (histograms, scan, scatters, cut)",
+                        "achieved": round(part_bytes / med["partition"] / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(part_bytes / med["partition"] / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": None, "algorithmic_bytes": part_bytes}}
+    del keys, part
+    if cpu:
+        from oracle import hsfc as H
+        t0 = time.perf_counter()
+        kh = H.grid_keys(dims, levels)
+        t1 = time.perf_counter()
+        H.partition(kh, nparts)
+        t2 = time.perf_counter()
+        out["cpu_baseline"] = {"value": round(n / (t2 - t0), 1), "unit": "cells/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle's keys ({t1 - t0:.2f}s) and qsort-based cut ({t2 - t1:.2f}s) "
+                                         f"of the whole grid, one host thread"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +248,8 @@ def main():
     ap.add_argument("--learned-seeds", default="1000-1015")
     ap.add_argument("--theta", type=float, default=0.9, help="the learned form's fallback threshold")
     ap.add_argument("--no-profile", action="store_true", help="skip the untimed kernel-timing step")
+    ap.add_argument("--hsfc-parts", type=int, default=64,
+                    help="parts of the Hilbert-curve partition of the workload's grid timed after the solves (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with one device-to-device copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -437,6 +496,14 @@ def main():
         cpu = oracle_baseline(cfg, Ao, bo, t_build, forms_all[head], summary[head]["its"])
     del Ao, bo
 
+    hsfc = None
+    if args.hsfc_parts > 0:
+        L = max(cfg.nx, cfg.ny, cfg.nz)
+        levels = max(1, (L - 1).bit_length())      # enough levels to give every cell its own key
+        hsfc = hsfc_measure(rsv, ctx, g, (cfg.nx, cfg.ny, cfg.nz), levels, args.hsfc_parts,
+                            cpu=not args.no_cpu_baseline)
+        log(f"hsfc: {hsfc}")
+
     # the runtime's device-to-device copy rate beside the vendor peak, for context
     # (1 GiB read + 1 GiB written, median of five, outside the timed steps)
     csrc = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -490,6 +557,7 @@ def main():
         "ras_local": ab_ras,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "hsfc_partition": hsfc,
         "assemble_from_host_s": round(host_assemble_s, 4),
         "assemble_from_host_GBps": round(B.nbytes / host_assemble_s / 1e9, 2),
         "device_bytes": A.device_bytes,
