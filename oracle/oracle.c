@@ -601,10 +601,20 @@ static int apply_pc(orc_apply_fn pc, void *ctx, int64_t N, const double *in, dou
     return pc(ctx, in, out);
 }
 
+/* The operator a Krylov method multiplies by: y = A x on vectors of length N
+ * (the 3x3-block matrices here, the scalar matrices of scalar.c). */
+typedef struct {
+    int64_t N;
+    orc_mv_fn mv;
+    const void *ctx;
+} orc_op;
+
+static void bcsr_mv(const void *ctx, const double *x, double *y) { orc_spmv((const orc_bcsr *)ctx, x, y); }
+
 /* r = b - A x; returns ||r|| */
-static double true_residual(const orc_bcsr *A, const double *b, const double *x, double *r, int64_t N)
+static double true_residual(const orc_op *A, const double *b, const double *x, double *r, int64_t N)
 {
-    orc_spmv(A, x, r);
+    A->mv(A->ctx, x, r);
     for (int64_t i = 0; i < N; ++i) r[i] = b[i] - r[i];
     return orc_nrm2(N, r);
 }
@@ -654,12 +664,12 @@ typedef struct {
     double theta;
 } gm_opts;
 
-static int gmres_core(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx, const gm_opts *o,
+static int gmres_core(const orc_op *A, orc_apply_fn pc, void *pc_ctx, const gm_opts *o,
                       const double *b, double *x, int32_t m, double tol, int64_t maxit,
                       orc_stats *st, double *hist)
 {
     if (!A || !b || !x || m < 1 || m > 62 || maxit < 0) return ORC_ERR_ARG;
-    const int64_t N = 3 * A->n;
+    const int64_t N = A->N;
     orc_stats dummy;
     if (!st) st = &dummy;
     st->its = 0; st->restarts = 0; st->fallbacks = 0; st->final_relres = 0.0; st->bad_cell = -1;
@@ -721,7 +731,7 @@ static int gmres_core(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx, const gm
                     }
                 }
                 if (prc != ORC_OK) { rc = prc; break; }
-                orc_spmv(A, z, w);
+                A->mv(A->ctx, z, w);
                 double wnorm0 = orc_nrm2(N, w);
                 cgs2(N, V, j, w, hcol);
                 double hn = orc_nrm2(N, w);
@@ -785,8 +795,19 @@ int orc_gmres(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
               const double *b, double *x, int32_t m, double tol, int64_t maxit,
               orc_stats *st, double *hist)
 {
+    if (!A) return ORC_ERR_ARG;
     gm_opts o = {0, NULL, NULL, 0.0};
-    return gmres_core(A, pc, pc_ctx, &o, b, x, m, tol, maxit, st, hist);
+    const orc_op op = {3 * A->n, bcsr_mv, A};
+    return gmres_core(&op, pc, pc_ctx, &o, b, x, m, tol, maxit, st, hist);
+}
+
+int orc_gmres_op(int64_t N, orc_mv_fn mv, const void *mv_ctx, orc_apply_fn pc, void *pc_ctx,
+                 const double *b, double *x, int32_t m, double tol, int64_t maxit, orc_stats *st, double *hist)
+{
+    if (N < 1 || !mv) return ORC_ERR_ARG;
+    gm_opts o = {0, NULL, NULL, 0.0};
+    const orc_op op = {N, mv, mv_ctx};
+    return gmres_core(&op, pc, pc_ctx, &o, b, x, m, tol, maxit, st, hist);
 }
 
 int orc_fgmres(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
@@ -795,16 +816,17 @@ int orc_fgmres(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
                orc_stats *st, double *hist)
 {
     gm_opts o = {1, fb, fb_ctx, theta};
-    if (!fb) return ORC_ERR_ARG;
-    return gmres_core(A, pc, pc_ctx, &o, b, x, m, tol, maxit, st, hist);
+    if (!fb || !A) return ORC_ERR_ARG;
+    const orc_op op = {3 * A->n, bcsr_mv, A};
+    return gmres_core(&op, pc, pc_ctx, &o, b, x, m, tol, maxit, st, hist);
 }
 
-int orc_bicgstab(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
-                 const double *b, double *x, double tol, int64_t maxit,
-                 orc_stats *st, double *hist)
+static int bicgstab_core(const orc_op *A, orc_apply_fn pc, void *pc_ctx,
+                         const double *b, double *x, double tol, int64_t maxit,
+                         orc_stats *st, double *hist)
 {
     if (!A || !b || !x || maxit < 0) return ORC_ERR_ARG;
-    const int64_t N = 3 * A->n;
+    const int64_t N = A->N;
     orc_stats dummy;
     if (!st) st = &dummy;
     st->its = 0; st->restarts = 0; st->fallbacks = 0; st->final_relres = 0.0; st->bad_cell = -1;
@@ -846,7 +868,7 @@ int orc_bicgstab(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
             for (int64_t q = 0; q < N; ++q) p[q] = r[q] + beta * (p[q] - omega * v[q]);
             rc = apply_pc(pc, pc_ctx, N, p, ph);
             if (rc != ORC_OK) break;
-            orc_spmv(A, ph, v);
+            A->mv(A->ctx, ph, v);
             double rv = orc_dot(N, rh, v);
             if (rv == 0.0 || !isfinite(rv)) { rc = isfinite(rv) ? ORC_BREAKDOWN : ORC_ERR_NAN; break; }
             alpha = rho_new / rv;
@@ -864,7 +886,7 @@ int orc_bicgstab(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
             }
             rc = apply_pc(pc, pc_ctx, N, s, sh);
             if (rc != ORC_OK) break;
-            orc_spmv(A, sh, t);
+            A->mv(A->ctx, sh, t);
             double tt = orc_dot(N, t, t);
             double ts = orc_dot(N, t, s);
             omega = (tt > 0.0) ? ts / tt : 0.0;
@@ -890,4 +912,21 @@ int orc_bicgstab(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
     }
     free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t);
     return rc;
+}
+
+int orc_bicgstab(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
+                 const double *b, double *x, double tol, int64_t maxit,
+                 orc_stats *st, double *hist)
+{
+    if (!A) return ORC_ERR_ARG;
+    const orc_op op = {3 * A->n, bcsr_mv, A};
+    return bicgstab_core(&op, pc, pc_ctx, b, x, tol, maxit, st, hist);
+}
+
+int orc_bicgstab_op(int64_t N, orc_mv_fn mv, const void *mv_ctx, orc_apply_fn pc, void *pc_ctx,
+                    const double *b, double *x, double tol, int64_t maxit, orc_stats *st, double *hist)
+{
+    if (N < 1 || !mv) return ORC_ERR_ARG;
+    const orc_op op = {N, mv, mv_ctx};
+    return bicgstab_core(&op, pc, pc_ctx, b, x, tol, maxit, st, hist);
 }

@@ -53,6 +53,7 @@ typedef struct orc_bcsr {
 } orc_bcsr;
 
 typedef int (*orc_apply_fn)(void *ctx, const double *in, double *out);
+typedef void (*orc_mv_fn)(const void *ctx, const double *x, double *y);   /* y = A x */
 
 typedef struct orc_stats {
     int64_t its;         /* Arnoldi steps (GMRES/FGMRES) or iterations (BiCGSTAB) */
@@ -106,6 +107,37 @@ int orc_fgmres(const orc_bcsr *A, orc_apply_fn pc, void *pc_ctx,
                orc_apply_fn fb, void *fb_ctx, double theta,
                const double *b, double *x, int32_t m, double tol, int64_t maxit,
                orc_stats *st, double *hist);
+
+/* the same Krylov methods for any operator y = A x on vectors of length N */
+int orc_gmres_op(int64_t N, orc_mv_fn mv, const void *mv_ctx, orc_apply_fn pc, void *pc_ctx,
+                 const double *b, double *x, int32_t m, double tol, int64_t maxit, orc_stats *st, double *hist);
+int orc_bicgstab_op(int64_t N, orc_mv_fn mv, const void *mv_ctx, orc_apply_fn pc, void *pc_ctx,
+                    const double *b, double *x, double tol, int64_t maxit, orc_stats *st, double *hist);
+
+/* ---- scalar (one unknown per cell) systems, scalar.c ---- */
+typedef struct orc_csr orc_csr;
+typedef struct orc_silu orc_silu;
+typedef struct orc_sras orc_sras;
+int  orc_csr_from_stencil(int32_t nx, int32_t ny, int32_t nz, const double *coef /* [n][7] */, orc_csr **out);
+void orc_csr_free(orc_csr *A);
+int64_t orc_csr_nnz(const orc_csr *A);
+void orc_csr_export(const orc_csr *A, int64_t *rowptr, int64_t *col, double *val);
+void orc_csr_spmv(const orc_csr *A, const double *x, double *y);
+int  orc_csr_ilu0(const orc_csr *A, orc_silu **out, int64_t *bad_row);
+void orc_silu_free(orc_silu *F);
+const orc_csr *orc_silu_factors(const orc_silu *F);
+int  orc_silu_apply(void *F, const double *r, double *z);
+int  orc_sras_setup(const orc_csr *A, int32_t nx, int32_t ny, int32_t nz, int32_t px, int32_t py, int32_t pz,
+                    int32_t overlap, orc_sras **out, int64_t *bad_row);
+void orc_sras_free(orc_sras *R);
+int64_t orc_sras_nsub(const orc_sras *R);
+int64_t orc_sras_sub_size(const orc_sras *R, int64_t s);
+void orc_sras_sub_cells(const orc_sras *R, int64_t s, int64_t *cells);
+int  orc_sras_apply(void *R, const double *r, double *z);
+int  orc_csr_gmres(const orc_csr *A, orc_apply_fn pc, void *pc_ctx, const double *b, double *x, int32_t m,
+                   double tol, int64_t maxit, orc_stats *st, double *hist);
+int  orc_csr_bicgstab(const orc_csr *A, orc_apply_fn pc, void *pc_ctx, const double *b, double *x, double tol,
+                      int64_t maxit, orc_stats *st, double *hist);
 
 /* ---- learned preconditioner network (unet.c) ---- */
 double  orc_bf16(double x);      /* round to the nearest BF16 value (ties to even) */

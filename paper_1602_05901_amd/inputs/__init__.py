@@ -51,6 +51,8 @@ def _load():
         lib.gen_uniform_vec.restype = None
         lib.gen_normal_vec.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p]
         lib.gen_normal_vec.restype = None
+        lib.gen_poisson.argtypes = [P(_Cfg), ctypes.c_void_p, ctypes.c_void_p]
+        lib.gen_poisson.restype = ctypes.c_int
         lib.gen_source_cells.argtypes = [P(_Cfg), ctypes.c_void_p]
         lib.gen_source_cells.restype = ctypes.c_int
         _lib = lib
@@ -102,6 +104,9 @@ def preset(name: str, seed: int = 0, m_shift: float | None = None) -> GenConfig:
         c = GenConfig(256, 256, 128, LNK_IID, 3.0, 0.0, 2.0, 0, 1e3, 1.0, seed)
     elif name == "C4":
         c = GenConfig(64, 64, 32, LNK_IID, 2.0, 0.0, 2.0, 0, 1e3, 1.0, seed)
+    elif name == "P1":
+        # scalar Poisson (Poisson Equation example): 7-point Laplacian, b = A x_true
+        c = GenConfig(512, 512, 512, LNK_IID, 0.0, 0.0, 0.0, 0, 1e3, 1.0, seed)
     elif name == "C5":
         c = GenConfig(512, 512, 128, LNK_CHANNELS, 0.5, 0.0, 2.0, 8, 1e3, 1.0, seed)
     else:
@@ -131,6 +136,24 @@ def blocks(cfg: GenConfig, lnk_field: np.ndarray | None = None) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"gen_blocks failed ({rc})")
     return out
+
+
+def poisson(cfg: GenConfig, lnk_field: np.ndarray | None = None) -> np.ndarray:
+    """Scalar 7-point coefficients, shape (ncell, 7), slots (-z,-y,-x,D,+x,+y,+z):
+    -div(k grad u) with harmonic face transmissibilities and u = 0 outside the
+    grid; lnk_field None gives the 7-point Laplacian (k = 1)."""
+    lib = _load()
+    out = np.empty((cfg.ncell, 7), dtype=np.float64)
+    ptr = None if lnk_field is None else np.ascontiguousarray(lnk_field, dtype=np.float64).ctypes.data
+    rc = lib.gen_poisson(ctypes.byref(cfg._c()), ptr, out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"gen_poisson failed ({rc})")
+    return out
+
+
+def x_true_scalar(cfg: GenConfig) -> np.ndarray:
+    """Manufactured solution of a scalar system, U(-1,1) per cell (stream 4)."""
+    return uniform(cfg.seed, 4, cfg.ncell, -1.0, 1.0)
 
 
 def uniform(seed: int, stream: int, n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:

@@ -205,3 +205,33 @@ int gen_blocks(const gen_cfg *c, const double *lnk, double *blocks)
             }
     return 0;
 }
+
+int gen_poisson(const gen_cfg *c, const double *lnk, double *coef)
+{
+    if (!cfg_ok(c) || !coef) return -1;
+    const int64_t nx = c->nx, ny = c->ny, nz = c->nz;
+    static const int OFF[7][3] = {{0, 0, -1}, {0, -1, 0}, {-1, 0, 0}, {0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t cc = (k * ny + j) * nx + i;
+                const double kc = lnk ? exp(lnk[cc]) : 1.0;
+                double *row = coef + 7 * cc;
+                double diag = 0.0;
+                for (int s = 0; s < 7; ++s) {
+                    if (s == 3) continue;
+                    const int64_t ii = i + OFF[s][0], jj = j + OFF[s][1], kk = k + OFF[s][2];
+                    if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) {
+                        row[s] = 0.0;
+                        diag += kc;                      /* boundary face, u = 0 outside */
+                        continue;
+                    }
+                    const double kn = lnk ? exp(lnk[(kk * ny + jj) * nx + ii]) : 1.0;
+                    const double T = lnk ? 2.0 * kc * kn / (kc + kn) : 1.0;
+                    row[s] = -T;
+                    diag += T;
+                }
+                row[3] = diag;
+            }
+    return 0;
+}

@@ -54,6 +54,15 @@ int gen_lnk(const gen_cfg *cfg, double *lnk);
  * blocks.  lnk is the field from gen_lnk (or any caller field). */
 int gen_blocks(const gen_cfg *cfg, const double *lnk, double *blocks);
 
+/* Scalar 7-point coefficients of a Poisson-type equation -div(k grad u) = f
+ * (the paper's Poisson Equation and pressure-system examples), layout
+ * double[ncell][7], slots as above.  Face transmissibility T = harmonic mean
+ * of the two cells' k = exp(ln k); off-diagonal = -T; diagonal = sum of the
+ * cell's face T plus k of the cell for every face on the grid boundary (a
+ * homogeneous Dirichlet condition); lnk = NULL means k = 1 (the 7-point
+ * Laplacian: diagonal 6, off-diagonals -1). */
+int gen_poisson(const gen_cfg *cfg, const double *lnk, double *coef);
+
 /* Fills out[i] = lo + (hi-lo)*u(seed, stream, i) for i < n. */
 void gen_uniform_vec(uint64_t seed, uint64_t stream, int64_t n, double lo, double hi, double *out);
 /* Fills out[i] = normal(seed, stream, i). */

@@ -15,6 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORC = os.path.join(ROOT, "oracle")
 PINS = "tests/test_oracle_pins_branches.py"
 HP = "tests/test_oracle_hsfc_pins.py"
+SP = "tests/test_oracle_scalar_pins.py"
 
 # (id, file, text in the oracle, replacement, pins that must fail)
 MUTATIONS = [
@@ -39,6 +40,11 @@ MUTATIONS = [
      [HP + "::test_partition_is_the_equal_count_cut_of_the_curve"]),
     ("quality_inner_faces_twice", "hsfc.c", "else if (m > c) f[p]++;", "else f[p]++;",
      [HP + "::test_quality_against_brute_force"]),
+    ("scalar_ilu_update_sign", "scalar.c", "M->val[where[j]] -= M->val[p] * M->val[q];",
+     "M->val[where[j]] += M->val[p] * M->val[q];",
+     [SP + "::test_ilu0_characterisation_and_apply"]),
+    ("scalar_ras_writes_every_cell", "scalar.c", "if (R->owner[cs[q]] == s) z[cs[q]] = zl[q];", "z[cs[q]] = zl[q];",
+     [SP + "::test_ras_on_a_line_is_the_restricted_sum_of_exact_local_solves"]),
     ("bicgstab_no_rv_exit", "oracle.c",
      "if (rv == 0.0 || !isfinite(rv)) { rc = isfinite(rv) ? ORC_BREAKDOWN : ORC_ERR_NAN; break; }",
      "if (!isfinite(rv)) { rc = ORC_ERR_NAN; break; }",
@@ -49,7 +55,7 @@ MUTATIONS = [
 def _build(tmp, mutation=None):
     src = os.path.join(tmp, "src")
     os.makedirs(src, exist_ok=True)
-    for f in ("oracle.c", "unet.c", "hsfc.c", "oracle.h"):
+    for f in ("oracle.c", "unet.c", "hsfc.c", "scalar.c", "oracle.h"):
         shutil.copy(os.path.join(ORC, f), src)
     if mutation is not None:
         _, fname, old, new, _ = mutation
@@ -59,7 +65,8 @@ def _build(tmp, mutation=None):
         open(path, "w").write(text.replace(old, new))
     lib = os.path.join(tmp, "liboracle_mut.so")
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", lib,
-                    os.path.join(src, "oracle.c"), os.path.join(src, "unet.c"), os.path.join(src, "hsfc.c"), "-lm"],
+                    os.path.join(src, "oracle.c"), os.path.join(src, "unet.c"), os.path.join(src, "hsfc.c"),
+                    os.path.join(src, "scalar.c"), "-lm"],
                    check=True)
     return lib
 
