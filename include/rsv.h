@@ -182,6 +182,17 @@ rsv_status rsv_row_to_cell(const rsv_grid *g, int64_t block_row, int32_t *i, int
  * Errors: RSV_ERR_ARG, RSV_ERR_OOM, RSV_ERR_PATTERN (nonzero block toward a
  * missing neighbour), RSV_ERR_NAN, RSV_ERR_HIP. */
 rsv_status rsv_matrix_assemble(rsv_grid *g, const double *blocks, int32_t where, rsv_matrix **out);
+/* A scalar system (one unknown per cell, 1x1 blocks: the paper's Poisson
+ * Equation example and pressure systems): coef HOST or DEVICE FP64
+ * [ncell][7] in block-row order, slots -z,-y,-x,D,+x,+y,+z by cell direction
+ * (a coefficient toward a missing neighbour must be 0, else
+ * RSV_ERR_PATTERN; non-finite: RSV_ERR_NAN).  Vectors of a scalar matrix
+ * have length ncell in block-row order.  rsv_matrix_update, rsv_spmv,
+ * rsv_spmv_noalloc (no scratch needed), rsv_precond_setup with RSV_PC_RAS
+ * (scalar RAS, FP64) or RSV_PC_BILU0 (ILU(0) of the whole grid: RAS with one
+ * subdomain and no overlap) or RSV_PC_NONE, rsv_precond_apply and rsv_solve
+ * (GMRES, BiCGSTAB) accept it; the learned preconditioner does not. */
+rsv_status rsv_matrix_assemble_scalar(rsv_grid *g, const double *coef, int32_t where, rsv_matrix **out);
 /* New values, same grid (next Newton step).  Preconditioners built on the
  * old values must be set up again.  Errors as for assemble. */
 rsv_status rsv_matrix_update(rsv_matrix *A, const double *blocks, int32_t where);

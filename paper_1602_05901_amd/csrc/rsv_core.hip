@@ -387,6 +387,8 @@ rsv_status rsv_matrix_assemble(rsv_grid *g, const double *blocks, int32_t where,
     rsv_matrix *M = new (std::nothrow) rsv_matrix();
     if (!M) return set_err(c, RSV_ERR_OOM, "matrix");
     M->g = g;
+    M->bs = 3;
+    M->nv = g->nv;
     const size_t abytes = (size_t)(g->geo.nslot / 64) * 63 * 64 * sizeof(double);
     rsv_status s = dev_alloc(c, (void **)&M->d_A, abytes);
     if (s == RSV_OK) {
@@ -404,6 +406,7 @@ rsv_status rsv_matrix_assemble(rsv_grid *g, const double *blocks, int32_t where,
 rsv_status rsv_matrix_update(rsv_matrix *M, const double *blocks, int32_t where)
 {
     if (!M || !blocks) return set_err(M ? M->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");
+    if (M->bs == 1) return scalar_assemble_values(M, blocks, where);
     return assemble_values(M, blocks, where);
 }
 

@@ -172,7 +172,10 @@ struct SolverWork;
 
 struct rsv_matrix {
     rsv_grid *g = nullptr;
-    double *d_A = nullptr;            // tile-lane blocks, nslot/64 * 63 * 64 doubles
+    int bs = 3;                       // unknowns per cell: 3 (block matrices) or 1 (scalar)
+    int64_t nv = 0;                   // solver vector length: tile-lane 3*nslot, or ncell in row order
+    double *d_A = nullptr;            // bs 3: tile-lane blocks, nslot/64 * 63 * 64 doubles
+    double *d_coef = nullptr;         // bs 1: coef[slot][row], 7 * ncell doubles
     SolverWork *ws = nullptr;
     std::vector<double> hist;
     int64_t bytes = 0;
@@ -227,6 +230,17 @@ rsv_status launch_spmv(rsv_ctx *c, const Geo &g, const double *A, int mode, cons
                        const double *aux1, double alpha, double beta, int k0);
 
 rsv_status launch_reduce(rsv_ctx *c, int nblocks, int K, int k0);    // partials[nblocks][K] -> d_scal[k0..]
+
+// scalar systems (rsv_scalar.hip): the product with the same modes, and the
+// matrix-independent front ends the Krylov drivers use
+rsv_status launch_sspmv(rsv_ctx *c, const Geo &g, const double *coef, int mode, const double *x, double *y,
+                        const double *aux, double alpha, double beta, int k0);
+rsv_status mat_spmv(rsv_matrix *M, int mode, const double *x, double *y, const double *aux, double alpha,
+                    double beta, int k0);
+rsv_status mat_in(rsv_matrix *M, const double *nat, double *v);                       // ABI order -> solver layout
+rsv_status mat_out(rsv_matrix *M, const double *v, double *nat, double alpha, double beta);   // nat = a v + b nat
+rsv_status scalar_assemble_values(rsv_matrix *M, const double *coef, int32_t where);
+rsv_status sras_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
 
 rsv_status launch_nat_to_tl(rsv_ctx *c, const Geo &g, const double *nat, double *tl);
 rsv_status launch_tl_to_nat(rsv_ctx *c, const Geo &g, const double *tl, double *nat, double alpha, double beta);

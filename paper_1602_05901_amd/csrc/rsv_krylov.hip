@@ -36,7 +36,7 @@ static rsv_status ws_reserve(rsv_matrix *M, int nvec)
     dev_free(w->pool);
     w->pool = nullptr;
     w->nvec = 0;
-    const size_t bytes = (size_t)nvec * (size_t)M->g->nv * sizeof(double);
+    const size_t bytes = (size_t)nvec * (size_t)M->nv * sizeof(double);
     rsv_status s = dev_alloc(c, (void **)&w->pool, bytes);
     if (s != RSV_OK) return s;
     RSV_HIP(c, hipMemsetAsync(w->pool, 0, bytes, c->stream));
@@ -109,7 +109,7 @@ struct Solve {
 // r = b - A x into r, returns ||r||
 static rsv_status true_resid(Solve &S, const double *b, const double *x, double *r, double *rn)
 {
-    rsv_status s = launch_spmv(S.c, *S.geo, S.M->d_A, SPMV_RESID, x, r, b, 0, 0, SC_RR);
+    rsv_status s = mat_spmv(S.M, SPMV_RESID, x, r, b, 0, 0, SC_RR);
     if (s == RSV_OK) s = scal_to_host(S.c, SC_RR, 1);
     if (s != RSV_OK) return s;
     *rn = std::sqrt(S.c->h_scal[SC_RR]);
@@ -167,7 +167,7 @@ static rsv_status gmres(Solve &S, PcImpl *P, PcImpl *FB, double theta, int m, in
             auto enqueue = [&](int j) -> rsv_status {
                 double *w = V + (int64_t)(j + 1) * n;
                 rsv_status e = pc_apply(c, P, n, V + (int64_t)j * n, zt);
-                if (e == RSV_OK) e = launch_spmv(c, *S.geo, S.M->d_A, SPMV_NORM, zt, w, nullptr, 0, 0, SC_W0);
+                if (e == RSV_OK) e = mat_spmv(S.M, SPMV_NORM, zt, w, nullptr, 0, 0, SC_W0);
                 if (e == RSV_OK) e = launch_dcgs_dots(c, n, V, n, j + 1, w, SC_DP);
                 if (e == RSV_OK) e = launch_dcgs_update(c, n, V, n, j + 1, w, SC_DP);
                 if (e == RSV_OK) e = scal_to_host_async(c, j & 1, SC_DP, 2 * (j + 1) + 4);
@@ -236,7 +236,7 @@ static rsv_status gmres(Solve &S, PcImpl *P, PcImpl *FB, double theta, int m, in
             auto enqueue = [&](int j) -> rsv_status {
                 double *w = V + (int64_t)(j + 1) * n;
                 rsv_status e = pc_apply(c, P, n, V + (int64_t)j * n, zt);
-                if (e == RSV_OK) e = launch_spmv(c, *S.geo, S.M->d_A, SPMV_NORM, zt, w, nullptr, 0, 0, SC_W0);
+                if (e == RSV_OK) e = mat_spmv(S.M, SPMV_NORM, zt, w, nullptr, 0, 0, SC_W0);
                 if (e == RSV_OK) e = launch_mdot(c, n, V, n, j + 1, w, SC_H1);
                 if (e == RSV_OK) e = launch_upd_dot(c, n, V, n, j + 1, w, SC_H1, SC_H2);
                 if (e == RSV_OK) e = launch_upd_norm(c, n, V, n, j + 1, w, SC_H2, SC_HN);
@@ -284,7 +284,7 @@ static rsv_status gmres(Solve &S, PcImpl *P, PcImpl *FB, double theta, int m, in
                 used_fb = want_fb;
                 s = pc_apply(c, use, n, V + (int64_t)j * n, z);
                 if (s != RSV_OK) return s;
-                s = launch_spmv(c, *S.geo, S.M->d_A, SPMV_NORM, z, w, nullptr, 0, 0, SC_W0);
+                s = mat_spmv(S.M, SPMV_NORM, z, w, nullptr, 0, 0, SC_W0);
                 if (s == RSV_OK) s = launch_mdot(c, n, V, n, j + 1, w, SC_H1);
                 if (s == RSV_OK) s = launch_upd_dot(c, n, V, n, j + 1, w, SC_H1, SC_H2);
                 if (s == RSV_OK) s = launch_upd_norm(c, n, V, n, j + 1, w, SC_H2, SC_HN);
@@ -379,7 +379,7 @@ static rsv_status bicgstab(Solve &S, PcImpl *P, int64_t maxit, double *b, double
             const double beta = (rho_new / rho) * (alpha / omega);
             if ((s = launch_bicg_p(c, n, r, v, beta, omega, p)) != RSV_OK) return s;
             if ((s = pc_apply(c, P, n, p, ph)) != RSV_OK) return s;
-            if ((s = launch_spmv(c, *S.geo, S.M->d_A, SPMV_DOT1, ph, v, rh, 0, 0, SC_RV)) != RSV_OK) return s;
+            if ((s = mat_spmv(S.M, SPMV_DOT1, ph, v, rh, 0, 0, SC_RV)) != RSV_OK) return s;
             if ((s = launch_bicg_s(c, n, r, v, s_, SC_RH, SC_RV, SC_SS)) != RSV_OK) return s;
             if ((s = scal_to_host_async(c, 0, SC_RR, SC_SS - SC_RR + 1)) != RSV_OK) return s;
             // The second half's preconditioner apply and product depend only
@@ -389,7 +389,7 @@ static rsv_status bicgstab(Solve &S, PcImpl *P, int64_t maxit, double *b, double
             const bool ahead = !S.ctl.met(0.25 * nr);
             if (ahead) {
                 if ((s = pc_apply(c, P, n, s_, sh)) != RSV_OK) return s;
-                if ((s = launch_spmv(c, *S.geo, S.M->d_A, SPMV_DOT2, sh, t, s_, 0, 0, SC_TS)) != RSV_OK) return s;
+                if ((s = mat_spmv(S.M, SPMV_DOT2, sh, t, s_, 0, 0, SC_TS)) != RSV_OK) return s;
             }
             if ((s = scal_wait(c, 0)) != RSV_OK) return s;
             const double rv = c->h_spec[SC_RV];
@@ -414,7 +414,7 @@ static rsv_status bicgstab(Solve &S, PcImpl *P, int64_t maxit, double *b, double
             }
             if (!ahead) {
                 if ((s = pc_apply(c, P, n, s_, sh)) != RSV_OK) return s;
-                if ((s = launch_spmv(c, *S.geo, S.M->d_A, SPMV_DOT2, sh, t, s_, 0, 0, SC_TS)) != RSV_OK) return s;
+                if ((s = mat_spmv(S.M, SPMV_DOT2, sh, t, s_, 0, 0, SC_TS)) != RSV_OK) return s;
             }
             if ((s = launch_bicg_xr(c, n, alpha, 0.0, ph, sh, s_, t, rh, x, r, SC_RR)) != RSV_OK) return s;
             if ((s = scal_to_host(c, SC_RR, SC_TT - SC_RR + 1)) != RSV_OK) return s;
@@ -459,6 +459,8 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
     rsv_ctx *c = A->g->ctx;
     if (p->precision != RSV_FP64 && p->precision != RSV_FP32) return set_err(c, RSV_ERR_ARG, "bad precision");
     if (p->iluk_level != 0) return set_err(c, RSV_ERR_ARG, "only ILU(0) is supported (iluk_level must be 0)");
+    if (A->bs == 1 && p->type == RSV_PC_LEARNED)
+        return set_err(c, RSV_ERR_ARG, "the learned preconditioner needs a 3x3-block matrix");
     rsv_precond *P = new (std::nothrow) rsv_precond();
     if (!P) return set_err(c, RSV_ERR_OOM, "precond");
     P->A = A;
@@ -466,8 +468,8 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
     rsv_status s = RSV_OK;
     switch (p->type) {
     case RSV_PC_NONE: break;
-    case RSV_PC_BILU0: s = bilu0_create(A, p, &P->impl, bad_cell); break;
-    case RSV_PC_RAS: s = ras_create(A, p, &P->impl, bad_cell); break;
+    case RSV_PC_BILU0: s = (A->bs == 1) ? sras_create(A, p, &P->impl, bad_cell) : bilu0_create(A, p, &P->impl, bad_cell); break;
+    case RSV_PC_RAS: s = (A->bs == 1) ? sras_create(A, p, &P->impl, bad_cell) : ras_create(A, p, &P->impl, bad_cell); break;
     case RSV_PC_LEARNED: {
         rsv_pc_params fb = *p;
         fb.type = RSV_PC_BILU0;
@@ -505,6 +507,15 @@ rsv_status rsv_spmv(rsv_matrix *M, double alpha, const double *x, double beta, d
 {
     if (!M || !x || !y) return set_err(M ? M->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");
     rsv_ctx *c = M->g->ctx;
+    if (M->bs == 1) {
+        // a scalar matrix works on row-ordered vectors: one launch, no staging
+        rsv_status s = mat_spmv(M, SPMV_AXPBY, x, y, nullptr, alpha, beta, 0);
+        if (s == RSV_OK) {
+            hipError_t e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) s = set_err(c, RSV_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
+        }
+        return s;
+    }
     // the tile-lane copies of x and A x live in the solver workspace (no allocation per call)
     rsv_status s = ws_reserve(M, 2);
     if (s != RSV_OK) return s;
@@ -531,6 +542,7 @@ rsv_status rsv_spmv_noalloc(rsv_matrix *M, double alpha, const double *x, double
 {
     if (!M || !x || !y) return set_err(M ? M->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");
     rsv_ctx *c = M->g->ctx;
+    if (M->bs == 1) return rsv_spmv(M, alpha, x, beta, y);   // scalar: no scratch at all
     const int64_t n = M->g->nv;
     if (!c->d_scratch) return set_err(c, RSV_ERR_ARG, "no fixed scratch on this device");
     if (2 * n > NOALLOC_SCRATCH_DOUBLES)
@@ -558,11 +570,11 @@ rsv_status rsv_precond_apply(rsv_precond *P, const double *r, double *z)
     rsv_status s = ws_reserve(M, 2);
     if (s == RSV_OK) s = flags_reset(c);
     if (s != RSV_OK) return s;
-    const int64_t n = M->g->nv;
+    const int64_t n = M->nv;
     double *rt = M->ws->pool, *zt = M->ws->pool + n;
-    s = launch_nat_to_tl(c, M->g->geo, r, rt);
+    s = mat_in(M, r, rt);
     if (s == RSV_OK) s = pc_apply(c, P->impl, n, rt, zt);
-    if (s == RSV_OK) s = launch_tl_to_nat(c, M->g->geo, zt, z, 1.0, 0.0);
+    if (s == RSV_OK) s = mat_out(M, zt, z, 1.0, 0.0);
     if (s == RSV_OK) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return set_err(c, RSV_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
@@ -596,12 +608,12 @@ rsv_status rsv_solve(rsv_matrix *A, rsv_precond *P, const rsv_solver_params *p, 
     const int nvec = (p->method == RSV_BICGSTAB) ? 10 : (p->method == RSV_FGMRES ? 2 * m + 5 : m + 5);
     rsv_status s = ws_reserve(A, nvec);
     if (s != RSV_OK) return st->status = s;
-    const int64_t n = A->g->nv;
+    const int64_t n = A->nv;
     double *pool = A->ws->pool;
     double *bt = pool + (int64_t)(nvec - 2) * n;
     double *xt = pool + (int64_t)(nvec - 1) * n;
-    s = launch_nat_to_tl(c, A->g->geo, b, bt);
-    if (s == RSV_OK) s = launch_nat_to_tl(c, A->g->geo, x, xt);
+    s = mat_in(A, b, bt);
+    if (s == RSV_OK) s = mat_in(A, x, xt);
     if (s == RSV_OK) s = launch_nonfinite(c, n, bt, SC_MISC);
     if (s == RSV_OK) s = launch_dot(c, n, bt, bt, SC_BB);
     if (s == RSV_OK) s = scal_to_host(c, 0, SC_MISC + 1);   // slots SC_BB and SC_MISC
@@ -633,7 +645,7 @@ rsv_status rsv_solve(rsv_matrix *A, rsv_precond *P, const rsv_solver_params *p, 
                    pool);
     }
     if (rc < 0) return st->status = rc;
-    s = launch_tl_to_nat(c, A->g->geo, xt, x, 1.0, 0.0);
+    s = mat_out(A, xt, x, 1.0, 0.0);
     if (s == RSV_OK) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) s = set_err(c, RSV_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
@@ -660,6 +672,7 @@ void rsv_matrix_destroy(rsv_matrix *M)
     (void)hipStreamSynchronize(M->g->ctx->stream);
     ws_free(M);
     dev_free(M->d_A);
+    dev_free(M->d_coef);
     delete M;
 }
 
@@ -667,7 +680,7 @@ int64_t rsv_matrix_device_bytes(const rsv_matrix *M)
 {
     if (!M) return 0;
     int64_t b = M->bytes;
-    if (M->ws) b += (int64_t)M->ws->nvec * M->g->nv * (int64_t)sizeof(double);
+    if (M->ws) b += (int64_t)M->ws->nvec * M->nv * (int64_t)sizeof(double);
     return b;
 }
 

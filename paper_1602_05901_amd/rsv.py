@@ -64,6 +64,7 @@ _SIGS = {
     "rsv_row_to_cell": ([vp, i64, _P(i32), _P(i32), _P(i32)], i32),
     "rsv_matrix_assemble": ([vp, vp, i32, _P(vp)], i32),
     "rsv_matrix_update": ([vp, vp, i32], i32),
+    "rsv_matrix_assemble_scalar": ([vp, vp, i32, _P(vp)], i32),
     "rsv_matrix_destroy": ([vp], None),
     "rsv_spmv": ([vp, dbl, vp, dbl, vp], i32),
     "rsv_spmv_noalloc": ([vp, dbl, vp, dbl, vp], i32),
@@ -246,13 +247,16 @@ class Grid:
 
 
 class Matrix:
-    def __init__(self, grid: Grid, blocks, where=None):
-        """blocks: [ncell,7,3,3] float64, numpy (host) or torch (host or device)."""
+    def __init__(self, grid: Grid, blocks, where=None, scalar=False):
+        """blocks: [ncell,7,3,3] float64 (3x3-block system) or, with scalar=True,
+        [ncell,7] float64 coefficients of a scalar system; numpy (host) or torch
+        (host or device)."""
         if where is None:
             where = MEM_DEVICE if (hasattr(blocks, "is_cuda") and blocks.is_cuda) else MEM_HOST
         h = vp()
-        _check(grid.ctx, lib().rsv_matrix_assemble(grid.h, _ptr(blocks), where, ctypes.byref(h)))
-        self.grid, self.ctx, self.h = grid, grid.ctx, h
+        fn = lib().rsv_matrix_assemble_scalar if scalar else lib().rsv_matrix_assemble
+        _check(grid.ctx, fn(grid.h, _ptr(blocks), where, ctypes.byref(h)))
+        self.grid, self.ctx, self.h, self.scalar = grid, grid.ctx, h, scalar
 
     def update(self, blocks, where=None):
         if where is None:
