@@ -232,6 +232,93 @@ def hsfc_measure(rsv, ctx, g, dims, levels, nparts, reps=5, cpu=True):
     return out
 
 
+def poisson_measure(rsv, ctx, dims, parts, its=90, reps=3, cpu=True):
+    """The paper's Poisson Equation example at one GPU's size: the scalar
+    7-point Laplacian on dims cells, b = A x_true, GMRES(30) with RAS
+    (parts subdomains -- about the paper's cells per core at 4096 cores --
+    overlap one, ILU(0) on every subdomain) run for a fixed `its` iterations
+    as the paper runs 90; the median of `reps` timed runs after one untimed,
+    then one untimed run with kernel events.  The oracle's cost per iteration
+    is taken on a sample of four subdomains of the same shape (a 2x2x1 box of
+    them), projected to the whole grid by the cell count."""
+    import numpy as np
+    import torch
+    from paper_1602_05901_amd import inputs as I
+    cfg = I.GenConfig(*dims, I.LNK_IID, 0.0, 0.0, 0.0, 0, 1e3, 1.0, 0)
+    t0 = time.time()
+    C = I.poisson(cfg)
+    xt = I.x_true_scalar(cfg)
+    log(f"poisson: generated {dims} in {time.time() - t0:.1f}s")
+    g = rsv.Grid(ctx, *dims)
+    A = rsv.Matrix(g, torch.from_numpy(C).cuda(), scalar=True)
+    del C
+    xtd = torch.from_numpy(xt).cuda()
+    b = torch.zeros_like(xtd)
+    A.spmv(xtd, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M = rsv.Precond(A, type=rsv.PC_RAS, ras_px=parts[0], ras_py=parts[1], ras_pz=parts[2], ras_overlap=1)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    times, st = [], None
+    for r in range(reps + 2):
+        x = torch.zeros_like(b)
+        prof = r == reps + 1
+        if prof:
+            ctx.profile(True, classes=("spmv", "ras", "ortho"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = rsv.solve(A, M, b, x, method=rsv.GMRES, restart=30, tol=0.0, maxit=its)
+        torch.cuda.synchronize()
+        if prof:
+            kr = ctx.profile_read()
+            ctx.profile(False)
+        elif r > 0:
+            times.append(time.perf_counter() - t0)
+    err = float(torch.linalg.norm(x - xtd) / torch.linalg.norm(xtd))
+    n = cfg.ncell
+    solve_s = float(np.median(times))
+    nnz = 7 * n - 2 * (dims[1] * dims[2] + dims[0] * dims[2] + dims[0] * dims[1])
+    spmv_bytes = 8 * nnz + 16 * n
+    kern = {k: {"avg_us": 1e3 * kr[k][0] / kr[k][1], "launches": kr[k][1]} for k in ("spmv", "ras", "ortho")
+            if kr[k][1]}
+    if "spmv" in kern:
+        kern["spmv"]["GBps"] = spmv_bytes / (kern["spmv"]["avg_us"] * 1e-6) / 1e9
+    out = {"workload": f"scalar 7-point Laplacian {dims[0]}x{dims[1]}x{dims[2]} ({n} unknowns), GMRES(30) + RAS "
+                       f"({parts[0]}x{parts[1]}x{parts[2]} subdomains of about {n // (parts[0] * parts[1] * parts[2])} "
+                       f"cells, overlap 1, ILU(0)), {its} iterations",
+           "setup_s": round(setup_s, 4), "solve_s": round(solve_s, 4), "its": st["its"],
+           "s_per_iteration": round(solve_s / its, 6), "relres_after": st["final_relres"], "err_vs_xtrue": err,
+           "unknown_iterations_per_s": round(n * its / solve_s, 1), "kernels": kern,
+           "paper_context": {"workload": "Poisson equation, 3e9 cells, GMRES(30) + RAS(overlap 1, ILU(0)), 90 iterations",
+                             "hardware": "IBM Blue Gene/Q", "solve_s_512_cores": 606.33,
+                             "solve_s_4096_cores": 80.30, "s_per_iteration_4096_cores": round(80.30 / 90, 3),
+                             "unknown_iterations_per_s_4096_cores": round(3e9 * 90 / 80.30, 1),
+                             "note": "solve = overall - gridding - building - assemble of the table's row"}}
+    M.close(); A.close(); g.close()
+    del b, xtd
+    if cpu:
+        from oracle import scalar as S
+        sx = -(-dims[0] // parts[0]) * 2
+        sy = -(-dims[1] // parts[1]) * 2
+        sz = -(-dims[2] // parts[2])
+        sc = I.GenConfig(sx, sy, sz, I.LNK_IID, 0.0, 0.0, 0.0, 0, 1e3, 1.0, 0)
+        Ao = S.CSR(sx, sy, sz, I.poisson(sc))
+        bo = Ao.spmv(I.x_true_scalar(sc))
+        t0 = time.perf_counter()
+        R = S.RAS(Ao, (sx, sy, sz), (2, 2, 1), 1)
+        t1 = time.perf_counter()
+        k = 5
+        S.gmres(Ao, bo, pc=R, m=30, tol=0.0, maxit=k)
+        t2 = time.perf_counter()
+        per_cell_it = (t2 - t1) / k / sc.ncell
+        out["cpu_baseline"] = {"value": round(per_cell_it * n * its, 2), "unit": "s", "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle's GMRES(30) + RAS on a {sx}x{sy}x{sz} grid of four subdomains "
+                                         f"of the same shape ({k} iterations in {t2 - t1:.2f}s after a {t1 - t0:.2f}s "
+                                         f"setup), scaled by cells and to {its} iterations; one host thread"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +337,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the untimed kernel-timing step")
     ap.add_argument("--hsfc-parts", type=int, default=64,
                     help="parts of the Hilbert-curve partition of the workload's grid timed after the solves (0: skip)")
+    ap.add_argument("--poisson", default="512,512,512:6,6,5",
+                    help="grid:subdomains of the scalar Poisson run after the solves (empty: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with one device-to-device copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -522,6 +611,17 @@ def main():
     if roofline is not None:
         roofline["d2d_copy_GBps"] = copy_GBps
 
+    poisson = None
+    if args.poisson:
+        A_keep_bytes = A.device_bytes
+        A.close()                                 # the block matrix and its workspace make room
+        pd, pp = args.poisson.split(":")
+        poisson = poisson_measure(rsv, ctx, tuple(int(v) for v in pd.split(",")), tuple(int(v) for v in pp.split(",")),
+                                  cpu=not args.no_cpu_baseline)
+        log(f"poisson: {poisson}")
+    else:
+        A_keep_bytes = A.device_bytes
+
     value = summary[head]["solve_s"]
     line = {
         "metric": "time-to-solve to 1e-8 FP64 rel. residual (s), SpMV/ILU HBM GB/s; learned/FP32 vs plain",
@@ -558,9 +658,10 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "hsfc_partition": hsfc,
+        "poisson_ras": poisson,
         "assemble_from_host_s": round(host_assemble_s, 4),
         "assemble_from_host_GBps": round(B.nbytes / host_assemble_s / 1e9, 2),
-        "device_bytes": A.device_bytes,
+        "device_bytes": A_keep_bytes,
         "hbm_used_bytes": int(hbm_peak[0]),
         "hbm_total_bytes": int(torch.cuda.mem_get_info()[1]),
         "device": ctx.device_info(),
@@ -573,7 +674,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("copy probe: 1073741824 bytes read, 1073741824 bytes written")
-    A.close(); g.close(); ctx.close()
+    if not args.poisson:
+        A.close()
+    g.close(); ctx.close()
 
 
 if __name__ == "__main__":
