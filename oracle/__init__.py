@@ -52,6 +52,9 @@ def lib():
         "orc_ilu_apply": ([vp, vp, vp], ctypes.c_int),
         "orc_ilu_apply_f32": ([vp, vp, vp], ctypes.c_int),
         "orc_ras_setup": ([vp, i32, i32, i32, i32, i32, i32, i32, P(vp), P(i64)], ctypes.c_int),
+        "orc_ras_setup_k": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, P(vp), P(i64)], ctypes.c_int),
+        "orc_iluk": ([vp, i32, P(vp), P(i64)], ctypes.c_int),
+        "orc_iluk_pattern": ([vp, i32, vp, vp, vp, i64], ctypes.c_int),
         "orc_ras_free": ([vp], None),
         "orc_ras_apply": ([vp, vp, vp], ctypes.c_int),
         "orc_ras_nsub": ([vp], i64),
@@ -157,11 +160,23 @@ def bcsr_to_dense(rp, col, val):
     return D
 
 
+def iluk_pattern(A: BCSR, k):
+    """(rowptr, col, level) of the level-k fill pattern."""
+    nnzb = lib().orc_iluk_pattern(A.h, k, None, None, None, 0)
+    if nnzb < 0:
+        raise OracleError(nnzb, "iluk_pattern")
+    rp = np.empty(A.n + 1, np.int64)
+    col = np.empty(nnzb, np.int64)
+    lev = np.empty(nnzb, np.int64)
+    lib().orc_iluk_pattern(A.h, k, _p(rp), _p(col), _p(lev), nnzb)
+    return rp, col, lev
+
+
 class ILU:
-    def __init__(self, A: BCSR):
+    def __init__(self, A: BCSR, level=0):
         h = ctypes.c_void_p()
         bad = ctypes.c_int64(-1)
-        rc = lib().orc_ilu0(A.h, ctypes.byref(h), ctypes.byref(bad))
+        rc = lib().orc_iluk(A.h, level, ctypes.byref(h), ctypes.byref(bad))
         if rc != OK:
             e = OracleError(rc, f"ilu0 bad_cell={bad.value}")
             e.bad_cell = bad.value
@@ -202,12 +217,12 @@ class ILU:
 
 
 class RAS:
-    def __init__(self, A: BCSR, dims, parts, overlap=1):
+    def __init__(self, A: BCSR, dims, parts, overlap=1, level=0):
         h = ctypes.c_void_p()
         bad = ctypes.c_int64(-1)
         nx, ny, nz = dims
         px, py, pz = parts
-        rc = lib().orc_ras_setup(A.h, nx, ny, nz, px, py, pz, overlap, ctypes.byref(h), ctypes.byref(bad))
+        rc = lib().orc_ras_setup_k(A.h, nx, ny, nz, px, py, pz, overlap, level, ctypes.byref(h), ctypes.byref(bad))
         if rc != OK:
             e = OracleError(rc, f"ras_setup bad_cell={bad.value}")
             e.bad_cell = bad.value

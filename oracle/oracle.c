@@ -242,7 +242,10 @@ void orc_ilu_free(orc_ilu *F)
 
 const orc_bcsr *orc_ilu_factors(const orc_ilu *F) { return F->LU; }
 
-int orc_ilu0(const orc_bcsr *A, orc_ilu **out, int64_t *bad_cell)
+/* The numeric IKJ factorisation on the pattern of A (which may hold explicit
+ * zero blocks at fill positions): ILU(0) of A when A carries its own pattern,
+ * ILU(k) when it carries the level-k pattern. */
+static int ilu_numeric(const orc_bcsr *A, orc_ilu **out, int64_t *bad_cell)
 {
     if (!A || !out) return ORC_ERR_ARG;
     if (bad_cell) *bad_cell = -1;
@@ -308,6 +311,122 @@ int orc_ilu0(const orc_bcsr *A, orc_ilu **out, int64_t *bad_cell)
     free(where);
     *out = F;
     return ORC_OK;
+}
+
+int orc_ilu0(const orc_bcsr *A, orc_ilu **out, int64_t *bad_cell)
+{
+    return ilu_numeric(A, out, bad_cell);
+}
+
+/* Level-of-fill pattern of ILU(k) (Saad, Iterative Methods for Sparse Linear
+ * Systems, 2nd ed., sec. 10.3.3): the entries of A have level 0; eliminating
+ * with row m < i gives position (i, j), j > m, the level lev(i,m) + lev(m,j)
+ * + 1, kept when it is at most k.  Returns the pattern as a block CSR whose
+ * new positions hold zero blocks, and the levels (nullable). */
+static orc_bcsr *iluk_pattern(const orc_bcsr *A, int32_t k, int64_t **levels_out)
+{
+    const int64_t n = A->n;
+    int64_t *rp = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t cap = A->nnzb + 16, used = 0;
+    int64_t *cols = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    int64_t *levs = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    int64_t *lev = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));   /* dense, per row */
+    int64_t *row = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));   /* sorted columns of row i */
+    if (!rp || !cols || !levs || !lev || !row) {
+        free(rp); free(cols); free(levs); free(lev); free(row);
+        return NULL;
+    }
+    for (int64_t j = 0; j < n; ++j) lev[j] = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t len = 0;
+        for (int64_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+            row[len++] = A->col[p];
+            lev[A->col[p]] = 0;
+        }
+        /* eliminate with every m < i of the row, ascending; the row grows */
+        for (int64_t t = 0; t < len && row[t] < i; ++t) {
+            const int64_t m = row[t];
+            for (int64_t q = rp[m]; q < rp[m + 1]; ++q) {
+                const int64_t j = cols[q];
+                if (j <= m) continue;
+                const int64_t l = lev[m] + levs[q] + 1;
+                if (l > k) continue;
+                if (lev[j] < 0) {              /* a new position: insert keeping the row sorted */
+                    int64_t u = len;
+                    while (u > 0 && row[u - 1] > j) { row[u] = row[u - 1]; --u; }
+                    row[u] = j;
+                    ++len;
+                    lev[j] = l;
+                } else if (l < lev[j]) {
+                    lev[j] = l;
+                }
+            }
+        }
+        if (used + len > cap) {
+            while (used + len > cap) cap *= 2;
+            int64_t *c2 = (int64_t *)realloc(cols, (size_t)cap * sizeof(int64_t));
+            int64_t *l2 = c2 ? (int64_t *)realloc(levs, (size_t)cap * sizeof(int64_t)) : NULL;
+            if (!c2 || !l2) {
+                free(c2 ? c2 : cols); free(rp); free(levs); free(lev); free(row);
+                return NULL;
+            }
+            cols = c2;
+            levs = l2;
+        }
+        rp[i] = used;
+        for (int64_t t = 0; t < len; ++t) {
+            cols[used] = row[t];
+            levs[used] = lev[row[t]];
+            lev[row[t]] = -1;
+            ++used;
+        }
+        rp[i + 1] = used;   /* row i is read by the rows after it */
+    }
+    orc_bcsr *P = bcsr_alloc(n, used);
+    if (P) {
+        memcpy(P->rowptr, rp, (size_t)(n + 1) * sizeof(int64_t));
+        memcpy(P->col, cols, (size_t)used * sizeof(int64_t));
+        memset(P->val, 0, (size_t)used * 9 * sizeof(double));
+        for (int64_t i = 0; i < n; ++i) {   /* the entries of A, the rest zero */
+            int64_t q = P->rowptr[i];
+            for (int64_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+                while (P->col[q] != A->col[p]) ++q;
+                memcpy(P->val + 9 * q, A->val + 9 * p, 9 * sizeof(double));
+            }
+        }
+    }
+    if (levels_out && P) *levels_out = levs;
+    else free(levs);
+    free(rp); free(cols); free(lev); free(row);
+    return P;
+}
+
+int orc_iluk(const orc_bcsr *A, int32_t k, orc_ilu **out, int64_t *bad_cell)
+{
+    if (!A || !out || k < 0) return ORC_ERR_ARG;
+    if (k == 0) return ilu_numeric(A, out, bad_cell);
+    orc_bcsr *P = iluk_pattern(A, k, NULL);
+    if (!P) return ORC_ERR_OOM;
+    int rc = ilu_numeric(P, out, bad_cell);
+    orc_bcsr_free(P);
+    return rc;
+}
+
+int orc_iluk_pattern(const orc_bcsr *A, int32_t k, int64_t *rowptr, int64_t *col, int64_t *level, int64_t cap)
+{
+    if (!A || k < 0) return ORC_ERR_ARG;
+    int64_t *levs = NULL;
+    orc_bcsr *P = iluk_pattern(A, k, &levs);
+    if (!P) return ORC_ERR_OOM;
+    const int64_t nnzb = P->nnzb;
+    if (rowptr && col && level && nnzb <= cap) {
+        memcpy(rowptr, P->rowptr, (size_t)(A->n + 1) * sizeof(int64_t));
+        memcpy(col, P->col, (size_t)nnzb * sizeof(int64_t));
+        memcpy(level, levs, (size_t)nnzb * sizeof(int64_t));
+    }
+    orc_bcsr_free(P);
+    free(levs);
+    return (int)nnzb;
 }
 
 /* z = U^{-1} L^{-1} r, row by row: forward y_i = r_i - sum_{k<i} L_ik y_k,
@@ -440,7 +559,14 @@ int orc_ras_setup(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
                   int32_t px, int32_t py, int32_t pz, int32_t overlap,
                   orc_ras **out, int64_t *bad_cell)
 {
-    if (!A || !out || px < 1 || py < 1 || pz < 1 || overlap < 0) return ORC_ERR_ARG;
+    return orc_ras_setup_k(A, nx, ny, nz, px, py, pz, overlap, 0, out, bad_cell);
+}
+
+int orc_ras_setup_k(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
+                    int32_t px, int32_t py, int32_t pz, int32_t overlap, int32_t level,
+                    orc_ras **out, int64_t *bad_cell)
+{
+    if (!A || !out || px < 1 || py < 1 || pz < 1 || overlap < 0 || level < 0) return ORC_ERR_ARG;
     if (px > nx || py > ny || pz > nz) return ORC_ERR_ARG;
     const int64_t n = A->n;
     if (n != (int64_t)nx * ny * nz) return ORC_ERR_ARG;
@@ -539,7 +665,7 @@ int orc_ras_setup(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
         }
         As->rowptr[m] = pos;
         int64_t bad = -1;
-        rc = orc_ilu0(As, &R->local[s], &bad);
+        rc = orc_iluk(As, level, &R->local[s], &bad);
         if (rc != ORC_OK && bad_cell) *bad_cell = (bad >= 0) ? cs[bad] : -1;
         orc_bcsr_free(As);
         for (int64_t q = 0; q < m; ++q) g2l[cs[q]] = -1;

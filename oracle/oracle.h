@@ -82,6 +82,10 @@ int  orc_ilu0(const orc_bcsr *A, orc_ilu **out, int64_t *bad_cell);
 void orc_ilu_free(orc_ilu *F);
 const orc_bcsr *orc_ilu_factors(const orc_ilu *F);   /* strict lower = L, upper incl. diagonal = U */
 int  orc_ilu_apply(void *F, const double *r, double *z);    /* z = (LU)^{-1} r */
+/* ILU(k): the IKJ factorisation on the level-k fill pattern (k = 0: ILU(0)) */
+int  orc_iluk(const orc_bcsr *A, int32_t k, orc_ilu **out, int64_t *bad_cell);
+/* the level-k pattern (rowptr n+1, col and level nnzb entries when nnzb <= cap); returns nnzb */
+int  orc_iluk_pattern(const orc_bcsr *A, int32_t k, int64_t *rowptr, int64_t *col, int64_t *level, int64_t cap);
 int  orc_ilu_apply_f32(void *F, const double *r, double *z);/* FP32 factors + FP32 sweeps */
 
 /* ---- RAS ---- */
@@ -89,6 +93,10 @@ typedef struct orc_ras orc_ras;
 int  orc_ras_setup(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
                    int32_t px, int32_t py, int32_t pz, int32_t overlap,
                    orc_ras **out, int64_t *bad_cell);
+/* the same with ILU(level) local solvers */
+int  orc_ras_setup_k(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
+                     int32_t px, int32_t py, int32_t pz, int32_t overlap, int32_t level,
+                     orc_ras **out, int64_t *bad_cell);
 void orc_ras_free(orc_ras *R);
 int  orc_ras_apply(void *R, const double *r, double *z);
 int64_t orc_ras_nsub(const orc_ras *R);

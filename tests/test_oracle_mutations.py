@@ -16,6 +16,7 @@ ORC = os.path.join(ROOT, "oracle")
 PINS = "tests/test_oracle_pins_branches.py"
 HP = "tests/test_oracle_hsfc_pins.py"
 SP = "tests/test_oracle_scalar_pins.py"
+KP = "tests/test_oracle_iluk_pins.py"
 
 # (id, file, text in the oracle, replacement, pins that must fail)
 MUTATIONS = [
@@ -45,6 +46,10 @@ MUTATIONS = [
      [SP + "::test_ilu0_characterisation_and_apply"]),
     ("scalar_ras_writes_every_cell", "scalar.c", "if (R->owner[cs[q]] == s) z[cs[q]] = zl[q];", "z[cs[q]] = zl[q];",
      [SP + "::test_ras_on_a_line_is_the_restricted_sum_of_exact_local_solves"]),
+    ("iluk_level_sum", "oracle.c", "const int64_t l = lev[m] + levs[q] + 1;", "const int64_t l = lev[m] + levs[q];",
+     [KP + "::test_level_one_pattern_of_the_seven_point_stencil[dims0]"]),
+    ("iluk_pattern_row_pointer", "oracle.c", "rp[i + 1] = used;   /* row i is read by the rows after it */", "",
+     [KP + "::test_level_one_pattern_of_the_seven_point_stencil[dims0]"]),
     ("bicgstab_no_rv_exit", "oracle.c",
      "if (rv == 0.0 || !isfinite(rv)) { rc = isfinite(rv) ? ORC_BREAKDOWN : ORC_ERR_NAN; break; }",
      "if (!isfinite(rv)) { rc = ORC_ERR_NAN; break; }",
