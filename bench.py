@@ -86,10 +86,10 @@ def log(*a):
 # per workload: the forms of one timed step (the first is the headline) and
 # the forms run once after the timed steps
 WORKLOAD_FORMS = {
-    "C5": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64"),
+    "C5": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64,gmres_ras64_iluk1"),
     "C3": ("gmres_bilu0,gmres_bilu0_fp32", "gmres_ras64"),
     "C2": ("gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,gmres_ras64_dcgs2,"
-           "gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64", ""),
+           "gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64,gmres_ras64_iluk1", ""),
     "C4": ("gmres_bilu0,gmres_bilu0_fp32", ""),
     "C1": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64"),
 }
@@ -390,6 +390,8 @@ def main():
         "bicgstab_ras64": (rsv.BICGSTAB, dict(type=rsv.PC_RAS, **ras)),
         "gmres_bilu0": (rsv.GMRES, dict(type=rsv.PC_BILU0)),
         "gmres_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_BILU0, precision=rsv.FP32)),
+        # RAS with ILU(1) local solvers (the RAS parameters' iluk_level 1)
+        "gmres_ras64_iluk1": (rsv.GMRES, dict(type=rsv.PC_RAS, iluk_level=1, **ras)),
     }
     # the same GMRES forms with the delayed second Gram-Schmidt pass
     for f in ("gmres_ras64", "gmres_bilu0", "gmres_ras64_fp32"):

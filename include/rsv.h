@@ -90,7 +90,10 @@ typedef struct rsv_pc_params {
     int32_t precision;   /* rsv_precision of the stored factors and triangular sweeps */
     int32_t ras_px, ras_py, ras_pz;  /* RAS: subdomain boxes per axis (default 4,4,4) */
     int32_t ras_overlap; /* RAS: matrix-graph overlap distance (default 1) */
-    int32_t iluk_level;  /* must be 0 (ILU(0)); kept to mirror RAS_PARS */
+    int32_t iluk_level;  /* level of fill k of the local ILU(k) (the RAS parameters' iluk_level, default 0):
+                          * 0 = ILU(0) on the fast paths; 1..8 (3x3-block matrices, FP64) = ILU(k) by
+                          * levels of fill, rows scheduled by dependency level, one workgroup per
+                          * subdomain (type RAS: the local solver; type BILU0: the whole grid) */
     int32_t pipelined;   /* 1 (default): sync-free tiled wavefront sweeps (RAS: every subdomain's local
                           * system in one auxiliary grid of boxes, swept together); 0: BILU0 one launch
                           * per hyperplane, RAS one workgroup per subdomain (reference mappings) */

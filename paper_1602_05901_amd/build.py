@@ -22,6 +22,7 @@ HIP_SOURCES = [
     "csrc/rsv_unet.hip",
     "csrc/rsv_hsfc.hip",
     "csrc/rsv_scalar.hip",
+    "csrc/rsv_iluk.hip",
 ]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

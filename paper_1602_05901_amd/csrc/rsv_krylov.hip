@@ -458,7 +458,9 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
     if (bad_cell) *bad_cell = -1;
     rsv_ctx *c = A->g->ctx;
     if (p->precision != RSV_FP64 && p->precision != RSV_FP32) return set_err(c, RSV_ERR_ARG, "bad precision");
-    if (p->iluk_level != 0) return set_err(c, RSV_ERR_ARG, "only ILU(0) is supported (iluk_level must be 0)");
+    if (p->iluk_level < 0 || p->iluk_level > 8) return set_err(c, RSV_ERR_ARG, "iluk_level must be in [0, 8]");
+    if (p->iluk_level > 0 && (A->bs == 1 || (p->type != RSV_PC_BILU0 && p->type != RSV_PC_RAS)))
+        return set_err(c, RSV_ERR_ARG, "ILU(k) with k > 0 is a block BILU / RAS local solver");
     if (A->bs == 1 && p->type == RSV_PC_LEARNED)
         return set_err(c, RSV_ERR_ARG, "the learned preconditioner needs a 3x3-block matrix");
     rsv_precond *P = new (std::nothrow) rsv_precond();
@@ -468,8 +470,14 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
     rsv_status s = RSV_OK;
     switch (p->type) {
     case RSV_PC_NONE: break;
-    case RSV_PC_BILU0: s = (A->bs == 1) ? sras_create(A, p, &P->impl, bad_cell) : bilu0_create(A, p, &P->impl, bad_cell); break;
-    case RSV_PC_RAS: s = (A->bs == 1) ? sras_create(A, p, &P->impl, bad_cell) : ras_create(A, p, &P->impl, bad_cell); break;
+    case RSV_PC_BILU0:
+        s = (A->bs == 1) ? sras_create(A, p, &P->impl, bad_cell)
+            : (p->iluk_level > 0) ? rasK_create(A, p, &P->impl, bad_cell) : bilu0_create(A, p, &P->impl, bad_cell);
+        break;
+    case RSV_PC_RAS:
+        s = (A->bs == 1) ? sras_create(A, p, &P->impl, bad_cell)
+            : (p->iluk_level > 0) ? rasK_create(A, p, &P->impl, bad_cell) : ras_create(A, p, &P->impl, bad_cell);
+        break;
     case RSV_PC_LEARNED: {
         rsv_pc_params fb = *p;
         fb.type = RSV_PC_BILU0;
