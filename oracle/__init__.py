@@ -270,7 +270,7 @@ def _pc_args(pc):
     if isinstance(pc, tuple) and pc[1] == "fp32":
         f, c = pc[0].fnptr(fp32=True)
         return f, c, keep
-    if isinstance(pc, (ILU, RAS)):
+    if hasattr(pc, "fnptr"):
         f, c = pc.fnptr()
         return f, c, keep
     if callable(pc):

@@ -131,6 +131,10 @@ void orc_csr_free(orc_csr *A);
 int64_t orc_csr_nnz(const orc_csr *A);
 void orc_csr_export(const orc_csr *A, int64_t *rowptr, int64_t *col, double *val);
 void orc_csr_spmv(const orc_csr *A, const double *x, double *y);
+/* a copy of rowptr (n+1) / col / val; columns strictly ascending in each row */
+int  orc_csr_from_arrays(int64_t n, const int64_t *rowptr, const int64_t *col, const double *val, orc_csr **out);
+/* read-only views of the arrays (owned by A) */
+void orc_csr_view(const orc_csr *A, int64_t *n, const int64_t **rowptr, const int64_t **col, const double **val);
 int  orc_csr_ilu0(const orc_csr *A, orc_silu **out, int64_t *bad_row);
 void orc_silu_free(orc_silu *F);
 const orc_csr *orc_silu_factors(const orc_silu *F);
@@ -146,6 +150,30 @@ int  orc_csr_gmres(const orc_csr *A, orc_apply_fn pc, void *pc_ctx, const double
                    double tol, int64_t maxit, orc_stats *st, double *hist);
 int  orc_csr_bicgstab(const orc_csr *A, orc_apply_fn pc, void *pc_ctx, const double *b, double *x, double tol,
                       int64_t maxit, orc_stats *st, double *hist);
+
+/* ---- aggregation multigrid V-cycle for 7-point scalar systems (mg.c) ---- */
+typedef struct orc_mg orc_mg;
+int  orc_mg_setup(const orc_csr *A /* not copied; must outlive */, int32_t nx, int32_t ny, int32_t nz,
+                  int32_t coarse_max, int32_t pre, int32_t post, orc_mg **out);
+void orc_mg_free(orc_mg *M);
+int  orc_mg_apply(void *M, const double *b, double *x);       /* x = one V-cycle from 0 */
+int32_t orc_mg_levels(const orc_mg *M);
+void orc_mg_level_dims(const orc_mg *M, int32_t l, int32_t *dims);
+const orc_csr *orc_mg_level_matrix(const orc_mg *M, int32_t l);
+int  orc_mg_gs_sweep(const orc_mg *M, const double *b, double *x, int32_t colour);   /* level 0 */
+
+/* ---- CPR-type two-stage preconditioners (cpr.c) ---- */
+enum { ORC_CPR_FP = 0, ORC_CPR_PF = 1, ORC_CPR_FPF = 2, ORC_CPR_FFPF = 3 };
+enum { ORC_DECOUPLE_NONE = 0, ORC_DECOUPLE_QUASI_IMPES = 1, ORC_DECOUPLE_ABF = 2 };
+typedef struct orc_cpr orc_cpr;
+int  orc_cpr_setup(const orc_bcsr *A /* not copied */, int32_t nx, int32_t ny, int32_t nz, int32_t variant,
+                   int32_t decouple, orc_apply_fn R, void *R_ctx, int32_t coarse_max, int32_t pre, int32_t post,
+                   orc_cpr **out, int64_t *bad_cell);
+void orc_cpr_free(orc_cpr *P);
+int  orc_cpr_apply(void *P, const double *f, double *x);
+void orc_cpr_weights(const orc_cpr *P, double *w);                /* [n][3] */
+const orc_csr *orc_cpr_pressure_matrix(const orc_cpr *P);
+const orc_mg *orc_cpr_mg(const orc_cpr *P);
 
 /* ---- learned preconditioner network (unet.c) ---- */
 double  orc_bf16(double x);      /* round to the nearest BF16 value (ties to even) */

@@ -98,6 +98,37 @@ int orc_csr_from_stencil(int32_t nx, int32_t ny, int32_t nz, const double *coef,
     return ORC_OK;
 }
 
+int orc_csr_from_arrays(int64_t n, const int64_t *rowptr, const int64_t *col, const double *val, orc_csr **out)
+{
+    if (n < 0 || !rowptr || !out) return ORC_ERR_ARG;
+    const int64_t nnz = rowptr[n];
+    if (nnz < 0 || (nnz > 0 && (!col || !val))) return ORC_ERR_ARG;
+    for (int64_t i = 0; i < n; ++i) {
+        if (rowptr[i + 1] < rowptr[i]) return ORC_ERR_ARG;
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            if (col[p] < 0 || col[p] >= n || (p > rowptr[i] && col[p] <= col[p - 1])) return ORC_ERR_ARG;
+            if (!isfinite(val[p])) return ORC_ERR_NAN;
+        }
+    }
+    orc_csr *A = csr_alloc(n, nnz);
+    if (!A) return ORC_ERR_OOM;
+    memcpy(A->rowptr, rowptr, (size_t)(n + 1) * sizeof(int64_t));
+    if (nnz > 0) {
+        memcpy(A->col, col, (size_t)nnz * sizeof(int64_t));
+        memcpy(A->val, val, (size_t)nnz * sizeof(double));
+    }
+    *out = A;
+    return ORC_OK;
+}
+
+void orc_csr_view(const orc_csr *A, int64_t *n, const int64_t **rowptr, const int64_t **col, const double **val)
+{
+    *n = A->n;
+    *rowptr = A->rowptr;
+    *col = A->col;
+    *val = A->val;
+}
+
 void orc_csr_spmv(const orc_csr *A, const double *x, double *y)
 {
     for (int64_t i = 0; i < A->n; ++i) {

@@ -25,6 +25,7 @@ def _lib():
             "orc_csr_nnz": ([vp], i64),
             "orc_csr_export": ([vp, vp, vp, vp], None),
             "orc_csr_spmv": ([vp, vp, vp], None),
+            "orc_csr_from_arrays": ([i64, vp, vp, vp, P(vp)], ctypes.c_int),
             "orc_csr_ilu0": ([vp, P(vp), P(i64)], ctypes.c_int),
             "orc_silu_free": ([vp], None),
             "orc_silu_factors": ([vp], vp),
@@ -63,6 +64,24 @@ class CSR:
         self.h = h
         self.n = nx * ny * nz
         self.dims = (nx, ny, nz)
+
+    @classmethod
+    def from_arrays(cls, rowptr, col, val, dims):
+        """A copy of a CSR matrix given by its arrays, on an nx x ny x nz grid."""
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int64)
+        val = _f64(val)
+        n = len(rowptr) - 1
+        assert n == dims[0] * dims[1] * dims[2]
+        h = ctypes.c_void_p()
+        rc = _lib().orc_csr_from_arrays(n, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, ctypes.byref(h))
+        if rc != 0:
+            raise OracleError(rc, "csr_from_arrays")
+        self = cls.__new__(cls)
+        self.h = h
+        self.n = n
+        self.dims = tuple(dims)
+        return self
 
     def __del__(self):
         if getattr(self, "h", None) is not None and self.h.value and _L is not None:
@@ -169,7 +188,7 @@ class RAS:
 
 
 def _pc(pc):
-    if isinstance(pc, (ILU, RAS)):
+    if hasattr(pc, "fnptr"):
         f, c = pc.fnptr()
         return f, c, None
     return _pc_args(pc)

@@ -17,6 +17,7 @@ PINS = "tests/test_oracle_pins_branches.py"
 HP = "tests/test_oracle_hsfc_pins.py"
 SP = "tests/test_oracle_scalar_pins.py"
 KP = "tests/test_oracle_iluk_pins.py"
+CP = "tests/test_oracle_cpr_pins.py"
 
 # (id, file, text in the oracle, replacement, pins that must fail)
 MUTATIONS = [
@@ -54,13 +55,38 @@ MUTATIONS = [
      "if (rv == 0.0 || !isfinite(rv)) { rc = isfinite(rv) ? ORC_BREAKDOWN : ORC_ERR_NAN; break; }",
      "if (!isfinite(rv)) { rc = ORC_ERR_NAN; break; }",
      [PINS + "::test_bicgstab_breakdown_exits[rv0]"]),
+    ("mg_post_sweep_order", "mg.c",
+     "        if ((rc = gs_colour(L, b, x, 1)) != ORC_OK) return rc;\n        if ((rc = gs_colour(L, b, x, 0)) != ORC_OK) return rc;\n    }\n    return ORC_OK;",
+     "        if ((rc = gs_colour(L, b, x, 0)) != ORC_OK) return rc;\n        if ((rc = gs_colour(L, b, x, 1)) != ORC_OK) return rc;\n    }\n    return ORC_OK;",
+     [CP + "::test_cycle_is_symmetric_for_a_symmetric_matrix"]),
+    ("mg_restriction_overwrites", "mg.c", "C->b[aggregate_of(L, i, C->nx, C->ny)] += L->r[i];",
+     "C->b[aggregate_of(L, i, C->nx, C->ny)] = L->r[i];",
+     [CP + "::test_cycle_error_operator_matches_the_multigrid_recursion"]),
+    ("mg_residual_sign", "mg.c", "L->r[i] = b[i] - L->r[i];", "L->r[i] = L->r[i] - b[i];",
+     [CP + "::test_cycle_error_operator_matches_the_multigrid_recursion"]),
+    ("mg_galerkin_overwrites", "mg.c", "cval[I * MG_ROW_CAP + q] += val[p];", "cval[I * MG_ROW_CAP + q] = val[p];",
+     [CP + "::test_levels_are_galerkin_products_on_halved_grids"]),
+    ("cpr_fpf_stale_residual", "cpr.c",
+     "        residual(P, f, x, P->r);\n        if ((rc = smoother_step(P, P->r, x)) != ORC_OK) return rc;\n        break;\n    case ORC_CPR_FFPF:",
+     "        if ((rc = smoother_step(P, P->r, x)) != ORC_OK) return rc;\n        break;\n    case ORC_CPR_FFPF:",
+     [CP + "::test_error_propagation_is_the_product_of_the_stages"]),
+    ("cpr_quasi_impes_sign", "cpr.c", "w[1] = (-d[1] * d[8] + d[7] * d[2]) / det;",
+     "w[1] = (d[1] * d[8] - d[7] * d[2]) / det;", [CP + "::test_decoupling_weights"]),
+    ("cpr_abf_column_of_the_inverse", "cpr.c", "w[1] = inv[1];\n        w[2] = inv[2];",
+     "w[1] = inv[3];\n        w[2] = inv[6];", [CP + "::test_decoupling_weights"]),
+    ("cpr_pressure_row_not_column", "cpr.c", "val[p] = w[0] * blk[0] + w[1] * blk[3] + w[2] * blk[6];",
+     "val[p] = w[0] * blk[0] + w[1] * blk[1] + w[2] * blk[2];",
+     [CP + "::test_pressure_matrix_is_the_restricted_decoupled_matrix"]),
 ]
+
+
+C_SOURCES = ("oracle.c", "unet.c", "hsfc.c", "scalar.c", "mg.c", "cpr.c")
 
 
 def _build(tmp, mutation=None):
     src = os.path.join(tmp, "src")
     os.makedirs(src, exist_ok=True)
-    for f in ("oracle.c", "unet.c", "hsfc.c", "scalar.c", "oracle.h"):
+    for f in C_SOURCES + ("oracle.h",):
         shutil.copy(os.path.join(ORC, f), src)
     if mutation is not None:
         _, fname, old, new, _ = mutation
@@ -70,8 +96,7 @@ def _build(tmp, mutation=None):
         open(path, "w").write(text.replace(old, new))
     lib = os.path.join(tmp, "liboracle_mut.so")
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", lib,
-                    os.path.join(src, "oracle.c"), os.path.join(src, "unet.c"), os.path.join(src, "hsfc.c"),
-                    os.path.join(src, "scalar.c"), "-lm"],
+                    *[os.path.join(src, f) for f in C_SOURCES], "-lm"],
                    check=True)
     return lib
 
