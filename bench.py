@@ -86,10 +86,12 @@ def log(*a):
 # per workload: the forms of one timed step (the first is the headline) and
 # the forms run once after the timed steps
 WORKLOAD_FORMS = {
-    "C5": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64,gmres_ras64_iluk1"),
+    "C5": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64,gmres_ras64_iluk1,gmres_cpr_fpf,"
+           "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0"),
     "C3": ("gmres_bilu0,gmres_bilu0_fp32", "gmres_ras64"),
     "C2": ("gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,gmres_ras64_dcgs2,"
-           "gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64,gmres_ras64_iluk1", ""),
+           "gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64,gmres_ras64_iluk1,gmres_cpr_fpf,"
+           "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0", ""),
     "C4": ("gmres_bilu0,gmres_bilu0_fp32", ""),
     "C1": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64"),
 }
@@ -392,6 +394,11 @@ def main():
         "gmres_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_BILU0, precision=rsv.FP32)),
         # RAS with ILU(1) local solvers (the RAS parameters' iluk_level 1)
         "gmres_ras64_iluk1": (rsv.GMRES, dict(type=rsv.PC_RAS, iluk_level=1, **ras)),
+        # CPR-FPF two-stage preconditioners (stage R = RAS(4x4x4) or BILU0,
+        # pressure stage = one aggregation-multigrid V-cycle, no decoupling)
+        "gmres_cpr_fpf": (rsv.GMRES, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_RAS, **ras)),
+        "gmres_cpr_fpf_bilu0": (rsv.GMRES, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_BILU0)),
+        "bicgstab_cpr_fpf_bilu0": (rsv.BICGSTAB, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_BILU0)),
     }
     # the same GMRES forms with the delayed second Gram-Schmidt pass
     for f in ("gmres_ras64", "gmres_bilu0", "gmres_ras64_fp32"):
@@ -439,7 +446,7 @@ def main():
         t2 = time.perf_counter()
         x = torch.zeros_like(b)
         if profile:
-            ctx.profile(True, classes=("spmv", "ilu_fwd", "ilu_bwd", "ortho"))
+            ctx.profile(True, classes=("spmv", "ilu_fwd", "ilu_bwd", "ortho", "cpr"))
         st = rsv.solve(A, M, b, x, method=method, restart=30, tol=1e-8, maxit=10000,
                        ortho=(rsv.DCGS2 if name.endswith("_dcgs2") else rsv.CGS2))
         torch.cuda.synchronize()
@@ -520,9 +527,9 @@ def main():
             # GMRES products (y = A z with ||y||^2) read no third vector; the few
             # residual launches per solve that do read b are counted the same
             ab["spmv"] = ab_global["spmv_plain"]
-        if forms_all[form][1].get("type") == rsv.PC_RAS:
+        pk = forms_all[form][1]
+        if pk.get("type") == rsv.PC_RAS or (pk.get("type") == rsv.PC_CPR and pk.get("cpr_stage") == rsv.PC_RAS):
             # the sweeps of this form are the local RAS sweeps
-            pk = forms_all[form][1]
             ab_ras = ras_algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz, (pk["ras_px"], pk["ras_py"], pk["ras_pz"]),
                                            pk["ras_overlap"])
             ab["ilu_fwd"], ab["ilu_bwd"] = ab_ras["ilu_fwd"], ab_ras["ilu_bwd"]

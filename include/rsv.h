@@ -59,8 +59,32 @@ typedef enum {
     RSV_PC_NONE = 0,
     RSV_PC_BILU0 = 1,    /* global block ILU(0) in natural (bottom-up) order */
     RSV_PC_RAS = 2,      /* restricted additive Schwarz, local block ILU(0) */
-    RSV_PC_LEARNED = 3   /* user-type preconditioner: the U-Net, BILU0 fallback (FGMRES only) */
+    RSV_PC_LEARNED = 3,  /* user-type preconditioner: the U-Net, BILU0 fallback (FGMRES only) */
+    RSV_PC_CPR = 4       /* CPR-type two-stage preconditioner (the paper's CPR_FP .. CPR_FFPF) */
 } rsv_pc_type;
+
+/* The four CPR-type algorithms of the CPR-like Preconditioners subsection.
+ * R = the whole-system stage (RAS or BILU0), P = the pressure stage
+ * x += Pi_p M_g(A_pp)^-1 Pi_r W r, each stage applied to the current residual
+ * r = f - A x:
+ *   RSV_CPR_FP    x = R f, then P;
+ *   RSV_CPR_PF    x = Pi_p M_g^-1 Pi_r W f, then R (the printed steps
+ *                 overwrite the first x and apply R to f again; read as the
+ *                 two-stage form);
+ *   RSV_CPR_FPF   x = R f, then P, then R (the simulator runs' choice);
+ *   RSV_CPR_FFPF  x = R f, then R, then P, then R. */
+typedef enum { RSV_CPR_FP = 0, RSV_CPR_PF = 1, RSV_CPR_FPF = 2, RSV_CPR_FFPF = 3 } rsv_cpr_variant;
+
+/* Decoupling of the pressure equation (the simulator runs name a decoupling
+ * without defining it).  The pressure equation of cell c is w_c^T times block
+ * row c, A_pp(c, n) = w_c^T A_cn e_0, and the restricted residual is
+ * w_c^T r_c; the pressure is unknown 0 of each cell.
+ *   RSV_DECOUPLE_NONE         w_c = e_0: A_pp is the pressure-pressure submatrix;
+ *   RSV_DECOUPLE_QUASI_IMPES  w_c = (1, w1, w2) with w_c^T A_cc zero in columns
+ *                             1 and 2 (Scheichl, Masson & Wendebourg 2003);
+ *   RSV_DECOUPLE_ABF          w_c^T = e_0^T A_cc^-1 (alternate block
+ *                             factorisation, Bank, Chan, Coughran & Smith 1989). */
+typedef enum { RSV_DECOUPLE_NONE = 0, RSV_DECOUPLE_QUASI_IMPES = 1, RSV_DECOUPLE_ABF = 2 } rsv_decouple;
 
 typedef enum { RSV_FP64 = 0, RSV_FP32 = 1 } rsv_precision;
 
@@ -109,7 +133,20 @@ typedef struct rsv_pc_params {
     int32_t ras_group;   /* RAS, pipelined: boxes placed side by side in groups of ras_group x ras_group,
                           * each group padded to whole 8 x 8 tiles (0, default: 1, each box padded alone;
                           * at most 16; made smaller when the boxes of a layer do not fill a group) */
-    int32_t reserved[5];
+    /* CPR (3x3-block matrices).  The stage R is built from the fields above
+     * with type cpr_stage (precision, RAS boxes and overlap, iluk_level,
+     * pipelined apply to it).  M_g is one V-cycle of an aggregation multigrid
+     * on the grid: 2x2x2 aggregates (an axis of one cell is kept), Galerkin
+     * coarse operators (which stay 7-point), red-black Gauss-Seidel smoothing
+     * (mg_pre sweeps red then black, mg_post sweeps black then red), and an
+     * exact solve on the first level with at most mg_coarse cells. */
+    int32_t cpr_variant; /* rsv_cpr_variant (default RSV_CPR_FPF) */
+    int32_t cpr_stage;   /* RSV_PC_RAS (default) or RSV_PC_BILU0 */
+    int32_t cpr_decouple;/* rsv_decouple (default RSV_DECOUPLE_NONE) */
+    int32_t mg_pre;      /* pre-smoothing sweeps, 1..8 (default 1) */
+    int32_t mg_post;     /* post-smoothing sweeps, 1..8 (default 1) */
+    int32_t mg_coarse;   /* largest coarsest level, 1..1024 cells (default 512) */
+    int32_t reserved[3];
 } rsv_pc_params;
 
 /* Solver parameters; mirrors SOLVER (rtol, atol, maxit, restart). */
@@ -231,14 +268,31 @@ int64_t rsv_matrix_device_bytes(const rsv_matrix *A);
 
 void rsv_pc_params_default(rsv_pc_params *p);
 /* Build the preconditioner (SOLVER_PC assemble hook): BILU0 factorisation,
- * RAS subdomains + local factorisations, or the learned network plus its
- * BILU0 fallback.  Errors: RSV_ERR_ARG, RSV_ERR_OOM, RSV_ERR_ZERO_PIVOT
+ * RAS subdomains + local factorisations, the learned network plus its
+ * BILU0 fallback, or a CPR preconditioner (its stage R, the decoupling
+ * weights, A_pp and the multigrid hierarchy with the inverse of its
+ * coarsest level).  Errors: RSV_ERR_ARG, RSV_ERR_OOM, RSV_ERR_ZERO_PIVOT
  * (the offending block row is written to *bad_cell if non-NULL), RSV_ERR_HIP. */
 rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond **out, int64_t *bad_cell);
 /* z = M^{-1} r (SOLVER_PC solve hook); r, z device vectors, may not alias.
  * For LEARNED this applies the network (no fallback). */
 rsv_status rsv_precond_apply(rsv_precond *M, const double *r, double *z);
 void rsv_precond_destroy(rsv_precond *M);
+/* CPR diagnostics (RSV_PC_CPR only; else RSV_ERR_ARG).
+ * rsv_cpr_levels: the multigrid's level count into *nlevels and, for
+ *   l < min(nlevels, cap), the grid of level l into dims[3l .. 3l+2] (HOST).
+ * rsv_cpr_pressure_matrix: the seven coefficients of every row of level l
+ *   (level 0 = A_pp) into the HOST array coef[n_l][7], rows in the order
+ *   i + nx (j + ny k') of that level's grid, where k' is the block-row layer
+ *   (the layer of the grid's ordering), slots -z,-y,-x,D,+x,+y,+z in k'.
+ * rsv_cpr_weights: the decoupling weights w_c into the HOST array w[ncell][3],
+ *   block-row order.
+ * rsv_cpr_pressure_apply: x = M_g(A_pp)^-1 b, one V-cycle; b and x DEVICE
+ *   vectors of length ncell in block-row order (may not alias). */
+rsv_status rsv_cpr_levels(const rsv_precond *M, int32_t *nlevels, int32_t *dims, int32_t cap);
+rsv_status rsv_cpr_pressure_matrix(const rsv_precond *M, int32_t level, double *coef);
+rsv_status rsv_cpr_weights(const rsv_precond *M, double *w);
+rsv_status rsv_cpr_pressure_apply(rsv_precond *M, const double *b, double *x);
 /* Diagnostics: the block ILU(0) factors of an FP64 BILU0 preconditioner
  * (Preconditioners section, ILU(0) of the block matrix), copied to HOST
  * arrays in block-row order: L[row][3][3][3], the unit-lower blocks
@@ -330,7 +384,8 @@ enum {
     RSV_K_VEC = 5,       /* other vector kernels (BiCGSTAB updates, copies, reductions) */
     RSV_K_FACTOR = 6,    /* factorisations */
     RSV_K_NET = 7,       /* U-Net kernels */
-    RSV_K_COUNT = 8
+    RSV_K_CPR = 8,       /* CPR: residual-restriction products, multigrid, prolongation, combination */
+    RSV_K_COUNT = 9
 };
 /* on = 1 starts (and zeroes) the per-class totals, on = 0 stops recording. */
 rsv_status rsv_profile_enable(rsv_ctx *ctx, int32_t on);

@@ -23,6 +23,7 @@ HIP_SOURCES = [
     "csrc/rsv_hsfc.hip",
     "csrc/rsv_scalar.hip",
     "csrc/rsv_iluk.hip",
+    "csrc/rsv_cpr.hip",
 ]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

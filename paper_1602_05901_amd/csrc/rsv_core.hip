@@ -423,6 +423,12 @@ void rsv_pc_params_default(rsv_pc_params *p)
     p->iluk_level = 0;
     p->pipelined = 1;
     p->theta = 0.9;
+    p->cpr_variant = RSV_CPR_FPF;
+    p->cpr_stage = RSV_PC_RAS;
+    p->cpr_decouple = RSV_DECOUPLE_NONE;
+    p->mg_pre = 1;
+    p->mg_post = 1;
+    p->mg_coarse = 512;
 }
 
 void rsv_solver_params_default(rsv_solver_params *p)

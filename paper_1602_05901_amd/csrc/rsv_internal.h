@@ -300,6 +300,9 @@ rsv_status bilu0_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int
 rsv_status bilu0_create_boxed(rsv_matrix *A, const rsv_pc_params *p, int btx, int bty, const int32_t *zmap,
                               PcImpl **out, int64_t *bad_cell);
 rsv_status ras_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
+// CPR-type two-stage preconditioner around the stage R (owned by the result,
+// deleted on failure); p carries the variant, decoupling and multigrid fields
+rsv_status cpr_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl *stage, PcImpl **out, int64_t *bad_cell);
 // base: the BILU0 preconditioner a learned_mode 1 network corrects (not owned)
 rsv_status learned_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, PcImpl *base);
 // LDS ring depth (slots) of the pipelined BILU0 sweeps for this device

@@ -459,10 +459,23 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
     rsv_ctx *c = A->g->ctx;
     if (p->precision != RSV_FP64 && p->precision != RSV_FP32) return set_err(c, RSV_ERR_ARG, "bad precision");
     if (p->iluk_level < 0 || p->iluk_level > 8) return set_err(c, RSV_ERR_ARG, "iluk_level must be in [0, 8]");
-    if (p->iluk_level > 0 && (A->bs == 1 || (p->type != RSV_PC_BILU0 && p->type != RSV_PC_RAS)))
+    if (p->iluk_level > 0 && (A->bs == 1 || (p->type != RSV_PC_BILU0 && p->type != RSV_PC_RAS &&
+                                             p->type != RSV_PC_CPR)))
         return set_err(c, RSV_ERR_ARG, "ILU(k) with k > 0 is a block BILU / RAS local solver");
     if (A->bs == 1 && p->type == RSV_PC_LEARNED)
         return set_err(c, RSV_ERR_ARG, "the learned preconditioner needs a 3x3-block matrix");
+    if (p->type == RSV_PC_CPR) {
+        if (A->bs == 1) return set_err(c, RSV_ERR_ARG, "CPR needs a 3x3-block matrix");
+        if (p->cpr_stage != RSV_PC_BILU0 && p->cpr_stage != RSV_PC_RAS)
+            return set_err(c, RSV_ERR_ARG, "cpr_stage must be RSV_PC_BILU0 or RSV_PC_RAS");
+        if (p->cpr_variant < RSV_CPR_FP || p->cpr_variant > RSV_CPR_FFPF)
+            return set_err(c, RSV_ERR_ARG, "bad cpr_variant");
+        if (p->cpr_decouple < RSV_DECOUPLE_NONE || p->cpr_decouple > RSV_DECOUPLE_ABF)
+            return set_err(c, RSV_ERR_ARG, "bad cpr_decouple");
+        if (p->mg_pre < 1 || p->mg_pre > 8 || p->mg_post < 1 || p->mg_post > 8)
+            return set_err(c, RSV_ERR_ARG, "mg_pre and mg_post must be in [1, 8]");
+        if (p->mg_coarse < 1 || p->mg_coarse > 1024) return set_err(c, RSV_ERR_ARG, "mg_coarse must be in [1, 1024]");
+    }
     rsv_precond *P = new (std::nothrow) rsv_precond();
     if (!P) return set_err(c, RSV_ERR_OOM, "precond");
     P->A = A;
@@ -478,6 +491,15 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
         s = (A->bs == 1) ? sras_create(A, p, &P->impl, bad_cell)
             : (p->iluk_level > 0) ? rasK_create(A, p, &P->impl, bad_cell) : ras_create(A, p, &P->impl, bad_cell);
         break;
+    case RSV_PC_CPR: {
+        rsv_pc_params st = *p;
+        st.type = p->cpr_stage;
+        PcImpl *stage = nullptr;
+        s = (st.iluk_level > 0) ? rasK_create(A, &st, &stage, bad_cell)
+            : (st.type == RSV_PC_RAS) ? ras_create(A, &st, &stage, bad_cell) : bilu0_create(A, &st, &stage, bad_cell);
+        if (s == RSV_OK) s = cpr_create(A, p, stage, &P->impl, bad_cell);
+        break;
+    }
     case RSV_PC_LEARNED: {
         rsv_pc_params fb = *p;
         fb.type = RSV_PC_BILU0;

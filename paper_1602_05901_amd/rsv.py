@@ -17,7 +17,9 @@ OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 ERR_ARG, ERR_OOM, ERR_HIP, ERR_ZERO_PIVOT, ERR_NAN, ERR_PATTERN, ERR_TIMEOUT = -1, -2, -3, -4, -5, -6, -7
 BOTTOM_UP, TOP_DOWN = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
-PC_NONE, PC_BILU0, PC_RAS, PC_LEARNED = 0, 1, 2, 3
+PC_NONE, PC_BILU0, PC_RAS, PC_LEARNED, PC_CPR = 0, 1, 2, 3, 4
+CPR_FP, CPR_PF, CPR_FPF, CPR_FFPF = 0, 1, 2, 3
+DECOUPLE_NONE, DECOUPLE_QUASI_IMPES, DECOUPLE_ABF = 0, 1, 2
 FP64, FP32 = 0, 1
 GMRES, BICGSTAB, FGMRES = 0, 1, 2
 CGS2, DCGS2 = 0, 1
@@ -29,7 +31,8 @@ class PcParams(ctypes.Structure):
     _fields_ = [("type", i32), ("precision", i32), ("ras_px", i32), ("ras_py", i32), ("ras_pz", i32),
                 ("ras_overlap", i32), ("iluk_level", i32), ("pipelined", i32), ("net", vp), ("lnk", vp),
                 ("theta", dbl), ("learned_mode", i32), ("ras_stack", i32), ("ras_group", i32),
-                ("reserved", i32 * 5)]
+                ("cpr_variant", i32), ("cpr_stage", i32), ("cpr_decouple", i32), ("mg_pre", i32),
+                ("mg_post", i32), ("mg_coarse", i32), ("reserved", i32 * 3)]
 
 
 class SolverParams(ctypes.Structure):
@@ -78,6 +81,10 @@ _SIGS = {
     "rsv_precond_setup": ([vp, _P(PcParams), _P(vp), _P(i64)], i32),
     "rsv_precond_apply": ([vp, vp, vp], i32),
     "rsv_precond_bilu0_factors": ([vp, vp, vp], i32),
+    "rsv_cpr_levels": ([vp, _P(i32), vp, i32], i32),
+    "rsv_cpr_pressure_matrix": ([vp, i32, vp], i32),
+    "rsv_cpr_weights": ([vp, vp], i32),
+    "rsv_cpr_pressure_apply": ([vp, vp, vp], i32),
     "rsv_precond_destroy": ([vp], None),
     "rsv_solver_params_default": ([_P(SolverParams)], None),
     "rsv_solve": ([vp, vp, _P(SolverParams), vp, vp, _P(Stats)], i32),
@@ -100,7 +107,7 @@ _SIGS = {
     "rsv_device_info": ([vp, vp, i32], i32),
     "rsv_set_wait_limit": ([vp, ctypes.c_double], i32),
 }
-K_NAMES = ["spmv", "ilu_fwd", "ilu_bwd", "ras", "ortho", "vec", "factor", "net"]
+K_NAMES = ["spmv", "ilu_fwd", "ilu_bwd", "ras", "ortho", "vec", "factor", "net", "cpr"]
 
 _lib = None
 
@@ -326,6 +333,32 @@ class Precond:
         D = np.zeros((n, 3, 3))
         _check(self.ctx, lib().rsv_precond_bilu0_factors(self.h, L.ctypes.data, D.ctypes.data))
         return L, D
+
+    def cpr_levels(self):
+        """Grids (nx, ny, nz) of the CPR pressure multigrid, finest first."""
+        import numpy as np
+        nl = i32(0)
+        dims = np.zeros(3 * 64, np.int32)
+        _check(self.ctx, lib().rsv_cpr_levels(self.h, ctypes.byref(nl), dims.ctypes.data, 64))
+        return [tuple(int(v) for v in dims[3 * l:3 * l + 3]) for l in range(nl.value)]
+
+    def cpr_pressure_matrix(self, level=0):
+        """[n_level, 7] coefficients of the pressure matrix on one level (row order)."""
+        import numpy as np
+        d = self.cpr_levels()[level]
+        out = np.zeros((d[0] * d[1] * d[2], 7))
+        _check(self.ctx, lib().rsv_cpr_pressure_matrix(self.h, level, out.ctypes.data))
+        return out
+
+    def cpr_weights(self):
+        import numpy as np
+        out = np.zeros((self.A.grid.ncell, 3))
+        _check(self.ctx, lib().rsv_cpr_weights(self.h, out.ctypes.data))
+        return out
+
+    def cpr_pressure_apply(self, b, x):
+        _check(self.ctx, lib().rsv_cpr_pressure_apply(self.h, _ptr(b), _ptr(x)))
+        return x
 
     def close(self):
         if self.h:
