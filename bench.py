@@ -87,11 +87,11 @@ def log(*a):
 # the forms run once after the timed steps
 WORKLOAD_FORMS = {
     "C5": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64,gmres_ras64_iluk1,gmres_cpr_fpf,"
-           "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0"),
+           "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0,gmres_cpr_fpf_bilu0_fp32"),
     "C3": ("gmres_bilu0,gmres_bilu0_fp32", "gmres_ras64"),
     "C2": ("gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,gmres_ras64_dcgs2,"
            "gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64,gmres_ras64_iluk1,gmres_cpr_fpf,"
-           "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0", ""),
+           "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0,gmres_cpr_fpf_fp32,gmres_cpr_fpf_bilu0_fp32", ""),
     "C4": ("gmres_bilu0,gmres_bilu0_fp32", ""),
     "C1": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64"),
 }
@@ -399,6 +399,9 @@ def main():
         "gmres_cpr_fpf": (rsv.GMRES, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_RAS, **ras)),
         "gmres_cpr_fpf_bilu0": (rsv.GMRES, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_BILU0)),
         "bicgstab_cpr_fpf_bilu0": (rsv.BICGSTAB, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_BILU0)),
+        # the FP32 form of CPR-FPF: FP32 sweeps, FP32 copies of A and of the level operators
+        "gmres_cpr_fpf_fp32": (rsv.GMRES, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_RAS, precision=rsv.FP32, **ras)),
+        "gmres_cpr_fpf_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_BILU0, precision=rsv.FP32)),
     }
     # the same GMRES forms with the delayed second Gram-Schmidt pass
     for f in ("gmres_ras64", "gmres_bilu0", "gmres_ras64_fp32"):

@@ -139,13 +139,16 @@ typedef struct rsv_pc_params {
      * on the grid: 2x2x2 aggregates (an axis of one cell is kept), Galerkin
      * coarse operators (which stay 7-point), red-black Gauss-Seidel smoothing
      * (mg_pre sweeps red then black, mg_post sweeps black then red), and an
-     * exact solve on the first level with at most mg_coarse cells. */
+     * exact solve on the first level with at most mg_coarse cells.  With
+     * precision RSV_FP32 the stage R sweeps in FP32 and the CPR's own
+     * residual products and multigrid read FP32 copies of A and of the level
+     * operators (arithmetic and vectors stay FP64). */
     int32_t cpr_variant; /* rsv_cpr_variant (default RSV_CPR_FPF) */
     int32_t cpr_stage;   /* RSV_PC_RAS (default) or RSV_PC_BILU0 */
     int32_t cpr_decouple;/* rsv_decouple (default RSV_DECOUPLE_NONE) */
     int32_t mg_pre;      /* pre-smoothing sweeps, 1..8 (default 1) */
     int32_t mg_post;     /* post-smoothing sweeps, 1..8 (default 1) */
-    int32_t mg_coarse;   /* largest coarsest level, 1..1024 cells (default 512) */
+    int32_t mg_coarse;   /* largest coarsest level, 1..1024 cells (default 128) */
     int32_t reserved[3];
 } rsv_pc_params;
 

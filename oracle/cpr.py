@@ -82,7 +82,7 @@ class _Levels:
 class MG(_Levels):
     """One V-cycle of the aggregation multigrid for a scalar 7-point CSR matrix."""
 
-    def __init__(self, A: CSR, dims, coarse_max=512, pre=1, post=1):
+    def __init__(self, A: CSR, dims, coarse_max=128, pre=1, post=1):
         h = ctypes.c_void_p()
         rc = _lib().orc_mg_setup(A.h, *dims, coarse_max, pre, post, ctypes.byref(h))
         if rc != 0:
@@ -131,7 +131,7 @@ class CPR(_Levels):
     """CPR-type preconditioner of a block matrix; R is an oracle
     preconditioner object of the whole system (ILU, RAS) with fnptr()."""
 
-    def __init__(self, A: BCSR, dims, R, variant=FPF, decouple=DECOUPLE_NONE, coarse_max=512, pre=1, post=1):
+    def __init__(self, A: BCSR, dims, R, variant=FPF, decouple=DECOUPLE_NONE, coarse_max=128, pre=1, post=1):
         f, c = R.fnptr()
         h = ctypes.c_void_p()
         bad = ctypes.c_int64(-1)

@@ -428,7 +428,7 @@ void rsv_pc_params_default(rsv_pc_params *p)
     p->cpr_decouple = RSV_DECOUPLE_NONE;
     p->mg_pre = 1;
     p->mg_post = 1;
-    p->mg_coarse = 512;
+    p->mg_coarse = 128;
 }
 
 void rsv_solver_params_default(rsv_solver_params *p)

@@ -108,8 +108,8 @@ __global__ __launch_bounds__(CB) void k_cpr_extract(Geo g, const double *__restr
 // Residual of the block system at x + Pi_p e (x NULL: zero; e NULL: none,
 // e in row order).  MODE 0: q[row] = w . (f - A (x + Pi_p e)), the restricted
 // residual (r not stored).  MODE 1: r = f - A (x + Pi_p e).
-template <int MODE>
-__global__ __launch_bounds__(CB) void k_cpr_resid(Geo g, const double *__restrict__ A, const double *__restrict__ x,
+template <int MODE, typename T>
+__global__ __launch_bounds__(CB) void k_cpr_resid(Geo g, const T *__restrict__ A, const double *__restrict__ x,
                                                   const double *__restrict__ e, const double *__restrict__ f,
                                                   double *__restrict__ r, const double *__restrict__ w,
                                                   double *__restrict__ q)
@@ -135,10 +135,10 @@ __global__ __launch_bounds__(CB) void k_cpr_resid(Geo g, const double *__restric
                 }
                 if (e) x0 += e[row_of(g, ax, ay, az)];
             }
-            const double *a = A + aidx(slot, s * 9);
-            acc0 += a[0 * 64] * x0 + a[1 * 64] * x1 + a[2 * 64] * x2;
-            acc1 += a[3 * 64] * x0 + a[4 * 64] * x1 + a[5 * 64] * x2;
-            acc2 += a[6 * 64] * x0 + a[7 * 64] * x1 + a[8 * 64] * x2;
+            const T *a = A + aidx(slot, s * 9);
+            acc0 += (double)a[0 * 64] * x0 + (double)a[1 * 64] * x1 + (double)a[2 * 64] * x2;
+            acc1 += (double)a[3 * 64] * x0 + (double)a[4 * 64] * x1 + (double)a[5 * 64] * x2;
+            acc2 += (double)a[6 * 64] * x0 + (double)a[7 * 64] * x1 + (double)a[8 * 64] * x2;
         }
     }
     const int64_t i0 = vidx(slot, 0), i1 = vidx(slot, 1), i2 = vidx(slot, 2);
@@ -210,7 +210,8 @@ __device__ inline int64_t agg_of(const LevelGeo &F, const LevelGeo &C, int i, in
 // colour), one thread per such cell.  zero: x = 0 on entry (no reads of x);
 // xc (nullable): read every neighbour as x + xc[aggregate of the neighbour]
 // (the coarse correction not yet added to x).
-__global__ __launch_bounds__(CB) void k_mg_gs(LevelGeo L, const double *__restrict__ coef,
+template <typename T>
+__global__ __launch_bounds__(CB) void k_mg_gs(LevelGeo L, const T *__restrict__ coef,
                                               const double *__restrict__ b, double *__restrict__ x, int colour,
                                               int zero, const double *__restrict__ xc, LevelGeo C)
 {
@@ -235,14 +236,15 @@ __global__ __launch_bounds__(CB) void k_mg_gs(LevelGeo L, const double *__restri
             if (a < 0 || a >= L.nx || bb < 0 || bb >= L.ny || cc < 0 || cc >= L.nz) continue;
             double v = x[lidx(L, a, bb, cc)];
             if (xc) v += xc[agg_of(L, C, a, bb, cc)];
-            s -= coef[d * n + c] * v;
+            s -= (double)coef[d * n + c] * v;
         }
     }
-    x[c] = s / coef[3 * n + c];
+    x[c] = s / (double)coef[3 * n + c];
 }
 
 // bc[I] = sum over the fine cells of aggregate I (ascending) of (b - A x)
-__global__ __launch_bounds__(CB) void k_mg_restrict(LevelGeo F, const double *__restrict__ coef,
+template <typename T>
+__global__ __launch_bounds__(CB) void k_mg_restrict(LevelGeo F, const T *__restrict__ coef,
                                                     const double *__restrict__ b, const double *__restrict__ x,
                                                     LevelGeo C, double *__restrict__ bc)
 {
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(CB) void k_mg_restrict(LevelGeo F, const double *__
                     dir_off(d, di, dj, dk);
                     const int a = i + di, bb = j + dj, cc = k + dk;
                     if (a < 0 || a >= F.nx || bb < 0 || bb >= F.ny || cc < 0 || cc >= F.nz) continue;
-                    ax += coef[d * n + c] * x[lidx(F, a, bb, cc)];
+                    ax += (double)coef[d * n + c] * x[lidx(F, a, bb, cc)];
                 }
                 sum += b[c] - ax;
             }
@@ -340,23 +342,27 @@ __global__ __launch_bounds__(CB) void k_mg_dense(LevelGeo L, const double *__res
 }
 
 // Gauss-Jordan elimination with partial pivoting of [A | I] in one
-// workgroup; writes inv^T (inv(r, q) at invT[q * n + r]) or raises the
-// zero-pivot flag.  n <= GJ_T.
-__global__ __launch_bounds__(GJ_T) void k_mg_gauss_jordan(int n, double *__restrict__ M, double *__restrict__ invT,
+// workgroup; writes inv (row-major) or raises the zero-pivot flag.
+// n <= GJ_T.  After column c is eliminated, the left block's columns < c are
+// unit columns and the pivot row is zero there, so each step updates only
+// columns >= col; the pivot row is staged in LDS.
+__global__ __launch_bounds__(GJ_T) void k_mg_gauss_jordan(int n, double *__restrict__ M, double *__restrict__ inv,
                                                           int32_t *flags)
 {
     __shared__ double fac[GJ_T];
+    __shared__ double prow[2 * GJ_T];
     __shared__ double red_v[GJ_T / 64];
     __shared__ int red_i[GJ_T / 64];
     __shared__ int piv_s;
+    __shared__ double pv_s;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int64_t w2 = 2 * (int64_t)n;
+    const int w2 = 2 * n;
     for (int col = 0; col < n; ++col) {
         // pivot: largest |M[r][col]|, r >= col, first such row on ties
         double bv = -1.0;
         int bi = n;
         for (int r = col + t; r < n; r += GJ_T) {
-            const double v = fabs(M[r * w2 + col]);
+            const double v = fabs(M[(int64_t)r * w2 + col]);
             if (v > bv) { bv = v; bi = r; }
         }
         for (int off = 32; off > 0; off >>= 1) {
@@ -372,6 +378,7 @@ __global__ __launch_bounds__(GJ_T) void k_mg_gauss_jordan(int n, double *__restr
             for (int q = 1; q < GJ_T / 64; ++q)
                 if (red_v[q] > v || (red_v[q] == v && red_i[q] < ii)) { v = red_v[q]; ii = red_i[q]; }
             piv_s = (v > 1e-300 && ii < n) ? ii : -1;
+            pv_s = (piv_s >= 0) ? M[(int64_t)piv_s * w2 + col] : 0.0;
         }
         __syncthreads();
         const int piv = piv_s;
@@ -379,49 +386,73 @@ __global__ __launch_bounds__(GJ_T) void k_mg_gauss_jordan(int n, double *__restr
             if (t == 0) atomicOr(&flags[0], (int32_t)FLAG_PIVOT);
             return;
         }
-        if (piv != col)
-            for (int64_t q = t; q < w2; q += GJ_T) {
-                const double a = M[col * w2 + q];
-                M[col * w2 + q] = M[piv * w2 + q];
-                M[piv * w2 + q] = a;
-            }
+        // swap rows col and piv, normalise the pivot row into LDS and back
+        const double pv = pv_s;
+        for (int q = col + t; q < w2; q += GJ_T) {
+            const double a = M[(int64_t)col * w2 + q];
+            const double p = M[(int64_t)piv * w2 + q];
+            if (piv != col) M[(int64_t)piv * w2 + q] = a;
+            const double pn = p / pv;
+            prow[q] = pn;
+            M[(int64_t)col * w2 + q] = pn;
+        }
         __syncthreads();
-        const double pv = M[col * w2 + col];
+        for (int r = t; r < n; r += GJ_T) fac[r] = (r == col) ? 0.0 : M[(int64_t)r * w2 + col];
         __syncthreads();
-        for (int64_t q = t; q < w2; q += GJ_T) M[col * w2 + q] /= pv;
-        for (int r = t; r < n; r += GJ_T) fac[r] = (r == col) ? 0.0 : M[r * w2 + col];
-        __syncthreads();
-        // one wavefront per row, its lanes along the row
+        // one wavefront per row, its lanes along the row, four loads in flight
         for (int r = wv; r < n; r += GJ_T / 64) {
             if (r == col) continue;
             const double fr = fac[r];
-            for (int64_t q = lane; q < w2; q += 64) M[r * w2 + q] -= fr * M[col * w2 + q];
+            double *row = M + (int64_t)r * w2;
+            int q = col + lane;
+            for (; q + 192 < w2; q += 256) {
+                const double a0 = row[q], a1 = row[q + 64], a2 = row[q + 128], a3 = row[q + 192];
+                row[q] = a0 - fr * prow[q];
+                row[q + 64] = a1 - fr * prow[q + 64];
+                row[q + 128] = a2 - fr * prow[q + 128];
+                row[q + 192] = a3 - fr * prow[q + 192];
+            }
+            for (; q < w2; q += 64) row[q] -= fr * prow[q];
         }
         __syncthreads();
     }
     for (int64_t idx = t; idx < (int64_t)n * n; idx += GJ_T) {
         const int r = (int)(idx / n), q = (int)(idx - (int64_t)r * n);
-        invT[(int64_t)q * n + r] = M[r * w2 + n + q];
+        inv[idx] = M[(int64_t)r * w2 + n + q];
     }
 }
 
-// x = inv b on the coarsest level (one workgroup)
-__global__ __launch_bounds__(GJ_T) void k_mg_coarse(int n, const double *__restrict__ invT,
-                                                    const double *__restrict__ b, double *__restrict__ x)
+// x = inv b on the coarsest level: 16 rows per workgroup, 16 lanes per row
+// along it (coalesced row segments), lanes combined by shuffles
+constexpr int CO_ROWS = 16;
+__global__ __launch_bounds__(CB) void k_mg_coarse(int n, const double *__restrict__ inv,
+                                                  const double *__restrict__ b, double *__restrict__ x)
 {
-    for (int r = threadIdx.x; r < n; r += GJ_T) {
-        double acc = 0.0;
-        for (int q = 0; q < n; ++q) acc += invT[(int64_t)q * n + r] * b[q];
-        x[r] = acc;
+    const int l = threadIdx.x & 15;
+    const int r = blockIdx.x * CO_ROWS + (threadIdx.x >> 4);
+    double acc = 0.0;
+    if (r < n) {
+        const double *row = inv + (int64_t)r * n;
+        for (int q = l; q < n; q += 16) acc += row[q] * b[q];
     }
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    if (r < n && l == 0) x[r] = acc;
 }
 
 inline int nblk(int64_t n) { return (int)((n + CB - 1) / CB); }
+
+// FP64 -> FP32 copy
+__global__ __launch_bounds__(CB) void k_to_f32(int64_t n, const double *__restrict__ in, float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
 
 struct MgLevel {
     LevelGeo geo{1, 1, 1};
     int64_t n = 0;
     double *coef = nullptr, *b = nullptr, *x = nullptr;
+    float *coef32 = nullptr;      // FP32 form: the coefficients the cycle reads
 };
 
 struct CprImpl : PcImpl {
@@ -431,7 +462,9 @@ struct CprImpl : PcImpl {
     int variant = RSV_CPR_FPF, pre = 1, post = 1;
     double *w = nullptr;          // tile-lane, 3 per slot
     double *r = nullptr, *t = nullptr;   // tile-lane work vectors
-    double *invT = nullptr;       // coarsest inverse, transposed
+    double *inv = nullptr;        // coarsest inverse, row-major
+    float *A32 = nullptr;         // FP32 form: tile-lane FP32 copy of A for the residual products
+    bool fp32 = false;
     std::vector<MgLevel> lev;
     int64_t nbytes = 0;
 
@@ -441,8 +474,10 @@ struct CprImpl : PcImpl {
         dev_free(w);
         dev_free(r);
         dev_free(t);
-        dev_free(invT);
+        dev_free(inv);
+        dev_free(A32);
         for (auto &L : lev) {
+            dev_free(L.coef32);
             dev_free(L.coef);
             dev_free(L.b);
             dev_free(L.x);
@@ -456,11 +491,19 @@ struct CprImpl : PcImpl {
         return dev_alloc(c, (void **)p, (size_t)ndoubles * 8);
     }
 
-    rsv_status cycle(int l)
+    rsv_status cycle(int l) { return fp32 ? cycle_t<float>(l) : cycle_t<double>(l); }
+
+    template <typename T>
+    static const T *coef_of(const MgLevel &L);
+
+    template <typename T>
+    rsv_status cycle_t(int l)
     {
         MgLevel &L = lev[l];
+        const T *cf = coef_of<T>(L);
         if (l == (int)lev.size() - 1) {
-            hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(GJ_T), 0, c->stream, (int)L.n, invT, L.b, L.x);
+            hipLaunchKernelGGL(k_mg_coarse, dim3((int)((L.n + CO_ROWS - 1) / CO_ROWS)), dim3(CB), 0, c->stream,
+                               (int)L.n, (const double *)inv, L.b, L.x);
             RSV_LAUNCH(c);
             return RSV_OK;
         }
@@ -468,20 +511,20 @@ struct CprImpl : PcImpl {
         const int64_t hx = (L.geo.nx + 1) / 2;
         const int nb = nblk(hx * L.geo.ny * L.geo.nz);
         for (int s = 0; s < pre; ++s) {
-            hipLaunchKernelGGL(k_mg_gs, dim3(nb), dim3(CB), 0, c->stream, L.geo, L.coef, L.b, L.x, 0, s == 0 ? 1 : 0,
+            hipLaunchKernelGGL(k_mg_gs<T>, dim3(nb), dim3(CB), 0, c->stream, L.geo, cf, L.b, L.x, 0, s == 0 ? 1 : 0,
                                (const double *)nullptr, C.geo);
-            hipLaunchKernelGGL(k_mg_gs, dim3(nb), dim3(CB), 0, c->stream, L.geo, L.coef, L.b, L.x, 1, 0,
+            hipLaunchKernelGGL(k_mg_gs<T>, dim3(nb), dim3(CB), 0, c->stream, L.geo, cf, L.b, L.x, 1, 0,
                                (const double *)nullptr, C.geo);
         }
-        hipLaunchKernelGGL(k_mg_restrict, dim3(nblk(C.n)), dim3(CB), 0, c->stream, L.geo, L.coef, L.b, L.x, C.geo,
+        hipLaunchKernelGGL(k_mg_restrict<T>, dim3(nblk(C.n)), dim3(CB), 0, c->stream, L.geo, cf, L.b, L.x, C.geo,
                            C.b);
         RSV_LAUNCH(c);
-        rsv_status st = cycle(l + 1);
+        rsv_status st = cycle_t<T>(l + 1);
         if (st != RSV_OK) return st;
         for (int s = 0; s < post; ++s) {
-            hipLaunchKernelGGL(k_mg_gs, dim3(nb), dim3(CB), 0, c->stream, L.geo, L.coef, L.b, L.x, 1, 0,
+            hipLaunchKernelGGL(k_mg_gs<T>, dim3(nb), dim3(CB), 0, c->stream, L.geo, cf, L.b, L.x, 1, 0,
                                s == 0 ? (const double *)C.x : (const double *)nullptr, C.geo);
-            hipLaunchKernelGGL(k_mg_gs, dim3(nb), dim3(CB), 0, c->stream, L.geo, L.coef, L.b, L.x, 0, 0,
+            hipLaunchKernelGGL(k_mg_gs<T>, dim3(nb), dim3(CB), 0, c->stream, L.geo, cf, L.b, L.x, 0, 0,
                                (const double *)nullptr, C.geo);
         }
         RSV_LAUNCH(c);
@@ -499,12 +542,19 @@ struct CprImpl : PcImpl {
     {
         const Geo &g = A->g->geo;
         ProfScope ps(c, RSV_K_CPR);
-        if (mode == 0)
-            hipLaunchKernelGGL(k_cpr_resid<0>, dim3(nblk(g.nslot)), dim3(CB), 0, c->stream, g, A->d_A, x, e, f,
-                               (double *)nullptr, w, lev[0].b);
-        else
-            hipLaunchKernelGGL(k_cpr_resid<1>, dim3(nblk(g.nslot)), dim3(CB), 0, c->stream, g, A->d_A, x, e, f, r,
+        const dim3 grid(nblk(g.nslot)), blk(CB);
+        if (fp32 && mode == 0)
+            hipLaunchKernelGGL((k_cpr_resid<0, float>), grid, blk, 0, c->stream, g, (const float *)A32, x, e, f,
+                               (double *)nullptr, (const double *)w, lev[0].b);
+        else if (fp32)
+            hipLaunchKernelGGL((k_cpr_resid<1, float>), grid, blk, 0, c->stream, g, (const float *)A32, x, e, f, r,
                                (const double *)w, (double *)nullptr);
+        else if (mode == 0)
+            hipLaunchKernelGGL((k_cpr_resid<0, double>), grid, blk, 0, c->stream, g, (const double *)A->d_A, x, e, f,
+                               (double *)nullptr, (const double *)w, lev[0].b);
+        else
+            hipLaunchKernelGGL((k_cpr_resid<1, double>), grid, blk, 0, c->stream, g, (const double *)A->d_A, x, e, f,
+                               r, (const double *)w, (double *)nullptr);
         RSV_LAUNCH(c);
         return RSV_OK;
     }
@@ -568,6 +618,11 @@ struct CprImpl : PcImpl {
     }
 };
 
+template <>
+const double *CprImpl::coef_of<double>(const MgLevel &L) { return L.coef; }
+template <>
+const float *CprImpl::coef_of<float>(const MgLevel &L) { return L.coef32; }
+
 }  // namespace
 
 rsv_status cpr_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl *stage, PcImpl **out, int64_t *bad_cell)
@@ -588,6 +643,7 @@ rsv_status cpr_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl *stage, PcIm
     P->variant = p->cpr_variant;
     P->pre = p->mg_pre;
     P->post = p->mg_post;
+    P->fp32 = (p->precision == RSV_FP32);
     const Geo &g = A->g->geo;
     rsv_status s = RSV_OK;
     // levels: halve every axis longer than one cell until at most mg_coarse cells
@@ -620,7 +676,7 @@ rsv_status cpr_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl *stage, PcIm
     }
     const int64_t nco = P->lev.back().n;
     double *aug = nullptr;
-    if (s == RSV_OK) s = P->alloc(&P->invT, nco * nco);
+    if (s == RSV_OK) s = P->alloc(&P->inv, nco * nco);
     if (s == RSV_OK) s = dev_alloc(c, (void **)&aug, (size_t)(2 * nco * nco) * 8);
     if (s == RSV_OK) s = flags_reset(c);
     if (s == RSV_OK) {
@@ -636,10 +692,26 @@ rsv_status cpr_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl *stage, PcIm
         const MgLevel &Lc = P->lev.back();
         hipLaunchKernelGGL(k_mg_dense, dim3(nblk(Lc.n)), dim3(CB), 0, c->stream, Lc.geo, (const double *)Lc.coef,
                            aug);
-        hipLaunchKernelGGL(k_mg_gauss_jordan, dim3(1), dim3(GJ_T), 0, c->stream, (int)Lc.n, aug, P->invT,
+        hipLaunchKernelGGL(k_mg_gauss_jordan, dim3(1), dim3(GJ_T), 0, c->stream, (int)Lc.n, aug, P->inv,
                            c->d_flags);
+        if (P->fp32) {
+            // FP32 form: the residual products and the cycle read FP32 copies
+            const int64_t na = 63 * g.nslot;
+            P->nbytes += na * 4;
+            if ((s = dev_alloc(c, (void **)&P->A32, (size_t)na * 4)) == RSV_OK)
+                hipLaunchKernelGGL(k_to_f32, dim3(nblk(na)), dim3(CB), 0, c->stream, na, (const double *)A->d_A,
+                                   P->A32);
+            for (auto &L : P->lev) {
+                if (s != RSV_OK) break;
+                P->nbytes += 7 * L.n * 4;
+                if ((s = dev_alloc(c, (void **)&L.coef32, (size_t)(7 * L.n) * 4)) == RSV_OK)
+                    hipLaunchKernelGGL(k_to_f32, dim3(nblk(7 * L.n)), dim3(CB), 0, c->stream, 7 * L.n,
+                                       (const double *)L.coef, L.coef32);
+            }
+        }
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) s = set_err(c, RSV_ERR_HIP, std::string("CPR setup launch: ") + hipGetErrorString(e));
+        if (s == RSV_OK && e != hipSuccess)
+            s = set_err(c, RSV_ERR_HIP, std::string("CPR setup launch: ") + hipGetErrorString(e));
     }
     if (s == RSV_OK) {
         hipError_t e = hipStreamSynchronize(c->stream);
