@@ -51,6 +51,37 @@ def algorithmic_bytes(nx, ny, nz):
     }
 
 
+def cpr_fpf_algorithmic_bytes(nx, ny, nz, fp32=False, coarse=128, pre=1, post=1):
+    """Bytes the CPR-FPF kernels of one apply must move, the stage R's sweeps
+    excluded (they are counted with the sweeps): the two residual products
+    (stored blocks of A, x, f and the weights or r, the pressure vector), one
+    multigrid V-cycle (every level's stored coefficients, b and x per colour
+    sweep pair and per restriction, the coarsest level's inverse) and the
+    final combination (z read and written, t, e)."""
+    c = nx * ny * nz
+    N = 3 * c
+    ab = algorithmic_bytes(nx, ny, nz)
+    wa = 36 if fp32 else 72
+    wc = 4 if fp32 else 8
+    resid = wa * ab["nnzb"] + 24 * N + 8 * c
+    dims = [(nx, ny, nz)]
+    while dims[-1][0] * dims[-1][1] * dims[-1][2] > coarse:
+        dims.append(tuple((v + 1) // 2 if v > 1 else 1 for v in dims[-1]))
+    mg = 0
+    for l, (a, b_, c_) in enumerate(dims):
+        n = a * b_ * c_
+        if l == len(dims) - 1:
+            mg += 8 * n * n + 16 * n
+            break
+        nzl = n + 2 * ((a - 1) * b_ * c_ + a * (b_ - 1) * c_ + a * b_ * (c_ - 1))
+        nc = dims[l + 1][0] * dims[l + 1][1] * dims[l + 1][2]
+        sweep = wc * nzl + 24 * n
+        mg += pre * sweep + (wc * nzl + 16 * n + 8 * nc) + post * sweep + 8 * nc
+    combine = 24 * N + 8 * c
+    return {"resid": resid, "mg": mg, "combine": combine, "apply": 2 * resid + mg + combine,
+            "levels": len(dims)}
+
+
 def ras_algorithmic_bytes(nx, ny, nz, parts, ov):
     """Bytes of the local sweeps of RAS per launch: the stored blocks of every
     local matrix (couplings inside Omega_s) and the vector passes over every
@@ -403,6 +434,7 @@ def main():
         "gmres_cpr_fpf_fp32": (rsv.GMRES, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_RAS, precision=rsv.FP32, **ras)),
         "gmres_cpr_fpf_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_BILU0, precision=rsv.FP32)),
     }
+    forms_all["gmres_cpr_fpf_bilu0_fp32_dcgs2"] = forms_all["gmres_cpr_fpf_bilu0_fp32"]
     # the same GMRES forms with the delayed second Gram-Schmidt pass
     for f in ("gmres_ras64", "gmres_bilu0", "gmres_ras64_fp32"):
         forms_all[f + "_dcgs2"] = forms_all[f]
@@ -539,6 +571,16 @@ def main():
         tab = {k: {"avg_us": 1e3 * kms[k] / kcnt[k], "launches": kcnt[k], "total_ms": kms[k],
                    "GBps": (ab[k] / (kms[k] / kcnt[k] * 1e-3) / 1e9) if k in ab and k != "ilu_apply" else None}
                for k in rsv.K_NAMES if kcnt[k] > 0}
+        if pk.get("type") == rsv.PC_CPR and kcnt["cpr"] > 0:
+            # CPR-FPF records four timed scopes per apply: the restricted
+            # residual, the V-cycle, the residual and the combination
+            cb = cpr_fpf_algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz, fp32=pk.get("precision") == rsv.FP32)
+            napply = kcnt["cpr"] // 4
+            ms_apply = kms["cpr"] / max(napply, 1)
+            tab["cpr"].update({"applies": napply, "ms_per_apply": ms_apply,
+                               "algorithmic_bytes_per_apply": cb["apply"], "mg_levels": cb["levels"],
+                               "GBps": cb["apply"] / (ms_apply * 1e-3) / 1e9,
+                               "frac": round(cb["apply"] / (ms_apply * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
         return kms, kcnt, ab, tab
 
     roofline = None
