@@ -54,6 +54,8 @@ def lib():
         "orc_ras_setup": ([vp, i32, i32, i32, i32, i32, i32, i32, P(vp), P(i64)], ctypes.c_int),
         "orc_ras_setup_k": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, P(vp), P(i64)], ctypes.c_int),
         "orc_iluk": ([vp, i32, P(vp), P(i64)], ctypes.c_int),
+        "orc_ilut": ([vp, i32, dbl, P(vp), P(i64)], ctypes.c_int),
+        "orc_ras_setup_ilut": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, dbl, P(vp), P(i64)], ctypes.c_int),
         "orc_iluk_pattern": ([vp, i32, vp, vp, vp, i64], ctypes.c_int),
         "orc_ras_free": ([vp], None),
         "orc_ras_apply": ([vp, vp, vp], ctypes.c_int),
@@ -173,10 +175,14 @@ def iluk_pattern(A: BCSR, k):
 
 
 class ILU:
-    def __init__(self, A: BCSR, level=0):
+    def __init__(self, A: BCSR, level=0, ilut=None):
+        """ILU(level) by levels of fill, or ILUT(p, tol) when ilut = (p, tol)."""
         h = ctypes.c_void_p()
         bad = ctypes.c_int64(-1)
-        rc = lib().orc_iluk(A.h, level, ctypes.byref(h), ctypes.byref(bad))
+        if ilut is not None:
+            rc = lib().orc_ilut(A.h, int(ilut[0]), float(ilut[1]), ctypes.byref(h), ctypes.byref(bad))
+        else:
+            rc = lib().orc_iluk(A.h, level, ctypes.byref(h), ctypes.byref(bad))
         if rc != OK:
             e = OracleError(rc, f"ilu0 bad_cell={bad.value}")
             e.bad_cell = bad.value
@@ -217,12 +223,18 @@ class ILU:
 
 
 class RAS:
-    def __init__(self, A: BCSR, dims, parts, overlap=1, level=0):
+    def __init__(self, A: BCSR, dims, parts, overlap=1, level=0, ilut=None):
+        """Local solvers ILU(level), or ILUT(p, tol) when ilut = (p, tol)."""
         h = ctypes.c_void_p()
         bad = ctypes.c_int64(-1)
         nx, ny, nz = dims
         px, py, pz = parts
-        rc = lib().orc_ras_setup_k(A.h, nx, ny, nz, px, py, pz, overlap, level, ctypes.byref(h), ctypes.byref(bad))
+        if ilut is not None:
+            rc = lib().orc_ras_setup_ilut(A.h, nx, ny, nz, px, py, pz, overlap, int(ilut[0]), float(ilut[1]),
+                                          ctypes.byref(h), ctypes.byref(bad))
+        else:
+            rc = lib().orc_ras_setup_k(A.h, nx, ny, nz, px, py, pz, overlap, level, ctypes.byref(h),
+                                       ctypes.byref(bad))
         if rc != OK:
             e = OracleError(rc, f"ras_setup bad_cell={bad.value}")
             e.bad_cell = bad.value

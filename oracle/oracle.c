@@ -318,6 +318,41 @@ int orc_ilu0(const orc_bcsr *A, orc_ilu **out, int64_t *bad_cell)
     return ilu_numeric(A, out, bad_cell);
 }
 
+/* an orc_ilu around finished factors (L strict lower, U upper with its
+ * diagonal; the struct takes LU over): the diagonal positions and U_ii^-1 */
+int orc_ilu_wrap(orc_bcsr *LU, orc_ilu **out, int64_t *bad_cell)
+{
+    if (!LU || !out) return ORC_ERR_ARG;
+    if (bad_cell) *bad_cell = -1;
+    const int64_t n = LU->n;
+    orc_ilu *F = (orc_ilu *)calloc(1, sizeof(orc_ilu));
+    if (!F) {
+        orc_bcsr_free(LU);
+        return ORC_ERR_OOM;
+    }
+    F->LU = LU;
+    F->diag = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    F->dinv = (double *)malloc((size_t)(n > 0 ? n : 1) * 9 * sizeof(double));
+    if (!F->diag || !F->dinv) {
+        orc_ilu_free(F);
+        return ORC_ERR_OOM;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        F->diag[i] = -1;
+        for (int64_t p = LU->rowptr[i]; p < LU->rowptr[i + 1]; ++p)
+            if (LU->col[p] == i) F->diag[i] = p;
+        if (F->diag[i] < 0 || orc_inv3(LU->val + 9 * F->diag[i], F->dinv + 9 * i) != ORC_OK) {
+            if (bad_cell) *bad_cell = i;
+            orc_ilu_free(F);
+            return ORC_ERR_ZERO_PIVOT;
+        }
+    }
+    *out = F;
+    return ORC_OK;
+}
+
+orc_bcsr *orc_bcsr_new(int64_t n, int64_t nnzb) { return bcsr_alloc(n, nnzb); }
+
 /* Level-of-fill pattern of ILU(k) (Saad, Iterative Methods for Sparse Linear
  * Systems, 2nd ed., sec. 10.3.3): the entries of A have level 0; eliminating
  * with row m < i gives position (i, j), j > m, the level lev(i,m) + lev(m,j)
@@ -562,9 +597,29 @@ int orc_ras_setup(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
     return orc_ras_setup_k(A, nx, ny, nz, px, py, pz, overlap, 0, out, bad_cell);
 }
 
+/* the local solver of RAS: ILU(level) (kind 0) or ILUT(p, tol) (kind 1) */
+static int ras_setup(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz, int32_t px, int32_t py, int32_t pz,
+                     int32_t overlap, int kind, int32_t level, int32_t p, double tol, orc_ras **out,
+                     int64_t *bad_cell);
+
 int orc_ras_setup_k(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
                     int32_t px, int32_t py, int32_t pz, int32_t overlap, int32_t level,
                     orc_ras **out, int64_t *bad_cell)
+{
+    return ras_setup(A, nx, ny, nz, px, py, pz, overlap, 0, level, 0, 0.0, out, bad_cell);
+}
+
+int orc_ras_setup_ilut(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
+                       int32_t px, int32_t py, int32_t pz, int32_t overlap, int32_t p, double tol,
+                       orc_ras **out, int64_t *bad_cell)
+{
+    if (!(tol >= 0.0)) return ORC_ERR_ARG;
+    return ras_setup(A, nx, ny, nz, px, py, pz, overlap, 1, 0, p, tol, out, bad_cell);
+}
+
+static int ras_setup(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz, int32_t px, int32_t py, int32_t pz,
+                     int32_t overlap, int kind, int32_t level, int32_t p, double tol, orc_ras **out,
+                     int64_t *bad_cell)
 {
     if (!A || !out || px < 1 || py < 1 || pz < 1 || overlap < 0 || level < 0) return ORC_ERR_ARG;
     if (px > nx || py > ny || pz > nz) return ORC_ERR_ARG;
@@ -665,7 +720,7 @@ int orc_ras_setup_k(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
         }
         As->rowptr[m] = pos;
         int64_t bad = -1;
-        rc = orc_iluk(As, level, &R->local[s], &bad);
+        rc = (kind == 0) ? orc_iluk(As, level, &R->local[s], &bad) : orc_ilut(As, p, tol, &R->local[s], &bad);
         if (rc != ORC_OK && bad_cell) *bad_cell = (bad >= 0) ? cs[bad] : -1;
         orc_bcsr_free(As);
         for (int64_t q = 0; q < m; ++q) g2l[cs[q]] = -1;

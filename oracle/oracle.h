@@ -87,6 +87,12 @@ int  orc_iluk(const orc_bcsr *A, int32_t k, orc_ilu **out, int64_t *bad_cell);
 /* the level-k pattern (rowptr n+1, col and level nnzb entries when nnzb <= cap); returns nnzb */
 int  orc_iluk_pattern(const orc_bcsr *A, int32_t k, int64_t *rowptr, int64_t *col, int64_t *level, int64_t cap);
 int  orc_ilu_apply_f32(void *F, const double *r, double *z);/* FP32 factors + FP32 sweeps */
+/* ILUT(p, tol) with 3x3 blocks (ilut.c); p < 0: per row, as many blocks in
+ * each triangle as that triangle of A's row holds */
+int  orc_ilut(const orc_bcsr *A, int32_t p, double tol, orc_ilu **out, int64_t *bad_cell);
+/* wrap finished factors (takes LU over), and a zeroed block CSR */
+int  orc_ilu_wrap(orc_bcsr *LU, orc_ilu **out, int64_t *bad_cell);
+orc_bcsr *orc_bcsr_new(int64_t n, int64_t nnzb);
 
 /* ---- RAS ---- */
 typedef struct orc_ras orc_ras;
@@ -97,6 +103,10 @@ int  orc_ras_setup(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
 int  orc_ras_setup_k(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
                      int32_t px, int32_t py, int32_t pz, int32_t overlap, int32_t level,
                      orc_ras **out, int64_t *bad_cell);
+/* the same with ILUT(p, tol) local solvers */
+int  orc_ras_setup_ilut(const orc_bcsr *A, int32_t nx, int32_t ny, int32_t nz,
+                        int32_t px, int32_t py, int32_t pz, int32_t overlap, int32_t p, double tol,
+                        orc_ras **out, int64_t *bad_cell);
 void orc_ras_free(orc_ras *R);
 int  orc_ras_apply(void *R, const double *r, double *z);
 int64_t orc_ras_nsub(const orc_ras *R);

@@ -44,7 +44,7 @@ def build_gen():
 
 def build_oracle():
     d = os.path.join(ROOT, "oracle")
-    srcs = [s for s in ("oracle.c", "unet.c", "hsfc.c", "scalar.c", "mg.c", "cpr.c") if os.path.exists(os.path.join(d, s))]
+    srcs = [s for s in ("oracle.c", "unet.c", "hsfc.c", "scalar.c", "mg.c", "cpr.c", "ilut.c") if os.path.exists(os.path.join(d, s))]
     _run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall", "-o", "liboracle.so", *srcs, "-lm"], d)
 
 

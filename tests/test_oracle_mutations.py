@@ -18,6 +18,7 @@ HP = "tests/test_oracle_hsfc_pins.py"
 SP = "tests/test_oracle_scalar_pins.py"
 KP = "tests/test_oracle_iluk_pins.py"
 CP = "tests/test_oracle_cpr_pins.py"
+TP = "tests/test_oracle_ilut_pins.py"
 
 # (id, file, text in the oracle, replacement, pins that must fail)
 MUTATIONS = [
@@ -77,10 +78,20 @@ MUTATIONS = [
     ("cpr_pressure_row_not_column", "cpr.c", "val[p] = w[0] * blk[0] + w[1] * blk[3] + w[2] * blk[6];",
      "val[p] = w[0] * blk[0] + w[1] * blk[1] + w[2] * blk[2];",
      [CP + "::test_pressure_matrix_is_the_restricted_decoupled_matrix"]),
+    ("ilut_threshold_not_squared", "ilut.c", "const double thr = (tol * tol) * nrm2;", "const double thr = tol * nrm2;",
+     [TP + "::test_first_two_rows_by_hand"]),
+    ("ilut_keeps_the_smallest", "ilut.c", "if (vb > va || (vb == va && cand[b] < cand[a])) ++rank;",
+     "if (vb < va || (vb == va && cand[b] < cand[a])) ++rank;", [TP + "::test_first_two_rows_by_hand"]),
+    ("ilut_update_sign", "ilut.c", "w[9 * j + e] = w[9 * j + e] - prod[e];", "w[9 * j + e] = w[9 * j + e] + prod[e];",
+     [TP + "::test_zero_tolerance_is_the_exact_lu"]),
+    ("ilut_no_drop_right_of_i", "ilut.c", "if (j > i && present[j] && !(fro2(w + 9 * j) < thr)) cand[m++] = j;",
+     "if (j > i && present[j]) cand[m++] = j;", [TP + "::test_kept_blocks_pass_the_drop_test_and_the_count"]),
+    ("ilut_l_not_scaled", "ilut.c", "memcpy(w + 9 * k, wk, sizeof(wk));", "",
+     [TP + "::test_zero_tolerance_is_the_exact_lu"]),
 ]
 
 
-C_SOURCES = ("oracle.c", "unet.c", "hsfc.c", "scalar.c", "mg.c", "cpr.c")
+C_SOURCES = ("oracle.c", "unet.c", "hsfc.c", "scalar.c", "mg.c", "cpr.c", "ilut.c")
 
 
 def _build(tmp, mutation=None):
