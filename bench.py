@@ -425,6 +425,8 @@ def main():
         "gmres_bilu0_fp32": (rsv.GMRES, dict(type=rsv.PC_BILU0, precision=rsv.FP32)),
         # RAS with ILU(1) local solvers (the RAS parameters' iluk_level 1)
         "gmres_ras64_iluk1": (rsv.GMRES, dict(type=rsv.PC_RAS, iluk_level=1, **ras)),
+        # RAS with ILUT(-1, 1e-3) local solvers (the RAS parameters' ILUT defaults)
+        "gmres_ras64_ilut": (rsv.GMRES, dict(type=rsv.PC_RAS, local_solver=rsv.LOCAL_ILUT, **ras)),
         # CPR-FPF two-stage preconditioners (stage R = RAS(4x4x4) or BILU0,
         # pressure stage = one aggregation-multigrid V-cycle, no decoupling)
         "gmres_cpr_fpf": (rsv.GMRES, dict(type=rsv.PC_CPR, cpr_stage=rsv.PC_RAS, **ras)),

@@ -88,6 +88,9 @@ typedef enum { RSV_DECOUPLE_NONE = 0, RSV_DECOUPLE_QUASI_IMPES = 1, RSV_DECOUPLE
 
 typedef enum { RSV_FP64 = 0, RSV_FP32 = 1 } rsv_precision;
 
+/* Local ILU of BILU0 and RAS (the RAS parameters' solver: ILUK or ILUT). */
+typedef enum { RSV_LOCAL_ILUK = 0, RSV_LOCAL_ILUT = 1 } rsv_local_solver;
+
 typedef enum { RSV_GMRES = 0, RSV_BICGSTAB = 1, RSV_FGMRES = 2 } rsv_method;
 
 /* Orthogonalisation of the GMRES Arnoldi vectors.  RSV_CGS2: classical
@@ -149,7 +152,21 @@ typedef struct rsv_pc_params {
     int32_t mg_pre;      /* pre-smoothing sweeps, 1..8 (default 1) */
     int32_t mg_post;     /* post-smoothing sweeps, 1..8 (default 1) */
     int32_t mg_coarse;   /* largest coarsest level, 1..1024 cells (default 128) */
-    int32_t reserved[3];
+    /* Local solver of BILU0 / RAS on 3x3-block matrices (the RAS parameters'
+     * solver field): RSV_LOCAL_ILUK (default; ILU(iluk_level)) or
+     * RSV_LOCAL_ILUT, threshold ILU with 3x3 blocks: row by row, the blocks
+     * left of the diagonal are eliminated in ascending order and a block B of
+     * the work row is dropped when |B|_F^2 < ilut_tol^2 x (sum of |A_ij|_F^2
+     * over A's row); of the rest, the ilut_p largest on each side are kept
+     * (ilut_p = -1: as many as A's row holds on that side; at most 32).
+     * FP64 factors; one wavefront per subdomain factors on the device with
+     * the work row in LDS (a subdomain's band, nx_s*ny_s cells, must fit:
+     * else RSV_ERR_ARG), then the ILU(k) apply runs on the resulting
+     * pattern.  A row whose work list outgrows 512 blocks gives RSV_ERR_ARG. */
+    int32_t local_solver;/* rsv_local_solver */
+    int32_t ilut_p;      /* default -1 */
+    double ilut_tol;     /* default 1e-3 */
+    int32_t reserved[4];
 } rsv_pc_params;
 
 /* Solver parameters; mirrors SOLVER (rtol, atol, maxit, restart). */

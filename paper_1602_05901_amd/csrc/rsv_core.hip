@@ -429,6 +429,9 @@ void rsv_pc_params_default(rsv_pc_params *p)
     p->mg_pre = 1;
     p->mg_post = 1;
     p->mg_coarse = 128;
+    p->local_solver = RSV_LOCAL_ILUK;
+    p->ilut_p = -1;
+    p->ilut_tol = 1e-3;
 }
 
 void rsv_solver_params_default(rsv_solver_params *p)

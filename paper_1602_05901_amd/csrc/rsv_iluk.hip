@@ -22,9 +22,15 @@
 // cofactors), and for an apply the forward sweep y_i = r_i - sum L_ij y_j and
 // the backward sweep z_i = U_ii^-1 (y_i - sum U_ij z_j), the owner writing
 // z_i into the tile-lane result.
+//
+// ILUT(p, tol) local solvers (the RAS parameters' ILUT solver) share the
+// subdomains and the apply; their factorisation and schedules run on the
+// device (see the ILUT section below).
 #include "rsv_internal.h"
 
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
 #include <new>
 #include <thread>
 #include <vector>
@@ -36,7 +42,8 @@ constexpr int KT = 256;   // threads of a subdomain's workgroup
 struct IlukDev {
     int64_t nrow;
     const int32_t *gslot, *own;          // per row: tile-lane slot of its cell; 1 if the subdomain owns it
-    const int64_t *lptr, *uptr;          // per row: ranges in the L / U position arrays
+    const int64_t *lptr, *uptr;          // per row: first entry in the L / U position arrays
+    const int64_t *lend, *uend;          // per row: one past its last entry (ILU(k): lptr + 1, uptr + 1)
     const int32_t *lcol, *ucol;          // column = row index (global across subdomains)
     const int64_t *lsrc, *usrc;          // A-entry base index of a stencil position, -1 for fill
     double *lval, *uval, *dval, *dinv;   // 9 per position / row, row-major blocks
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(KT) void k_iluk_apply(IlukDev d, const double *__re
                 const int32_t i = d.fo[t];
                 const int64_t sl = d.gslot[i];
                 double v0 = r[vidx(sl, 0)], v1 = r[vidx(sl, 1)], v2 = r[vidx(sl, 2)];
-                for (int64_t p = d.lptr[i]; p < d.lptr[i + 1]; ++p) {
+                for (int64_t p = d.lptr[i]; p < d.lend[i]; ++p) {
                     const double *L = d.lval + 9 * p, *yk = d.y + 3 * (int64_t)d.lcol[p];
                     const double y0 = yk[0], y1 = yk[1], y2 = yk[2];
                     v0 -= L[0] * y0 + L[1] * y1 + L[2] * y2;
@@ -158,7 +165,7 @@ __global__ __launch_bounds__(KT) void k_iluk_apply(IlukDev d, const double *__re
             for (int64_t t = bl[lv] + threadIdx.x; t < bl[lv + 1]; t += KT) {
                 const int32_t i = d.bo[t];
                 double v0 = d.y[3 * (int64_t)i], v1 = d.y[3 * (int64_t)i + 1], v2 = d.y[3 * (int64_t)i + 2];
-                for (int64_t q = d.uptr[i]; q < d.uptr[i + 1]; ++q) {
+                for (int64_t q = d.uptr[i]; q < d.uend[i]; ++q) {
                     const double *U = d.uval + 9 * q, *zj = d.y + 3 * (int64_t)d.ucol[q];
                     const double z0 = zj[0], z1 = zj[1], z2 = zj[2];
                     v0 -= U[0] * z0 + U[1] * z1 + U[2] * z2;
@@ -184,10 +191,444 @@ __global__ __launch_bounds__(KT) void k_iluk_apply(IlukDev d, const double *__re
     }
 }
 
+// ---------------------------------------------------------------- ILUT(p, tol)
+//
+// Threshold ILU with 3x3 blocks (the RAS parameters' ILUT solver, ilut_p and
+// ilut_tol), Saad's row-wise ILUT with blocks measured by their squared
+// Frobenius norm: row i starts as block row i of A with the threshold
+// thr = tol^2 * sum |A_ij|^2; its positions left of i are eliminated in
+// ascending order (w_k <- w_k U_kk^-1, dropped when |w_k|^2 < thr, else
+// w <- w - w_k U_k,:), fill entering as it is created; the positions right
+// of i below thr are dropped; the p largest left and right of i are kept
+// (ties: smaller column first; p < 0: as many as A's row holds on that
+// side); U_ii^-1 by LU with partial pivoting.
+//
+// The pattern depends on the values, so everything runs on the device: one
+// wavefront per subdomain factors its rows in order.  The work row lives in
+// LDS: a map from column (mod the window length 2 bw + 1, bw = the local
+// band width) to a slot of a small block buffer, a sorted list of the
+// positions still to eliminate, and per slot the block and whether it was
+// dropped.  The floating-point steps run in the oracle's order without
+// contraction (products sum their three terms left to right, norms their
+// nine squares in order, the pivot inverse is the same textbook LU), so the
+// drop and keep decisions are the oracle's.  Afterwards the same wavefront
+// computes the dependency levels (forward from the kept L columns, backward
+// from the kept U columns) and buckets its rows by level for the apply of
+// the ILU(k) path (k_iluk_apply).
+
+constexpr int TW = 64;            // one wavefront per subdomain
+constexpr int T_NBUF = 512;       // blocks of the work row
+constexpr int T_LCAP = 512;       // positions left of i awaiting elimination
+constexpr int T_CAP_MAX = 32;     // largest p
+constexpr int FLAG_ILUT_CAP = 16; // a row needed more than T_NBUF / T_LCAP entries
+
+struct IlutDev {
+    int64_t nrow;
+    const int32_t *acol;          // [nrow][7] global row of the stencil column, -1 outside Omega_s
+    const int64_t *asrc;          // [nrow][7] A entry base index of that block
+    const int64_t *sub_base;      // nsub + 1
+    const int32_t *sub_w;         // window length per subdomain
+    const int32_t *own;           // row of the cell << 1 | owner bit
+    int32_t p, capl, capu;
+    double tol2;
+    const int64_t *lptr, *uptr;   // row capacity starts
+    int64_t *lend, *uend;
+    int32_t *lcol, *ucol;
+    double *lval, *uval, *dval, *dinv;
+    int32_t *flev, *blev;
+    int32_t *fo, *bo;
+    int64_t *fl, *bl;             // per subdomain boundaries at fl_off[s] = base[s] + s
+    int32_t *fl_cnt, *bl_cnt;
+    int64_t *cnt;                 // scratch, same layout as fl
+};
+
+__device__ inline double fro2_blk(const double *a)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int e = 0; e < 9; ++e) s = s + a[e] * a[e];
+    return s;
+}
+
+__device__ inline void blk_mul_t(const double *a, const double *b, double *c)   // c = a b
+{
+#pragma clang fp contract(off)
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+            double t = a[3 * p] * b[q];
+            t = t + a[3 * p + 1] * b[3 + q];
+            t = t + a[3 * p + 2] * b[6 + q];
+            c[3 * p + q] = t;
+        }
+}
+
+__device__ inline double norm1_blk(const double *a)
+{
+    double best = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        double s = fabs(a[q]) + fabs(a[3 + q]);
+        s = s + fabs(a[6 + q]);
+        if (s > best) best = s;
+    }
+    return best;
+}
+
+// inverse by LU with partial pivoting, solving for the three unit vectors;
+// a pivot |u_pp| <= 1e-300 or a 1-norm condition above 1e14 is singular
+__device__ inline bool inv3_lu(const double *a, double *o)
+{
+#pragma clang fp contract(off)
+    double lu[9];
+    int perm[3] = {0, 1, 2};
+    for (int e = 0; e < 9; ++e) lu[e] = a[e];
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(lu[3 * r + c]) > fabs(lu[3 * piv + c])) piv = r;
+        if (!(fabs(lu[3 * piv + c]) > 1e-300)) return false;
+        if (piv != c) {
+            for (int q = 0; q < 3; ++q) {
+                const double t = lu[3 * c + q];
+                lu[3 * c + q] = lu[3 * piv + q];
+                lu[3 * piv + q] = t;
+            }
+            const int t = perm[c];
+            perm[c] = perm[piv];
+            perm[piv] = t;
+        }
+        for (int r = c + 1; r < 3; ++r) {
+            const double f = lu[3 * r + c] / lu[3 * c + c];
+            lu[3 * r + c] = f;
+            for (int q = c + 1; q < 3; ++q) lu[3 * r + q] = lu[3 * r + q] - f * lu[3 * c + q];
+        }
+    }
+    for (int col = 0; col < 3; ++col) {
+        double y[3];
+        for (int r = 0; r < 3; ++r) {
+            double v = (perm[r] == col) ? 1.0 : 0.0;
+            for (int t = 0; t < r; ++t) v = v - lu[3 * r + t] * y[t];
+            y[r] = v;
+        }
+        for (int r = 2; r >= 0; --r) {
+            double v = y[r];
+            for (int t = r + 1; t < 3; ++t) v = v - lu[3 * r + t] * o[3 * t + col];
+            o[3 * r + col] = v / lu[3 * r + r];
+        }
+    }
+    return norm1_blk(a) * norm1_blk(o) <= 1e14;
+}
+
+// wavefront-wide inclusive prefix sum of v
+__device__ inline int64_t wave_scan(int64_t v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// rows of [g0, g1) bucketed by level lev[] (nlev levels): bounds and order
+__device__ void bucket_rows(int64_t g0, int64_t g1, const int32_t *lev, int nlev, int64_t *cnt, int64_t *bounds,
+                            int32_t *ord)
+{
+    const int lane = threadIdx.x;
+    for (int l = lane; l <= nlev; l += TW) cnt[l] = 0;
+    __syncthreads();
+    for (int64_t g = g0 + lane; g < g1; g += TW) atomicAdd((unsigned long long *)&cnt[lev[g]], 1ull);
+    __syncthreads();
+    // exclusive scan of cnt[0..nlev) into bounds, offset g0
+    int64_t carry = 0;
+    for (int l0 = 0; l0 < nlev; l0 += TW) {
+        const int l = l0 + lane;
+        const int64_t v = (l < nlev) ? cnt[l] : 0;
+        const int64_t inc = wave_scan(v);
+        if (l < nlev) bounds[l] = g0 + carry + inc - v;
+        carry += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) bounds[nlev] = g0 + carry;
+    __syncthreads();
+    for (int l = lane; l < nlev; l += TW) cnt[l] = bounds[l];
+    __syncthreads();
+    for (int64_t g = g0 + lane; g < g1; g += TW) {
+        const int64_t at = (int64_t)atomicAdd((unsigned long long *)&cnt[lev[g]], 1ull);
+        ord[at] = (int32_t)g;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(TW) void k_ilut_factor(IlutDev t, const double *__restrict__ A, int32_t *flags)
+{
+#pragma clang fp contract(off)
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int s = blockIdx.x, lane = threadIdx.x;
+    const int64_t g0 = t.sub_base[s], g1 = t.sub_base[s + 1];
+    const int32_t W = t.sub_w[s];
+    double *wbuf = (double *)smem;                       // [T_NBUF][9]
+    double *cf2 = wbuf + 9 * T_NBUF;                     // [T_NBUF] squared norms
+    int32_t *touched = (int32_t *)(cf2 + T_NBUF);        // [T_NBUF] column of each slot
+    int32_t *llist = touched + T_NBUF;                   // [T_LCAP]
+    int32_t *tslot = llist + T_LCAP;                     // [T_CAP_MAX]
+    int32_t *outpos = tslot + T_CAP_MAX;                 // [T_NBUF] output position of a kept slot, -1 none
+    unsigned char *cls = (unsigned char *)(outpos + T_NBUF);   // [T_NBUF] 0 none, 1 L, 2 U, 3 diagonal
+    unsigned char *dropped = cls + T_NBUF;               // [T_NBUF]
+    int16_t *wmap = (int16_t *)(dropped + T_NBUF);       // [W]
+    __shared__ double wk[9], thr_s;
+    __shared__ int nbuf, nll, pos_s, keep_s, nu_s, err_s, nla_s, nua_s, maxf_s, nkl_s, nku_s, diag_s;
+    __shared__ int64_t q0_s;
+
+    for (int q = lane; q < W; q += TW) wmap[q] = -1;
+    if (lane == 0) { err_s = 0; maxf_s = 0; }
+    __syncthreads();
+    for (int64_t g = g0; g < g1; ++g) {
+        // the row of A: slots 0.. in column (= stencil slot) order
+        if (lane == 0) {
+            nbuf = 0;
+            nll = 0;
+            int nla = 0, nua = 0;
+            for (int st = 0; st < 7; ++st) {
+                const int32_t c = t.acol[7 * g + st];
+                if (c < 0) continue;
+                const int sl = nbuf++;
+                touched[sl] = c;
+                dropped[sl] = 0;
+                wmap[c % W] = (int16_t)sl;
+                if (c < g) { llist[nll++] = c; ++nla; }
+                if (c > g) ++nua;
+            }
+            nla_s = nla;
+            nua_s = nua;
+        }
+        __syncthreads();
+        for (int it = lane; it < 63; it += TW) {
+            const int st = it / 9, e = it - 9 * (it / 9);
+            const int32_t c = t.acol[7 * g + st];
+            if (c >= 0) wbuf[9 * wmap[c % W] + e] = A[t.asrc[7 * g + st] + 64 * e];
+        }
+        __syncthreads();
+        if (lane == 0) {
+            double nrm2 = 0.0;
+            for (int sl = 0; sl < nbuf; ++sl) nrm2 = nrm2 + fro2_blk(wbuf + 9 * sl);
+            thr_s = t.tol2 * nrm2;
+            pos_s = 0;
+        }
+        __syncthreads();
+        // elimination of the positions left of g in ascending order
+        for (;;) {
+            if (pos_s >= nll || err_s) break;
+            if (lane == 0) {
+                const int32_t k = llist[pos_s];
+                const int sk = wmap[k % W];
+                double v[9];
+                blk_mul_t(wbuf + 9 * sk, t.dinv + 9 * (int64_t)k, v);
+                if (fro2_blk(v) < thr_s) {
+                    dropped[sk] = 1;
+                    keep_s = 0;
+                } else {
+                    for (int e = 0; e < 9; ++e) { wbuf[9 * sk + e] = v[e]; wk[e] = v[e]; }
+                    keep_s = 1;
+                    const int64_t q0 = t.uptr[k], q1 = t.uend[k];
+                    q0_s = q0;
+                    nu_s = (int)(q1 - q0);
+                    for (int64_t q = q0; q < q1; ++q) {
+                        const int32_t j = t.ucol[q];
+                        int sl = wmap[j % W];
+                        if (sl < 0) {
+                            if (nbuf == T_NBUF) { err_s = 1; break; }
+                            sl = nbuf++;
+                            touched[sl] = j;
+                            dropped[sl] = 0;
+                            for (int e = 0; e < 9; ++e) wbuf[9 * sl + e] = 0.0;
+                            wmap[j % W] = (int16_t)sl;
+                            if (j < g) {
+                                if (nll == T_LCAP) { err_s = 1; break; }
+                                int at = nll++;
+                                while (at > pos_s + 1 && llist[at - 1] > j) { llist[at] = llist[at - 1]; --at; }
+                                llist[at] = j;
+                            }
+                        }
+                        tslot[q - q0] = sl;
+                    }
+                }
+                pos_s = pos_s + 1;
+            }
+            __syncthreads();
+            if (keep_s && !err_s) {
+                for (int it = lane; it < 9 * nu_s; it += TW) {
+                    const int qq = it / 9, e = it - 9 * (it / 9), pp = e / 3, q3 = e - 3 * (e / 3);
+                    const double *U = t.uval + 9 * (q0_s + qq);
+                    double sacc = wk[3 * pp] * U[q3];
+                    sacc = sacc + wk[3 * pp + 1] * U[3 + q3];
+                    sacc = sacc + wk[3 * pp + 2] * U[6 + q3];
+                    double *tgt = wbuf + 9 * tslot[qq] + e;
+                    *tgt = *tgt - sacc;
+                }
+            }
+            __syncthreads();
+        }
+        if (err_s) break;
+        // classify the slots, then keep the largest of each side
+        for (int sl = lane; sl < nbuf; sl += TW) {
+            const int32_t c = touched[sl];
+            const double f2 = fro2_blk(wbuf + 9 * sl);
+            cf2[sl] = f2;
+            unsigned char k = 0;
+            if (c == g) k = 3;
+            else if (!dropped[sl] && c < g) k = 1;
+            else if (!dropped[sl] && c > g && !(f2 < thr_s)) k = 2;
+            cls[sl] = k;
+            outpos[sl] = -1;
+        }
+        __syncthreads();
+        {
+            const int pl = t.p < 0 ? nla_s : t.p, pu = t.p < 0 ? nua_s : t.p;
+            // rank by size within the side (outpos holds it until the cut)
+            for (int a = lane; a < nbuf; a += TW) {
+                const int ka = cls[a];
+                if (ka == 1 || ka == 2) {
+                    int rank = 0;
+                    for (int b = 0; b < nbuf; ++b)
+                        if (b != a && cls[b] == ka &&
+                            (cf2[b] > cf2[a] || (cf2[b] == cf2[a] && touched[b] < touched[a])))
+                            ++rank;
+                    outpos[a] = rank;
+                }
+            }
+            __syncthreads();
+            for (int a = lane; a < nbuf; a += TW) {
+                const int ka = cls[a];
+                if ((ka == 1 && outpos[a] >= pl) || (ka == 2 && outpos[a] >= pu)) cls[a] = 0;
+            }
+            __syncthreads();
+            for (int a = lane; a < nbuf; a += TW) {
+                const int ka = cls[a];
+                if (ka == 1 || ka == 2) {
+                    int r = 0;
+                    for (int b = 0; b < nbuf; ++b)
+                        if (cls[b] == ka && touched[b] < touched[a]) ++r;
+                    outpos[a] = r;
+                }
+                if (ka == 3) diag_s = a;
+            }
+            __syncthreads();
+            if (lane == 0) {
+                int nkl = 0, nku = 0;
+                for (int a = 0; a < nbuf; ++a) {
+                    if (cls[a] == 1) ++nkl;
+                    if (cls[a] == 2) ++nku;
+                }
+                nkl_s = nkl;
+                nku_s = nku;
+            }
+            __syncthreads();
+            // write the kept blocks in ascending column order
+            for (int it = lane; it < 9 * nbuf; it += TW) {
+                const int a = it / 9, e = it - 9 * (it / 9);
+                const int ka = cls[a];
+                if (ka == 1) {
+                    const int64_t q = t.lptr[g] + outpos[a];
+                    t.lval[9 * q + e] = wbuf[9 * a + e];
+                    if (e == 0) t.lcol[q] = touched[a];
+                } else if (ka == 2) {
+                    const int64_t q = t.uptr[g] + outpos[a];
+                    t.uval[9 * q + e] = wbuf[9 * a + e];
+                    if (e == 0) t.ucol[q] = touched[a];
+                } else if (ka == 3) {
+                    t.dval[9 * g + e] = wbuf[9 * a + e];
+                }
+            }
+        }
+        if (lane == 0) {
+            t.lend[g] = t.lptr[g] + nkl_s;
+            t.uend[g] = t.uptr[g] + nku_s;
+            double di[9];
+            if (!inv3_lu(wbuf + 9 * diag_s, di)) {
+                atomicOr(&flags[0], (int32_t)FLAG_PIVOT);
+                atomicMin(&flags[1], (int32_t)(t.own[g] >> 1));
+                for (int e = 0; e < 9; ++e) di[e] = 0.0;
+            }
+            for (int e = 0; e < 9; ++e) t.dinv[9 * g + e] = di[e];
+            // forward level: one more than every kept L column's
+            int lv = 0;
+            for (int a = 0; a < nbuf; ++a)
+                if (cls[a] == 1) lv = max(lv, t.flev[touched[a]] + 1);
+            t.flev[g] = lv;
+            maxf_s = max(maxf_s, lv);
+        }
+        __syncthreads();
+        for (int sl = lane; sl < nbuf; sl += TW) wmap[touched[sl] % W] = -1;
+        __syncthreads();
+    }
+    if (err_s) {
+        if (lane == 0) atomicOr(&flags[0], FLAG_ILUT_CAP);
+        return;
+    }
+    // backward levels, descending rows
+    __shared__ int maxb_s;
+    if (lane == 0) {
+        int mb = 0;
+        for (int64_t g = g1 - 1; g >= g0; --g) {
+            int lv = 0;
+            for (int64_t q = t.uptr[g]; q < t.uend[g]; ++q) lv = max(lv, t.blev[t.ucol[q]] + 1);
+            t.blev[g] = lv;
+            mb = max(mb, lv);
+        }
+        maxb_s = mb;
+        t.fl_cnt[s] = maxf_s + 1;
+        t.bl_cnt[s] = mb + 1;
+    }
+    __syncthreads();
+    const int64_t off = g0 + s;
+    bucket_rows(g0, g1, t.flev, maxf_s + 1, t.cnt + off, t.fl + off, t.fo);
+    bucket_rows(g0, g1, t.blev, maxb_s + 1, t.cnt + off, t.bl + off, t.bo);
+}
+
 int64_t kbox_start(int64_t b, int64_t len, int64_t p)
 {
     const int64_t base = len / p, rem = len % p;
     return b * base + std::min(b, rem);
+}
+
+// Omega_s of subdomain s: the cells within graph distance ov of its box, in
+// ascending global index, whether s owns each, and the local index of a cell
+struct Omega {
+    int64_t ex0 = 0, ey0 = 0, ez0 = 0, EX = 0, EY = 0, EZ = 0;
+    std::vector<int64_t> cells;
+    std::vector<int32_t> owned;
+    std::vector<int32_t> lmap;
+    int32_t at(int64_t i, int64_t j, int64_t k) const
+    {
+        if (i < ex0 || i >= ex0 + EX || j < ey0 || j >= ey0 + EY || k < ez0 || k >= ez0 + EZ) return -1;
+        return lmap[((k - ez0) * EY + (j - ey0)) * EX + (i - ex0)];
+    }
+};
+
+Omega omega_of(const Geo &G, int s, int px, int py, int pz, int ov)
+{
+    const int64_t nx = G.nx, ny = G.ny, nz = G.nz;
+    auto dist = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo - v : (v >= hi ? v - hi + 1 : 0); };
+    Omega o;
+    const int64_t sx = s % px, sy = (s / px) % py, sz = s / ((int64_t)px * py);
+    const int64_t x0 = kbox_start(sx, nx, px), x1 = kbox_start(sx + 1, nx, px);
+    const int64_t y0 = kbox_start(sy, ny, py), y1 = kbox_start(sy + 1, ny, py);
+    const int64_t z0 = kbox_start(sz, nz, pz), z1 = kbox_start(sz + 1, nz, pz);
+    o.ex0 = std::max<int64_t>(0, x0 - ov);
+    o.ey0 = std::max<int64_t>(0, y0 - ov);
+    o.ez0 = std::max<int64_t>(0, z0 - ov);
+    o.EX = std::min<int64_t>(nx, x1 + ov) - o.ex0;
+    o.EY = std::min<int64_t>(ny, y1 + ov) - o.ey0;
+    o.EZ = std::min<int64_t>(nz, z1 + ov) - o.ez0;
+    o.lmap.assign((size_t)(o.EX * o.EY * o.EZ), -1);
+    for (int64_t k = o.ez0; k < o.ez0 + o.EZ; ++k)
+        for (int64_t j = o.ey0; j < o.ey0 + o.EY; ++j)
+            for (int64_t i = o.ex0; i < o.ex0 + o.EX; ++i) {
+                if (dist(i, x0, x1) + dist(j, y0, y1) + dist(k, z0, z1) > ov) continue;
+                o.lmap[((k - o.ez0) * o.EY + (j - o.ey0)) * o.EX + (i - o.ex0)] = (int32_t)o.cells.size();
+                o.cells.push_back((k * ny + j) * nx + i);
+                o.owned.push_back(i >= x0 && i < x1 && j >= y0 && j < y1 && k >= z0 && k < z1);
+            }
+    return o;
 }
 
 // symbolic ILU(k) of one subdomain's local matrix, rows in local order
@@ -240,34 +681,16 @@ struct RasK final : PcImpl {
     rsv_status setup(int px, int py, int pz, int ov, int level, int64_t *bad_cell)
     {
         const Geo &G = M->g->geo;
-        const int64_t nx = G.nx, ny = G.ny, nz = G.nz;
+        const int64_t nx = G.nx, ny = G.ny;
         nsub = px * py * pz;
         std::vector<SubPlan> P(nsub);
-        auto dist = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo - v : (v >= hi ? v - hi + 1 : 0); };
         auto plan = [&](int s) {
             SubPlan &sp = P[s];
-            const int64_t sx = s % px, sy = (s / px) % py, sz = s / ((int64_t)px * py);
-            const int64_t x0 = kbox_start(sx, nx, px), x1 = kbox_start(sx + 1, nx, px);
-            const int64_t y0 = kbox_start(sy, ny, py), y1 = kbox_start(sy + 1, ny, py);
-            const int64_t z0 = kbox_start(sz, nz, pz), z1 = kbox_start(sz + 1, nz, pz);
-            const int64_t ex0 = std::max<int64_t>(0, x0 - ov), ex1 = std::min<int64_t>(nx, x1 + ov);
-            const int64_t ey0 = std::max<int64_t>(0, y0 - ov), ey1 = std::min<int64_t>(ny, y1 + ov);
-            const int64_t ez0 = std::max<int64_t>(0, z0 - ov), ez1 = std::min<int64_t>(nz, z1 + ov);
-            const int64_t EX = ex1 - ex0, EY = ey1 - ey0, EZ = ez1 - ez0;
-            std::vector<int32_t> lmap((size_t)(EX * EY * EZ), -1);
-            for (int64_t k = ez0; k < ez1; ++k)
-                for (int64_t j = ey0; j < ey1; ++j)
-                    for (int64_t i = ex0; i < ex1; ++i) {
-                        if (dist(i, x0, x1) + dist(j, y0, y1) + dist(k, z0, z1) > ov) continue;
-                        lmap[((k - ez0) * EY + (j - ey0)) * EX + (i - ex0)] = (int32_t)sp.cells.size();
-                        sp.cells.push_back((k * ny + j) * nx + i);
-                        sp.owned.push_back(i >= x0 && i < x1 && j >= y0 && j < y1 && k >= z0 && k < z1);
-                    }
+            Omega om = omega_of(G, s, px, py, pz, ov);
+            sp.cells = std::move(om.cells);
+            sp.owned = std::move(om.owned);
             const int64_t m = (int64_t)sp.cells.size();
-            auto at = [&](int64_t i, int64_t j, int64_t k) -> int32_t {
-                if (i < ex0 || i >= ex1 || j < ey0 || j >= ey1 || k < ez0 || k >= ez1) return -1;
-                return lmap[((k - ez0) * EY + (j - ey0)) * EX + (i - ex0)];
-            };
+            auto at = [&](int64_t i, int64_t j, int64_t k) -> int32_t { return om.at(i, j, k); };
             sp.lcol.assign(m, {});
             sp.ucol.assign(m, {});
             std::vector<std::vector<int32_t>> ulev(m);
@@ -422,8 +845,8 @@ struct RasK final : PcImpl {
         if (st == RSV_OK) st = alloc(&ddinv, (size_t)9 * nrow);
         if (st == RSV_OK) st = alloc(&dy, (size_t)3 * nrow);
         if (st != RSV_OK) return st;
-        d = IlukDev{nrow, dgslot, down, dlptr, duptr, dlcol, ducol, dlsrc, dusrc, dlval, duval, ddval, ddinv,
-                    dy, dfo, dbo, dfl, dbl, dfloff, dbloff, dflcnt, dblcnt, ddbase};
+        d = IlukDev{nrow, dgslot, down, dlptr, duptr, dlptr + 1, duptr + 1, dlcol, ducol, dlsrc, dusrc, dlval, duval,
+                    ddval, ddinv, dy, dfo, dbo, dfl, dbl, dfloff, dbloff, dflcnt, dblcnt, ddbase};
         rsv_status fs = flags_reset(c);      // synchronises: the host arrays may go after this
         if (fs != RSV_OK) return fs;
         {
@@ -434,6 +857,152 @@ struct RasK final : PcImpl {
             hipLaunchKernelGGL(k_iluk_factor, dim3(nsub), dim3(KT), 0, c->stream, d, c->d_flags);
         }
         RSV_LAUNCH(c);
+        return flags_check(c, bad_cell);
+    }
+};
+
+// ILUT(p, tol) local solvers: the host lays out Omega_s and the local
+// stencil (value-independent), the device factors and schedules
+struct RasT final : PcImpl {
+    rsv_matrix *M = nullptr;
+    rsv_ctx *c = nullptr;
+    int nsub = 0;
+    int64_t nrow = 0, capl = 0, capu = 0;
+    std::vector<void *> mem;
+    IlukDev d{};
+
+    ~RasT() override
+    {
+        if (c) (void)hipStreamSynchronize(c->stream);
+        for (void *p : mem) dev_free(p);
+    }
+    int64_t bytes() const override { return nrow * ((capl + capu) * 76 + 2 * 72 + 24 + 7 * 12 + 48); }
+
+    template <class T> rsv_status upload(T **dp, const std::vector<T> &h)
+    {
+        rsv_status s = dev_alloc(c, (void **)dp, std::max<size_t>(h.size(), 1) * sizeof(T));
+        if (s != RSV_OK) return s;
+        mem.push_back(*dp);
+        if (!h.empty()) RSV_HIP(c, hipMemcpyAsync(*dp, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+        return RSV_OK;
+    }
+    template <class T> rsv_status alloc(T **dp, size_t n)
+    {
+        rsv_status s = dev_alloc(c, (void **)dp, std::max<size_t>(n, 1) * sizeof(T));
+        if (s == RSV_OK) mem.push_back(*dp);
+        return s;
+    }
+
+    rsv_status apply(const double *r, double *z) override
+    {
+        ProfScope ps(c, RSV_K_RAS);
+        hipLaunchKernelGGL(k_iluk_apply, dim3(nsub), dim3(KT), 0, c->stream, d, r, z);
+        RSV_LAUNCH(c);
+        return RSV_OK;
+    }
+
+    rsv_status setup(int px, int py, int pz, int ov, int p, double tol, int64_t *bad_cell)
+    {
+        const Geo &G = M->g->geo;
+        const int64_t nx = G.nx, ny = G.ny;
+        nsub = px * py * pz;
+        capl = capu = (p < 0) ? 3 : p;
+        std::vector<Omega> O(nsub);
+        {
+            const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+            std::vector<std::thread> th;
+            for (int t = 0; t < nth; ++t)
+                th.emplace_back([&, t] { for (int s = t; s < nsub; s += nth) O[s] = omega_of(G, s, px, py, pz, ov); });
+            for (auto &x : th) x.join();
+        }
+        std::vector<int64_t> base(nsub + 1, 0);
+        for (int s = 0; s < nsub; ++s) base[s + 1] = base[s] + (int64_t)O[s].cells.size();
+        nrow = base[nsub];
+        if (nrow >= ((int64_t)1 << 31)) return set_err(c, RSV_ERR_ARG, "ILUT: more than 2^31 subdomain cells");
+        std::vector<int32_t> gslot(nrow), own(nrow), acol(7 * nrow, -1), subw(nsub), floff(nsub);
+        std::vector<int64_t> asrc(7 * nrow, -1), lptr(nrow), uptr(nrow);
+        const size_t lds_fixed = (size_t)T_NBUF * (9 * 8 + 8 + 4 + 4 + 1 + 1) + (size_t)(T_LCAP + T_CAP_MAX) * 4;
+        for (int s = 0; s < nsub; ++s) {
+            const Omega &om = O[s];
+            const int64_t m = (int64_t)om.cells.size();
+            int64_t bw = 0;
+            for (int64_t r = 0; r < m; ++r) {
+                const int64_t g = base[s] + r, cc = om.cells[r];
+                const int i = (int)(cc % nx), j = (int)((cc / nx) % ny), k = (int)(cc / (nx * ny));
+                gslot[g] = (int32_t)slot_of(G, i, j, k);
+                own[g] = (int32_t)((row_of(G, i, j, k) << 1) | (om.owned[r] ? 1 : 0));
+                lptr[g] = g * capl;
+                uptr[g] = g * capu;
+                const int32_t nb[7] = {om.at(i, j, k - 1), om.at(i, j - 1, k), om.at(i - 1, j, k), (int32_t)r,
+                                       om.at(i + 1, j, k), om.at(i, j + 1, k), om.at(i, j, k + 1)};
+                // block (row, direction st) sits at the row's own slot
+                const int64_t rs = slot_of(G, i, j, k);
+                for (int st = 0; st < 7; ++st) {
+                    if (nb[st] < 0) continue;
+                    acol[7 * g + st] = (int32_t)(base[s] + nb[st]);
+                    bw = std::max<int64_t>(bw, std::abs((int64_t)nb[st] - r));
+                    asrc[7 * g + st] = aidx(rs, st * 9);
+                }
+            }
+            subw[s] = (int32_t)(2 * bw + 1);
+            floff[s] = (int32_t)(base[s] + s);
+            if (lds_fixed + 2 * (size_t)subw[s] + 1024 > (size_t)c->lds_max)   // 1 KiB for the static LDS
+                return set_err(c, RSV_ERR_ARG, "ILUT: a subdomain's band is too wide for the work row in LDS; use more RAS subdomains");
+        }
+        size_t lds = lds_fixed + 2 * (size_t)*std::max_element(subw.begin(), subw.end());
+        O.clear();
+        int32_t *dgslot, *down, *dacol, *dsubw, *dfloff, *dlcol, *ducol, *dflev, *dblev, *dfo, *dbo, *dflcnt, *dblcnt;
+        int64_t *dasrc, *dbase, *dlptr, *duptr, *dlend, *duend, *dfl, *dbl, *dcnt;
+        double *dlval, *duval, *ddval, *ddinv, *dy;
+        rsv_status st = upload(&dgslot, gslot);
+        if (st == RSV_OK) st = upload(&down, own);
+        if (st == RSV_OK) st = upload(&dacol, acol);
+        if (st == RSV_OK) st = upload(&dasrc, asrc);
+        if (st == RSV_OK) st = upload(&dbase, base);
+        if (st == RSV_OK) st = upload(&dsubw, subw);
+        if (st == RSV_OK) st = upload(&dfloff, floff);
+        if (st == RSV_OK) st = upload(&dlptr, lptr);
+        if (st == RSV_OK) st = upload(&duptr, uptr);
+        if (st == RSV_OK) st = alloc(&dlend, (size_t)nrow);
+        if (st == RSV_OK) st = alloc(&duend, (size_t)nrow);
+        if (st == RSV_OK) st = alloc(&dlcol, (size_t)(nrow * capl));
+        if (st == RSV_OK) st = alloc(&ducol, (size_t)(nrow * capu));
+        if (st == RSV_OK) st = alloc(&dlval, (size_t)(9 * nrow * capl));
+        if (st == RSV_OK) st = alloc(&duval, (size_t)(9 * nrow * capu));
+        if (st == RSV_OK) st = alloc(&ddval, (size_t)(9 * nrow));
+        if (st == RSV_OK) st = alloc(&ddinv, (size_t)(9 * nrow));
+        if (st == RSV_OK) st = alloc(&dy, (size_t)(3 * nrow));
+        if (st == RSV_OK) st = alloc(&dflev, (size_t)nrow);
+        if (st == RSV_OK) st = alloc(&dblev, (size_t)nrow);
+        if (st == RSV_OK) st = alloc(&dfo, (size_t)nrow);
+        if (st == RSV_OK) st = alloc(&dbo, (size_t)nrow);
+        if (st == RSV_OK) st = alloc(&dfl, (size_t)(nrow + nsub));
+        if (st == RSV_OK) st = alloc(&dbl, (size_t)(nrow + nsub));
+        if (st == RSV_OK) st = alloc(&dcnt, (size_t)(nrow + nsub));
+        if (st == RSV_OK) st = alloc(&dflcnt, (size_t)nsub);
+        if (st == RSV_OK) st = alloc(&dblcnt, (size_t)nsub);
+        if (st != RSV_OK) return st;
+        IlutDev t{nrow, dacol, dasrc, dbase, dsubw, down, p, (int32_t)capl, (int32_t)capu, tol * tol, dlptr, duptr,
+                  dlend, duend, dlcol, ducol, dlval, duval, ddval, ddinv, dflev, dblev, dfo, dbo, dfl, dbl, dflcnt,
+                  dblcnt, dcnt};
+        d = IlukDev{nrow, dgslot, down, dlptr, duptr, dlend, duend, dlcol, ducol, nullptr, nullptr, dlval, duval,
+                    ddval, ddinv, dy, dfo, dbo, dfl, dbl, dfloff, dfloff, dflcnt, dblcnt, nullptr};
+        rsv_status fs = flags_reset(c);      // synchronises: the host arrays may go after this
+        if (fs != RSV_OK) return fs;
+        if (lds > 65536)
+            RSV_HIP(c, hipFuncSetAttribute((const void *)k_ilut_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds));
+        {
+            ProfScope ps(c, RSV_K_FACTOR);
+            hipLaunchKernelGGL(k_ilut_factor, dim3(nsub), dim3(TW), lds, c->stream, t, (const double *)M->d_A,
+                               c->d_flags);
+        }
+        RSV_LAUNCH(c);
+        int32_t f[2];
+        RSV_HIP(c, hipMemcpyAsync(f, c->d_flags, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+        RSV_HIP(c, hipStreamSynchronize(c->stream));
+        if (f[0] & FLAG_ILUT_CAP)
+            return set_err(c, RSV_ERR_ARG, "ILUT: a row's work list outgrew its 512 blocks; raise ilut_tol or set ilut_p");
         return flags_check(c, bad_cell);
     }
 };
@@ -457,6 +1026,32 @@ rsv_status rasK_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int6
     R->M = A;
     R->c = c;
     rsv_status s = R->setup(px, py, pz, ov, p->iluk_level, bad_cell);
+    if (s != RSV_OK) {
+        delete R;
+        return s;
+    }
+    *out = R;
+    return RSV_OK;
+}
+
+rsv_status rasT_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell)
+{
+    rsv_ctx *c = A->g->ctx;
+    const Geo &G = A->g->geo;
+    int px = 1, py = 1, pz = 1, ov = 0;      // ILUT of the whole grid: one subdomain, no overlap
+    if (p->type == RSV_PC_RAS) {
+        px = p->ras_px; py = p->ras_py; pz = p->ras_pz; ov = p->ras_overlap;
+        if (px < 1 || py < 1 || pz < 1 || px > G.nx || py > G.ny || pz > G.nz || ov < 0)
+            return set_err(c, RSV_ERR_ARG, "bad RAS subdomain counts or overlap");
+    }
+    if (p->precision != RSV_FP64) return set_err(c, RSV_ERR_ARG, "ILUT has FP64 factors only");
+    if (p->ilut_p < -1 || p->ilut_p > T_CAP_MAX) return set_err(c, RSV_ERR_ARG, "ilut_p must be in [-1, 32]");
+    if (!(p->ilut_tol >= 0.0) || !std::isfinite(p->ilut_tol)) return set_err(c, RSV_ERR_ARG, "ilut_tol must be >= 0");
+    RasT *R = new (std::nothrow) RasT();
+    if (!R) return set_err(c, RSV_ERR_OOM, "ILUT RAS");
+    R->M = A;
+    R->c = c;
+    rsv_status s = R->setup(px, py, pz, ov, p->ilut_p, p->ilut_tol, bad_cell);
     if (s != RSV_OK) {
         delete R;
         return s;

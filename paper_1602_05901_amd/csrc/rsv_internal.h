@@ -243,6 +243,8 @@ rsv_status scalar_assemble_values(rsv_matrix *M, const double *coef, int32_t whe
 rsv_status sras_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
 // ILU(k), k >= 1, for 3x3-block matrices (rsv_iluk.hip): RAS local solvers, or the whole grid as one subdomain
 rsv_status rasK_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
+// ILUT(p, tol) for 3x3-block matrices (rsv_iluk.hip): RAS local solvers, or the whole grid
+rsv_status rasT_create(rsv_matrix *A, const rsv_pc_params *p, PcImpl **out, int64_t *bad_cell);
 
 rsv_status launch_nat_to_tl(rsv_ctx *c, const Geo &g, const double *nat, double *tl);
 rsv_status launch_tl_to_nat(rsv_ctx *c, const Geo &g, const double *tl, double *nat, double alpha, double beta);

@@ -464,6 +464,12 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
         return set_err(c, RSV_ERR_ARG, "ILU(k) with k > 0 is a block BILU / RAS local solver");
     if (A->bs == 1 && p->type == RSV_PC_LEARNED)
         return set_err(c, RSV_ERR_ARG, "the learned preconditioner needs a 3x3-block matrix");
+    if (p->local_solver != RSV_LOCAL_ILUK && p->local_solver != RSV_LOCAL_ILUT)
+        return set_err(c, RSV_ERR_ARG, "bad local_solver");
+    if (p->local_solver == RSV_LOCAL_ILUT &&
+        (A->bs == 1 || p->iluk_level != 0 ||
+         (p->type != RSV_PC_BILU0 && p->type != RSV_PC_RAS && p->type != RSV_PC_CPR)))
+        return set_err(c, RSV_ERR_ARG, "ILUT is a block BILU / RAS local solver (iluk_level 0)");
     if (p->type == RSV_PC_CPR) {
         if (A->bs == 1) return set_err(c, RSV_ERR_ARG, "CPR needs a 3x3-block matrix");
         if (p->cpr_stage != RSV_PC_BILU0 && p->cpr_stage != RSV_PC_RAS)
@@ -485,17 +491,20 @@ rsv_status rsv_precond_setup(rsv_matrix *A, const rsv_pc_params *p, rsv_precond 
     case RSV_PC_NONE: break;
     case RSV_PC_BILU0:
         s = (A->bs == 1) ? sras_create(A, p, &P->impl, bad_cell)
+            : (p->local_solver == RSV_LOCAL_ILUT) ? rasT_create(A, p, &P->impl, bad_cell)
             : (p->iluk_level > 0) ? rasK_create(A, p, &P->impl, bad_cell) : bilu0_create(A, p, &P->impl, bad_cell);
         break;
     case RSV_PC_RAS:
         s = (A->bs == 1) ? sras_create(A, p, &P->impl, bad_cell)
+            : (p->local_solver == RSV_LOCAL_ILUT) ? rasT_create(A, p, &P->impl, bad_cell)
             : (p->iluk_level > 0) ? rasK_create(A, p, &P->impl, bad_cell) : ras_create(A, p, &P->impl, bad_cell);
         break;
     case RSV_PC_CPR: {
         rsv_pc_params st = *p;
         st.type = p->cpr_stage;
         PcImpl *stage = nullptr;
-        s = (st.iluk_level > 0) ? rasK_create(A, &st, &stage, bad_cell)
+        s = (st.local_solver == RSV_LOCAL_ILUT) ? rasT_create(A, &st, &stage, bad_cell)
+            : (st.iluk_level > 0) ? rasK_create(A, &st, &stage, bad_cell)
             : (st.type == RSV_PC_RAS) ? ras_create(A, &st, &stage, bad_cell) : bilu0_create(A, &st, &stage, bad_cell);
         if (s == RSV_OK) s = cpr_create(A, p, stage, &P->impl, bad_cell);
         break;

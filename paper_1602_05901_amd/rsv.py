@@ -20,6 +20,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 PC_NONE, PC_BILU0, PC_RAS, PC_LEARNED, PC_CPR = 0, 1, 2, 3, 4
 CPR_FP, CPR_PF, CPR_FPF, CPR_FFPF = 0, 1, 2, 3
 DECOUPLE_NONE, DECOUPLE_QUASI_IMPES, DECOUPLE_ABF = 0, 1, 2
+LOCAL_ILUK, LOCAL_ILUT = 0, 1
 FP64, FP32 = 0, 1
 GMRES, BICGSTAB, FGMRES = 0, 1, 2
 CGS2, DCGS2 = 0, 1
@@ -32,7 +33,8 @@ class PcParams(ctypes.Structure):
                 ("ras_overlap", i32), ("iluk_level", i32), ("pipelined", i32), ("net", vp), ("lnk", vp),
                 ("theta", dbl), ("learned_mode", i32), ("ras_stack", i32), ("ras_group", i32),
                 ("cpr_variant", i32), ("cpr_stage", i32), ("cpr_decouple", i32), ("mg_pre", i32),
-                ("mg_post", i32), ("mg_coarse", i32), ("reserved", i32 * 3)]
+                ("mg_post", i32), ("mg_coarse", i32), ("local_solver", i32), ("ilut_p", i32), ("ilut_tol", dbl),
+                ("reserved", i32 * 4)]
 
 
 class SolverParams(ctypes.Structure):

@@ -73,6 +73,8 @@ def test_defaults_follow_paper(tmp_path):
     rsv.lib().rsv_pc_params_default(ctypes.byref(p))
     assert p.ras_overlap == gold["ras"]["overlap"]
     assert p.iluk_level == gold["ras"]["iluk_level"]
+    assert p.local_solver == rsv.LOCAL_ILUK                 # the figure's default solver ILUK
+    assert p.ilut_p == gold["ras"]["ilut_p"] and p.ilut_tol == gold["ras"]["ilut_tol"]
     s = rsv.SolverParams()
     rsv.lib().rsv_solver_params_default(ctypes.byref(s))
     assert s.restart == gold["gmres_restart"]
