@@ -37,7 +37,8 @@
 
 namespace {
 
-constexpr int KT = 256;   // threads of a subdomain's workgroup
+constexpr int KT = 256;   // threads of a subdomain's workgroup (factorisation)
+constexpr int KA = 1024;  // threads of a subdomain's workgroup (apply: a level's rows spread over more lanes)
 
 struct IlukDev {
     int64_t nrow;
@@ -133,14 +134,14 @@ __global__ __launch_bounds__(KT) void k_iluk_factor(IlukDev d, int32_t *flags)
     }
 }
 
-__global__ __launch_bounds__(KT) void k_iluk_apply(IlukDev d, const double *__restrict__ r, double *__restrict__ z)
+__global__ __launch_bounds__(KA) void k_iluk_apply(IlukDev d, const double *__restrict__ r, double *__restrict__ z)
 {
     const int s = blockIdx.x;
     {
         const int nlev = d.fl_cnt[s];
         const int64_t *fl = d.fl + d.fl_off[s];
         for (int lv = 0; lv < nlev; ++lv) {
-            for (int64_t t = fl[lv] + threadIdx.x; t < fl[lv + 1]; t += KT) {
+            for (int64_t t = fl[lv] + threadIdx.x; t < fl[lv + 1]; t += KA) {
                 const int32_t i = d.fo[t];
                 const int64_t sl = d.gslot[i];
                 double v0 = r[vidx(sl, 0)], v1 = r[vidx(sl, 1)], v2 = r[vidx(sl, 2)];
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(KT) void k_iluk_apply(IlukDev d, const double *__re
         const int nlev = d.bl_cnt[s];
         const int64_t *bl = d.bl + d.bl_off[s];
         for (int lv = 0; lv < nlev; ++lv) {
-            for (int64_t t = bl[lv] + threadIdx.x; t < bl[lv + 1]; t += KT) {
+            for (int64_t t = bl[lv] + threadIdx.x; t < bl[lv + 1]; t += KA) {
                 const int32_t i = d.bo[t];
                 double v0 = d.y[3 * (int64_t)i], v1 = d.y[3 * (int64_t)i + 1], v2 = d.y[3 * (int64_t)i + 2];
                 for (int64_t q = d.uptr[i]; q < d.uend[i]; ++q) {
@@ -673,7 +674,7 @@ struct RasK final : PcImpl {
     rsv_status apply(const double *r, double *z) override
     {
         ProfScope ps(c, RSV_K_RAS);
-        hipLaunchKernelGGL(k_iluk_apply, dim3(nsub), dim3(KT), 0, c->stream, d, r, z);
+        hipLaunchKernelGGL(k_iluk_apply, dim3(nsub), dim3(KA), 0, c->stream, d, r, z);
         RSV_LAUNCH(c);
         return RSV_OK;
     }
@@ -896,7 +897,7 @@ struct RasT final : PcImpl {
     rsv_status apply(const double *r, double *z) override
     {
         ProfScope ps(c, RSV_K_RAS);
-        hipLaunchKernelGGL(k_iluk_apply, dim3(nsub), dim3(KT), 0, c->stream, d, r, z);
+        hipLaunchKernelGGL(k_iluk_apply, dim3(nsub), dim3(KA), 0, c->stream, d, r, z);
         RSV_LAUNCH(c);
         return RSV_OK;
     }
