@@ -117,12 +117,12 @@ def log(*a):
 # per workload: the forms of one timed step (the first is the headline) and
 # the forms run once after the timed steps
 WORKLOAD_FORMS = {
-    "C5": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64,gmres_ras64_iluk1,gmres_cpr_fpf,"
-           "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0,gmres_cpr_fpf_bilu0_fp32"),
+    "C5": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64,gmres_ras64_iluk1,gmres_ras64_ilut,"
+           "gmres_cpr_fpf,gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0,gmres_cpr_fpf_bilu0_fp32"),
     "C3": ("gmres_bilu0,gmres_bilu0_fp32", "gmres_ras64"),
     "C2": ("gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,gmres_ras64_dcgs2,"
            "gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64,gmres_ras64_iluk1,gmres_cpr_fpf,"
-           "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0,gmres_cpr_fpf_fp32,gmres_cpr_fpf_bilu0_fp32", ""),
+           "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0,gmres_cpr_fpf_fp32,gmres_cpr_fpf_bilu0_fp32,gmres_ras64_ilut", ""),
     "C4": ("gmres_bilu0,gmres_bilu0_fp32", ""),
     "C1": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64"),
 }
@@ -317,6 +317,13 @@ def poisson_measure(rsv, ctx, dims, parts, its=90, reps=3, cpu=True):
             if kr[k][1]}
     if "spmv" in kern:
         kern["spmv"]["GBps"] = spmv_bytes / (kern["spmv"]["avg_us"] * 1e-6) / 1e9
+    ras_bytes = M.apply_bytes
+    if "ras" in kern and ras_bytes > 0:
+        # one apply moves every Omega_s entry's ids and coefficients once and
+        # five vector passes over the entries (the library's own count)
+        gbps = ras_bytes / (kern["ras"]["avg_us"] * 1e-6) / 1e9
+        kern["ras"].update({"algorithmic_bytes": ras_bytes, "GBps": round(gbps, 1),
+                            "frac": round(gbps / HBM_PEAK_GBS, 4)})
     out = {"workload": f"scalar 7-point Laplacian {dims[0]}x{dims[1]}x{dims[2]} ({n} unknowns), GMRES(30) + RAS "
                        f"({parts[0]}x{parts[1]}x{parts[2]} subdomains of about {n // (parts[0] * parts[1] * parts[2])} "
                        f"cells, overlap 1, ILU(0)), {its} iterations",
@@ -474,6 +481,7 @@ def main():
         forms.append("fgmres_learned")
 
     hbm_peak = [0]   # device memory in use (all allocations, torch and the library) after each solve
+    apply_bytes = {}  # per form: the library's algorithmic bytes of one apply (level-scheduled solvers)
 
     def run_form(name, profile=False, keep_x=False):
         method, pkw = forms_all[name]
@@ -483,7 +491,7 @@ def main():
         t2 = time.perf_counter()
         x = torch.zeros_like(b)
         if profile:
-            ctx.profile(True, classes=("spmv", "ilu_fwd", "ilu_bwd", "ortho", "cpr"))
+            ctx.profile(True, classes=("spmv", "ilu_fwd", "ilu_bwd", "ortho", "cpr", "ras"))
         st = rsv.solve(A, M, b, x, method=method, restart=30, tol=1e-8, maxit=10000,
                        ortho=(rsv.DCGS2 if name.endswith("_dcgs2") else rsv.CGS2))
         torch.cuda.synchronize()
@@ -492,6 +500,7 @@ def main():
         if profile:
             kern = ctx.profile_read()
             ctx.profile(False)
+        apply_bytes[name] = M.apply_bytes
         free_b, total_b = torch.cuda.mem_get_info()
         hbm_peak[0] = max(hbm_peak[0], total_b - free_b)
         err = float(torch.linalg.norm(x - xtd) / torch.linalg.norm(xtd))
@@ -573,6 +582,11 @@ def main():
         tab = {k: {"avg_us": 1e3 * kms[k] / kcnt[k], "launches": kcnt[k], "total_ms": kms[k],
                    "GBps": (ab[k] / (kms[k] / kcnt[k] * 1e-3) / 1e9) if k in ab and k != "ilu_apply" else None}
                for k in rsv.K_NAMES if kcnt[k] > 0}
+        if kcnt["ras"] > 0 and apply_bytes.get(form, -1) > 0:
+            # the level-scheduled local solvers (ILU(k), ILUT): one launch per apply
+            gb = apply_bytes[form] / (kms["ras"] / kcnt["ras"] * 1e-3) / 1e9
+            tab["ras"].update({"algorithmic_bytes_per_apply": apply_bytes[form], "GBps": gb,
+                               "frac": round(gb / HBM_PEAK_GBS, 4)})
         if pk.get("type") == rsv.PC_CPR and kcnt["cpr"] > 0:
             # CPR-FPF records four timed scopes per apply: the restricted
             # residual, the V-cycle, the residual and the combination

@@ -321,6 +321,11 @@ rsv_status rsv_cpr_pressure_apply(rsv_precond *M, const double *b, double *x);
  * The caller owns both arrays (27 and 9 doubles per cell).  RSV_ERR_ARG for
  * another preconditioner type or the FP32 form. */
 rsv_status rsv_precond_bilu0_factors(const rsv_precond *M, double *L, double *Dinv);
+/* Diagnostics: the bytes one apply must move at least -- each factor entry,
+ * index and vector read or written once -- for the level-scheduled local
+ * solvers (ILU(k) with k >= 1, ILUT, the scalar RAS); -1 for the others (their
+ * byte counts are stated with their kernels) or a NULL preconditioner. */
+int64_t rsv_precond_apply_bytes(const rsv_precond *M);
 
 /* ---------------------------------------------------------------- solver */
 

@@ -241,6 +241,7 @@ struct IlutDev {
     int64_t *fl, *bl;             // per subdomain boundaries at fl_off[s] = base[s] + s
     int32_t *fl_cnt, *bl_cnt;
     int64_t *cnt;                 // scratch, same layout as fl
+    int64_t *nkept;               // per subdomain: L and U blocks kept
 };
 
 __device__ inline double fro2_blk(const double *a)
@@ -377,10 +378,11 @@ __global__ __launch_bounds__(TW) void k_ilut_factor(IlutDev t, const double *__r
     int16_t *wmap = (int16_t *)(dropped + T_NBUF);       // [W]
     __shared__ double wk[9], thr_s;
     __shared__ int nbuf, nll, pos_s, keep_s, nu_s, err_s, nla_s, nua_s, maxf_s, nkl_s, nku_s, diag_s;
+    __shared__ unsigned long long kept_s;
     __shared__ int64_t q0_s;
 
     for (int q = lane; q < W; q += TW) wmap[q] = -1;
-    if (lane == 0) { err_s = 0; maxf_s = 0; }
+    if (lane == 0) { err_s = 0; maxf_s = 0; kept_s = 0; }
     __syncthreads();
     for (int64_t g = g0; g < g1; ++g) {
         // the row of A: slots 0.. in column (= stencil slot) order
@@ -543,6 +545,7 @@ __global__ __launch_bounds__(TW) void k_ilut_factor(IlutDev t, const double *__r
         if (lane == 0) {
             t.lend[g] = t.lptr[g] + nkl_s;
             t.uend[g] = t.uptr[g] + nku_s;
+            kept_s += (unsigned long long)(nkl_s + nku_s);
             double di[9];
             if (!inv3_lu(wbuf + 9 * diag_s, di)) {
                 atomicOr(&flags[0], (int32_t)FLAG_PIVOT);
@@ -576,6 +579,7 @@ __global__ __launch_bounds__(TW) void k_ilut_factor(IlutDev t, const double *__r
             mb = max(mb, lv);
         }
         maxb_s = mb;
+        t.nkept[s] = (int64_t)kept_s;
         t.fl_cnt[s] = maxf_s + 1;
         t.bl_cnt[s] = mb + 1;
     }
@@ -655,6 +659,9 @@ struct RasK final : PcImpl {
         for (void *p : mem) dev_free(p);
     }
     int64_t bytes() const override { return (nl + nu) * (72 + 12) + nrow * (2 * 72 + 24 + 32); }
+    // per factor block its values and column (76 B); per row the pivot
+    // inverse, ids and ranges (120 B), r in, y out, y in, y out, z out (120 B)
+    int64_t apply_bytes() const override { return (nl + nu) * 76 + nrow * 240; }
 
     template <class T> rsv_status upload(T **dp, const std::vector<T> &h)
     {
@@ -878,6 +885,8 @@ struct RasT final : PcImpl {
         for (void *p : mem) dev_free(p);
     }
     int64_t bytes() const override { return nrow * ((capl + capu) * 76 + 2 * 72 + 24 + 7 * 12 + 48); }
+    int64_t nkept = 0;            // factor blocks kept (L and U, diagonals apart)
+    int64_t apply_bytes() const override { return nkept * 76 + nrow * 240; }
 
     template <class T> rsv_status upload(T **dp, const std::vector<T> &h)
     {
@@ -953,7 +962,7 @@ struct RasT final : PcImpl {
         size_t lds = lds_fixed + 2 * (size_t)*std::max_element(subw.begin(), subw.end());
         O.clear();
         int32_t *dgslot, *down, *dacol, *dsubw, *dfloff, *dlcol, *ducol, *dflev, *dblev, *dfo, *dbo, *dflcnt, *dblcnt;
-        int64_t *dasrc, *dbase, *dlptr, *duptr, *dlend, *duend, *dfl, *dbl, *dcnt;
+        int64_t *dasrc, *dbase, *dlptr, *duptr, *dlend, *duend, *dfl, *dbl, *dcnt, *dnk;
         double *dlval, *duval, *ddval, *ddinv, *dy;
         rsv_status st = upload(&dgslot, gslot);
         if (st == RSV_OK) st = upload(&down, own);
@@ -982,10 +991,11 @@ struct RasT final : PcImpl {
         if (st == RSV_OK) st = alloc(&dcnt, (size_t)(nrow + nsub));
         if (st == RSV_OK) st = alloc(&dflcnt, (size_t)nsub);
         if (st == RSV_OK) st = alloc(&dblcnt, (size_t)nsub);
+        if (st == RSV_OK) st = alloc(&dnk, (size_t)nsub);
         if (st != RSV_OK) return st;
         IlutDev t{nrow, dacol, dasrc, dbase, dsubw, down, p, (int32_t)capl, (int32_t)capu, tol * tol, dlptr, duptr,
                   dlend, duend, dlcol, ducol, dlval, duval, ddval, ddinv, dflev, dblev, dfo, dbo, dfl, dbl, dflcnt,
-                  dblcnt, dcnt};
+                  dblcnt, dcnt, dnk};
         d = IlukDev{nrow, dgslot, down, dlptr, duptr, dlend, duend, dlcol, ducol, nullptr, nullptr, dlval, duval,
                     ddval, ddinv, dy, dfo, dbo, dfl, dbl, dfloff, dfloff, dflcnt, dblcnt, nullptr};
         rsv_status fs = flags_reset(c);      // synchronises: the host arrays may go after this
@@ -1004,7 +1014,13 @@ struct RasT final : PcImpl {
         RSV_HIP(c, hipStreamSynchronize(c->stream));
         if (f[0] & FLAG_ILUT_CAP)
             return set_err(c, RSV_ERR_ARG, "ILUT: a row's work list outgrew its 512 blocks; raise ilut_tol or set ilut_p");
-        return flags_check(c, bad_cell);
+        rsv_status fc = flags_check(c, bad_cell);
+        if (fc != RSV_OK) return fc;
+        std::vector<int64_t> nk(nsub);
+        RSV_HIP(c, hipMemcpy(nk.data(), dnk, (size_t)nsub * sizeof(int64_t), hipMemcpyDeviceToHost));
+        nkept = 0;
+        for (int64_t v : nk) nkept += v;
+        return RSV_OK;
     }
 };
 

@@ -186,6 +186,8 @@ struct PcImpl {
     // z = M^{-1} r on tile-lane vectors (length nv); no aliasing
     virtual rsv_status apply(const double *r_tl, double *z_tl) = 0;
     virtual int64_t bytes() const = 0;
+    // algorithmic bytes one apply moves (factor data read once, vectors); -1: not stated
+    virtual int64_t apply_bytes() const { return -1; }
     // FP64 BILU0 only: the factors in block-row order into host arrays
     virtual rsv_status bilu0_factors(double * /*L*/, double * /*Dinv*/) { return RSV_ERR_ARG; }
 };

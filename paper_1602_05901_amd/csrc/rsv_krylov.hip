@@ -535,6 +535,12 @@ void rsv_precond_destroy(rsv_precond *P)
     delete P;
 }
 
+int64_t rsv_precond_apply_bytes(const rsv_precond *P)
+{
+    if (!P || !P->impl) return -1;
+    return P->impl->apply_bytes();
+}
+
 rsv_status rsv_precond_bilu0_factors(const rsv_precond *P, double *L, double *Dinv)
 {
     if (!P || !L || !Dinv) return set_err(P ? P->A->g->ctx : nullptr, RSV_ERR_ARG, "NULL argument");

@@ -233,6 +233,9 @@ struct SRas final : PcImpl {
         for (void *p : mem) dev_free(p);
     }
     int64_t bytes() const override { return nent * (4 * 8 + 8 * 8) + nsub * 12; }
+    // per Omega_s entry: row and owner ids, 3 + 3 neighbour entries, 3 + 3
+    // coefficients, the pivot (88 B); r in, y out, y in, y out, z out (40 B)
+    int64_t apply_bytes() const override { return nent * 128; }
 
     template <class T> rsv_status alloc(T **p, size_t n)
     {

@@ -83,6 +83,7 @@ _SIGS = {
     "rsv_precond_setup": ([vp, _P(PcParams), _P(vp), _P(i64)], i32),
     "rsv_precond_apply": ([vp, vp, vp], i32),
     "rsv_precond_bilu0_factors": ([vp, vp, vp], i32),
+    "rsv_precond_apply_bytes": ([vp], i64),
     "rsv_cpr_levels": ([vp, _P(i32), vp, i32], i32),
     "rsv_cpr_pressure_matrix": ([vp, i32, vp], i32),
     "rsv_cpr_weights": ([vp, vp], i32),
@@ -335,6 +336,11 @@ class Precond:
         D = np.zeros((n, 3, 3))
         _check(self.ctx, lib().rsv_precond_bilu0_factors(self.h, L.ctypes.data, D.ctypes.data))
         return L, D
+
+    @property
+    def apply_bytes(self):
+        """Algorithmic bytes of one apply (level-scheduled local solvers), else -1."""
+        return lib().rsv_precond_apply_bytes(self.h)
 
     def cpr_levels(self):
         """Grids (nx, ny, nz) of the CPR pressure multigrid, finest first."""
