@@ -216,7 +216,12 @@ __global__ __launch_bounds__(BS) void k_factors_to_rows(Geo g, const double *__r
 // A wavefront can keep at most 63 memory operations outstanding and retires
 // them in order, so one wave alone cannot hide HBM latency for the ~30 loads
 // each step needs; each loader wave owns every NL-th step and brings its own
-// outstanding-load budget.
+// outstanding-load budget.  The compute wave leaves each step's results in
+// the step's slot; the loader that refills the slot D steps later first
+// stores them to HBM.  A wave's memory instructions queue behind the loads
+// of the CU's other waves, so every store the compute wave issued itself
+// would hold up its chain of steps (measured: 25 % of the sweep time on
+// tiles without neighbours); it stores only the face rows.
 //
 // Step t of a tile: lane (i,j) of the compute wave handles cell k = t - (i+j)
 // (forward) or k = nz-1-(t-(14-i-j)) (backward); the cell's data sit in row
@@ -230,9 +235,11 @@ __global__ __launch_bounds__(BS) void k_factors_to_rows(Geo g, const double *__r
 // 32-bit call epoch in the upper half of a 64-bit word (FP32 values: one
 // word), so a word is valid exactly when its tag equals the current epoch --
 // no fences between tiles, no clearing between calls.  Word (p*W + h)*8 + e
-// of a row holds half h of component p of entry e, so the eight boundary
-// lanes store eight consecutive words (whole 64-byte segments, no partial
-// writes).  The loader of step t
+// of a row holds half h of component p of entry e.  The compute wave writes
+// a whole face row with one store instruction (for the same reason, the
+// number of store instructions, not their width, sets their cost): lane q
+// takes word q of the row from the results in LDS, where the boundary lane
+// has just put them.  The loader of step t
 // reads the row (one word per lane), waits until every needed word carries
 // the epoch, and writes the values into the slot.  Tiles are handed out by an
 // atomic ticket in topological order, so a tile only waits on tiles held by
@@ -251,17 +258,10 @@ __device__ inline void face_st(uint64_t *p, uint64_t v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// component p of entry e of a face row (see the word order above)
-__device__ inline void face_put(uint64_t *row, int e, int p, double v, uint32_t ep)
-{
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    face_st(row + (2 * p) * 8 + e, ((uint64_t)ep << 32) | (b & 0xffffffffull));
-    face_st(row + (2 * p + 1) * 8 + e, ((uint64_t)ep << 32) | (b >> 32));
-}
-__device__ inline void face_put(uint64_t *row, int e, int p, float v, uint32_t ep)
-{
-    face_st(row + p * 8 + e, ((uint64_t)ep << 32) | (uint64_t)__float_as_uint(v));
-}
+
+// 32-bit half h of a value's bits (h = 0 for FP32)
+__device__ inline uint32_t half_bits(double v, int h) { return (uint32_t)((uint64_t)__double_as_longlong(v) >> (32 * h)); }
+__device__ inline uint32_t half_bits(float v, int) { return __float_as_uint(v); }
 
 __device__ inline double shfl_d(double v, int src) { return __shfl(v, src, 64); }
 __device__ inline float shfl_d(float v, int src) { return __shfl(v, src, 64); }
@@ -322,15 +322,14 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
     const int D = a.D;
     constexpr int NE = DIR == 0 ? 30 : 39;       // T entries per lane per step (27 blocks [+9 D^-1] + 3 vector)
     constexpr int NS = DIR == 0 ? NE : NE + 1;   // + the output map entry (bwd)
-    constexpr int slot_elems = NS * 64 + 48;     // + x and y faces (8 entries x 3 components each)
+    constexpr int RES = NS * 64 + 48;            // + x and y faces (8 entries x 3 components each)
+    constexpr int slot_elems = RES + 192;        // + the step's results ([64 lanes][3])
     T *ring = (T *)smem;
     int32_t *tags = (int32_t *)(smem + (size_t)D * slot_elems * sizeof(T));
     int32_t *consumed = tags + D;
     int32_t *tile_ring = consumed + 1;   // tile of the workgroup's k-th tile in entry k mod 4
     int32_t *tile_tag = tile_ring + 4;   // k + 1 once entry k mod 4 holds the k-th tile
     int32_t *ftags = tile_tag + 4;       // per slot: step whose face values are in the slot (+1)
-    // exchange rows of the compute wave ([64][3] T) after the ring and its 64 tag words
-    const uint32_t xch_off = (uint32_t)((size_t)D * slot_elems * sizeof(T) + 64 * sizeof(int32_t));
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
     int li, lj;
     lane_ij(L, li, lj);
@@ -360,6 +359,33 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
     if (threadIdx.x == 0) publish(0);
     __syncthreads();
     int gstep = 0;   // running step count across tiles (tags are gstep + 1)
+    int prevT = -1;  // the workgroup's previous tile
+    bool aborted = false;
+    // Loader part: the results of global step Gs (tile Ts, local step ts),
+    // which the compute wave left in slot sl, go to HBM (lanes whose cell is
+    // in range).  The loader that refills a slot does this first, so the
+    // compute wave issues no stores of its own besides the face rows.
+    auto store_results = [&](const T *sl, int Ts, int ts) {
+        const int kk = DIR == 0 ? ts - (li + lj) : ts - (14 - li - lj);
+        if (Ts < 0 || kk < 0 || kk >= nz) return;
+        const T *res = sl + RES + L * 3;
+        const int row = DIR == 0 ? wrap_nz(ts, nz) : wrap_nz(nz + 13 - ts, nz);
+        const int64_t rb = (int64_t)Ts * nz + row;
+        if constexpr (DIR == 0) {
+            T *yp = yout + rb * 192 + L;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) __builtin_nontemporal_store(res[p], yp + p * 64);
+        } else {
+            int64_t o = rb * 192 + L;
+            if (src.zmap) {
+                const int32_t zm = ((const int32_t *)(sl + NE * 64))[L];
+                if (zm < 0) return;
+                o = ((int64_t)zm >> 6) * 192 + (zm & 63);
+            }
+#pragma unroll
+            for (int p = 0; p < 3; ++p) __builtin_nontemporal_store((double)res[p], zout + o + p * 64);
+        }
+    };
     for (int k = 0;; ++k) {
         if (__hip_atomic_load(&tile_tag[k & 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != k + 1) {
             const uint64_t t0 = wall_clock64();
@@ -372,7 +398,10 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            if (gave_up) break;   // the error flag is set; every wave leaves
+            if (gave_up) {   // the error flag is set; every wave leaves
+                aborted = true;
+                break;
+            }
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         const int T_ = __hip_atomic_load(&tile_ring[k & 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -413,6 +442,9 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 const int lo = lane_first(dmin), hi = lane_first(dmax + 1) - 1;
                 return L < lo ? lo : (L > hi ? hi : L);
             };
+            // The factor blocks are read once per apply and the results written
+            // once: both bypass the caches' retention (nontemporal; measured
+            // 3-4 % faster sweeps on the 512x512x128 grid).
             auto issue_data = [&](Regs &R, int t) {
                 const int tc = t < nsteps ? t : nsteps - 1;
                 const int row = DIR == 0 ? wrap_nz(tc, nz) : wrap_nz(nz + 13 - tc, nz);
@@ -420,11 +452,11 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 const int Ls = issue_lane(tc);
                 const T *q0 = src.p0 + rb * src.s0 + src.o0 + Ls;
 #pragma unroll
-                for (int e = 0; e < 27; ++e) R.v[e] = q0[e * 64];
+                for (int e = 0; e < 27; ++e) R.v[e] = __builtin_nontemporal_load(q0 + e * 64);
                 if constexpr (DIR == 1) {
                     const T *q1 = src.p1 + rb * src.s1 + src.o1 + Ls;
 #pragma unroll
-                    for (int e = 0; e < 9; ++e) R.v[27 + e] = q1[e * 64];
+                    for (int e = 0; e < 9; ++e) R.v[27 + e] = __builtin_nontemporal_load(q1 + e * 64);
                 }
                 if constexpr (DIR == 0) {
                     const double *q2 = src.v64 + rb * 192 + Ls;
@@ -462,6 +494,12 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     }
                 }
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                // the slot still holds the results of step G - D (this tile's or the previous one's)
+                if (G >= D) {
+                    const int Gs = G - D;
+                    const bool cur = Gs >= gstep;
+                    store_results(sl, cur ? T_ : prevT, cur ? Gs - gstep : Gs - gstep + nsteps);
+                }
 #pragma unroll
                 for (int e = 0; e < nv + 3; ++e) sl[e * 64 + L] = R.v[e];
                 if constexpr (DIR == 1) ((int32_t *)(sl + NE * 64))[L] = R.zm;
@@ -473,16 +511,16 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 const bool okx = !hasx || !need || (uint32_t)(wx >> 32) == a.epoch;
                 const bool oky = !hasy || !need || (uint32_t)(wy >> 32) == a.epoch;
                 if (!(okx && oky)) {
-                    // Slow path.  Forward sweep (seven loaders): every loader polls
-                    // its own step's rows at a short fixed interval, so consecutive
+                    // Slow path.  Seven loaders: every loader polls its own
+                    // step's rows at a short fixed interval, so consecutive
                     // steps are not serialised on each other's poll round trips.
-                    // Backward FP64 sweep (three loaders): rows become valid in step
-                    // order, so first wait (in LDS) until the previous step has been
-                    // delivered; then only the loader of the oldest pending step
-                    // polls device memory, with exponential backoff up to four
-                    // 512-cycle sleeps.  (Measured: the first is faster forward,
-                    // the second backward; a cap of 16 sleeps made the C2
-                    // backward sweep 4 % slower.)
+                    // Backward FP64 sweep (three loaders): rows become valid in
+                    // step order, so first wait (in LDS) until the previous step
+                    // has been delivered; then only the loader of the oldest
+                    // pending step polls device memory, with exponential backoff
+                    // up to four 512-cycle sleeps.  (Measured: the first is
+                    // faster forward, the second backward; a cap of 16 sleeps
+                    // made the backward sweep at 128x128x64 4 % slower.)
                     const uint64_t t0 = wall_clock64();
                     uint32_t n = 0;
                     constexpr bool serial = NLOAD < 7;
@@ -539,24 +577,37 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             const int lx = DIR == 0 ? (li > 0 ? ij_lane(li - 1, lj) : L) : (li < 7 ? ij_lane(li + 1, lj) : L);
             const int ly = DIR == 0 ? (lj > 0 ? ij_lane(li, lj - 1) : L) : (lj < 7 ? ij_lane(li, lj + 1) : L);
             const bool cx = DIR == 0 ? li == 0 : li == 7, cy = DIR == 0 ? lj == 0 : lj == 7;
-            const bool px = DIR == 0 ? (li == 7 && bx < a.btx - 1) : (li == 0 && bx > 0);
-            const bool py = DIR == 0 ? (lj == 7 && by < a.bty - 1) : (lj == 0 && by > 0);
-            uint64_t *fxo = a.faceX + (int64_t)T_ * frow;
-            uint64_t *fyo = a.faceY + (int64_t)T_ * frow;
+            // packed face stores: lane q < RW owns word q of each outgoing face
+            // row, half h = (q >> 3) % W of component (q >> 3) / W of entry
+            // e = q & 7, read from the result row of the boundary lane of
+            // entry e (x face: i = 7 forward, 0 backward, j = e; y face: i = e)
+            const int fe = L & 7, fp = (L >> 3) / W, fh = (L >> 3) % W;
+            const int fbx = DIR == 0 ? 7 : 0;
+            const int fx_src = ij_lane(fbx, fe) * 3 + fp;   // in the step's result rows
+            const int fy_src = ij_lane(fe, fbx) * 3 + fp;
+            const bool fxw = L < RW && (DIR == 0 ? bx < a.btx - 1 : bx > 0);
+            const bool fyw = L < RW && (DIR == 0 ? by < a.bty - 1 : by > 0);
+            // the boundary cell of entry e at step t is in range when (t - fk0) is in [0, nz)
+            const int fk0 = DIR == 0 ? 7 + fe : 14 - fe;
+            uint64_t *fxo = a.faceX + (int64_t)T_ * frow + L;
+            uint64_t *fyo = a.faceY + (int64_t)T_ * frow + L;
             uint32_t waited = 0;
             if (a.trace && L == 0) a.trace[4 * T_ + 0] = wall_clock64();
             // Neighbour values come through LDS: every step the wave writes its
-            // three results to its exchange row; at the next step an interior
-            // lane reads the row of its -x (+x) and -y (+y) neighbour lane and a
-            // boundary lane reads the face entry the loader put in the step's
-            // slot.  One wave only, so its LDS accesses stay in program order.
+            // three results into the result rows of the step's slot; at the next
+            // step an interior lane reads the row of its -x (+x) and -y (+y)
+            // neighbour lane there (the slot is released for new operands, but
+            // its result rows are rewritten only by this wave, D steps later),
+            // and a boundary lane reads the face entry the loader put in the
+            // step's slot.  One wave only, so its LDS accesses stay in program
+            // order.  At a tile's first step the previous slot holds another
+            // tile's results, but only the lane of the tile corner is in range
+            // then, and it takes both values from faces.
             const uint32_t slot_bytes = (uint32_t)slot_elems * sizeof(T);
-            const uint32_t xo_int = xch_off + (uint32_t)lx * 3 * sizeof(T);
-            const uint32_t yo_int = xch_off + (uint32_t)ly * 3 * sizeof(T);
+            const uint32_t xo_int = (uint32_t)(RES + lx * 3) * sizeof(T);
+            const uint32_t yo_int = (uint32_t)(RES + ly * 3) * sizeof(T);
             const uint32_t xo_face = (uint32_t)(NS * 64 + lj * 3) * sizeof(T);
             const uint32_t yo_face = (uint32_t)(NS * 64 + 24 + li * 3) * sizeof(T);
-            T *xrow = (T *)(smem + xch_off) + L * 3;
-            xrow[0] = xrow[1] = xrow[2] = (T)0;
             T last[3] = {0, 0, 0};   // this lane's previous result: the -z (+z) neighbour value
             // spin until the loaders have delivered step G into `slot` (tag G + 1);
             // `seen` is a tag value already read
@@ -579,29 +630,25 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 for (int e = 0; e < NE; ++e) nf[e] = sl[e * 64 + L];
             };
             int slot = gstep % D;                                   // slot of the current step
-            int row = DIR == 0 ? 0 : wrap_nz(nz + 13, nz);          // tile row of the current step
             // Step t with operands f (already in registers).  Order: neighbour
-            // reads and the next slot's tag; the cell update; exchange-row
-            // writes; release of this step's slot (all its reads are consumed);
-            // the next step's operands into fn (they land while the global
-            // stores below are issued).
+            // reads and the next slot's tag; the cell update; result writes;
+            // release of this step's slot (its reads are consumed and its
+            // results written); the next step's operands into fn (they land
+            // while the face stores below are issued).
             int fseen = 0;   // face tag of the current step's slot, read one step ahead
             auto step = [&](const T *f, T *fn, int t) {
                 const int G = gstep + t;
                 const int nslot = slot + 1 == D ? 0 : slot + 1;
+                const int pslot = slot == 0 ? D - 1 : slot - 1;   // the previous step's slot
                 wait_slot(ftags, slot, G, fseen);   // the boundary lanes read this step's faces
-                const T *bx = (const T *)(smem + (cx ? (uint32_t)slot * slot_bytes + xo_face : xo_int));
-                const T *by = (const T *)(smem + (cy ? (uint32_t)slot * slot_bytes + yo_face : yo_int));
+                const T *bx = (const T *)(smem + (cx ? (uint32_t)slot * slot_bytes + xo_face : (uint32_t)pslot * slot_bytes + xo_int));
+                const T *by = (const T *)(smem + (cy ? (uint32_t)slot * slot_bytes + yo_face : (uint32_t)pslot * slot_bytes + yo_int));
                 T vx[3], vy[3];
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
                     vx[p] = bx[p];
                     vy[p] = by[p];
                 }
-                // output slot of a mapped backward sweep (read before the slot is released)
-                int32_t zm = -1;
-                if constexpr (DIR == 1)
-                    if (src.zmap) zm = ((const int32_t *)(ring + (size_t)slot * slot_elems + NE * 64))[L];
                 const bool more = t + 1 < nsteps;
                 const int seen = more ? __hip_atomic_load(&tags[nslot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
                 const int kk = DIR == 0 ? t - d : t - e_;
@@ -609,13 +656,20 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                 T out[3];
                 if (DIR == 0) fwd_cell(f, last, vy, vx, f + 27, out);
                 else bwd_cell(f, f + 27, vx, vy, last, f + 36, out);
+                T *res = ring + (size_t)slot * slot_elems + RES;
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
                     out[p] = act ? out[p] : (T)0;
-                    xrow[p] = out[p];
+                    res[L * 3 + p] = out[p];
                     last[p] = out[p];
                 }
-                // every read of this step's slot has been consumed above: hand it back
+                // this step's outgoing face words, from the result rows just written
+                // (one wave: its LDS accesses complete in program order)
+                const uint32_t fxv = half_bits(res[fx_src], fh);
+                const uint32_t fyv = half_bits(res[fy_src], fh);
+                // every read of this step's slot has been consumed and its results
+                // written (the loader that refills the slot stores them): hand it back
+                __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
                 if (L == 0) __hip_atomic_store(consumed, G + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -624,34 +678,13 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
                     load_ops(fn, nslot);
                     fseen = __hip_atomic_load(&ftags[nslot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
-                if (act) {
-                    if (DIR == 0) {
-                        T *yp = yout + (rowbase + row) * 192 + L;
-#pragma unroll
-                        for (int p = 0; p < 3; ++p) yp[p * 64] = out[p];
-                    } else if (!src.zmap) {
-                        double *zp = zout + (rowbase + row) * 192 + L;
-#pragma unroll
-                        for (int p = 0; p < 3; ++p) zp[p * 64] = (double)out[p];
-                    } else if (zm >= 0) {
-                        double *zp = zout + ((int64_t)zm >> 6) * 192 + (zm & 63);
-#pragma unroll
-                        for (int p = 0; p < 3; ++p) zp[p * 64] = (double)out[p];
-                    }
-                    if (px) {
-                        uint64_t *fp = fxo + (int64_t)(t - 7) * RW;
-#pragma unroll
-                        for (int p = 0; p < 3; ++p) face_put(fp, lj, p, out[p], a.epoch);
-                    }
-                    if (py) {
-                        uint64_t *fp = fyo + (int64_t)(t - 7) * RW;
-#pragma unroll
-                        for (int p = 0; p < 3; ++p) face_put(fp, li, p, out[p], a.epoch);
-                    }
+                // this step's face rows (row t - 7): the neighbouring tiles wait for them
+                if ((unsigned)(t - fk0) < (unsigned)nz) {
+                    const uint64_t ep = (uint64_t)a.epoch << 32;
+                    if (fxw) face_st(fxo + (int64_t)(t - 7) * RW, ep | fxv);
+                    if (fyw) face_st(fyo + (int64_t)(t - 7) * RW, ep | fyv);
                 }
                 slot = nslot;
-                if (DIR == 0) row = row + 1 == nz ? 0 : row + 1;
-                else row = row == 0 ? nz - 1 : row - 1;
             };
             T fa[NE], fb[NE];
             wait_slot(tags, slot, gstep, __hip_atomic_load(&tags[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
@@ -669,6 +702,24 @@ __global__ __launch_bounds__(64 * (1 + NLOAD)) void k_sweep(SweepArgs a, SweepSr
             }
         }
         gstep += nsteps;
+        prevT = T_;
+    }
+    // loaders: the results of the last D steps are still in the ring
+    if (wave > 0 && !aborted && prevT >= 0) {
+        const int G0 = gstep - nsteps;   // first step of the last tile
+        for (int G = gstep - D > G0 ? gstep - D : G0; G < gstep; ++G) {
+            if (G % NLOAD != wave - 1) continue;
+            if (__hip_atomic_load(consumed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G + 1) {
+                const uint64_t t0 = wall_clock64();
+                uint32_t n = 0;
+                while (__hip_atomic_load(consumed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < G + 1) {
+                    if (spin_guard(a.flags, t0, n, a.wait_limit)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            store_results(ring + (size_t)(G % D) * slot_elems, prevT, G - G0);
+        }
     }
 }
 
@@ -680,13 +731,13 @@ template <typename T>
 inline size_t sweep_slot_bytes(int dir)
 {
     const int NS = (dir == 0) ? 30 : 40;   // entries per lane (+ the bwd output map entry)
-    return (size_t)(NS * 64 + 48) * sizeof(T);
+    return (size_t)(NS * 64 + 48 + 192) * sizeof(T);   // + faces + the step's results
 }
-// dynamic LDS of a sweep: D ring slots, 64 tag words, the exchange rows
+// dynamic LDS of a sweep: D ring slots and 64 tag words
 template <typename T>
 inline size_t sweep_lds_bytes(int dir, int D)
 {
-    return (size_t)D * sweep_slot_bytes<T>(dir) + 64 * sizeof(int32_t) + 64 * 3 * sizeof(T);
+    return (size_t)D * sweep_slot_bytes<T>(dir) + 64 * sizeof(int32_t);
 }
 
 // ---------------------------------------------------------------- the preconditioner object
@@ -950,7 +1001,7 @@ struct Bilu0 : PcImpl {
 
 int64_t sweep_ring_depth(const rsv_ctx *c, int dir, int fp32)
 {
-    const size_t cap = (size_t)c->lds_max - 64 * sizeof(int32_t) - 64 * 3 * sizeof(double);
+    const size_t cap = (size_t)c->lds_max - 64 * sizeof(int32_t);
     const size_t sb = fp32 ? sweep_slot_bytes<float>(dir) : sweep_slot_bytes<double>(dir);
     return (int64_t)std::max<size_t>(2, std::min<size_t>(12, cap / sb));
 }
