@@ -296,53 +296,210 @@ hipError_t launch_conv(hipStream_t st, const ConvGeo &g, const uint16_t *X, cons
     return hipGetLastError();
 }
 
-// Weight gradient dW[tap][ci][co] = sum_v X[v + off(tap)][ci] * G[v][co] as an
-// MFMA GEMM with k = voxel: rows m = ci, columns n = co.  grid.x = tile
-// (tap, ci block, co block), grid.y = voxel chunk (split K); one partial per
-// chunk, summed in chunk order afterwards.
+// Weight and bias gradients, dW[tap][ci][co] = sum_v X[v + off(tap)][ci] G[v][co]
+// and db[co] = sum_v G[v][co], as an MFMA GEMM over voxels on
+// v_mfma_f32_16x16x32_bf16 (rows m = ci, columns n = co, k = voxel; lane l
+// holds A[m = l%16][k = 8*(l/16) .. +7], B[k = 8*(l/16) .. +7][n = l%16], and
+// D[m = 4*(l/16) + i][n = l%16]).  A workgroup owns one 16 x 16 channel pair
+// (ci block, co block) and a chunk of bricks of 16 (x) x 4 (y) x 4 (z)
+// voxels.  Per brick it stages in LDS, channel-major with 16 voxels per row,
+// the input halo three times (shifted by dx = 0, 1, 2, so every A fragment is
+// one aligned 16-byte read) and the gradient tile; wave w then computes the
+// taps t = w, w + 4, ... for all 256 voxels (the B fragment of a k-step serves
+// all its taps).  The next brick's global loads are issued before the MFMAs
+// of the current one.  The rows of a channel are padded so that the 16
+// channels of a fragment fall on distinct LDS banks.
+//
+// Split over voxels: each chunk writes one partial (taps, then the bias sums
+// for ci block 0); k_dw_reduce adds them in a fixed order into the gradients.
+// (Summing them inside this kernel, by the last workgroup to finish, needs a
+// device-scope release per workgroup, which writes back the XCD's L2: 5x the
+// time of this kernel and the reduction together at 64x64x32.)
+constexpr int DW_XS = CH_Z * CH_Y * 16 + 8;   // bf16 per input channel and shift (576 + padding)
+constexpr int DW_GS = CT_Z * CT_Y * 16 + 8;   // bf16 per output channel (256 + padding)
+constexpr int DW_PART = 27 * 256 + 16;        // floats per partial: 27 taps x 16 x 16, then 16 bias sums
+constexpr int DW_MAXCHUNK = 256;              // chunks per pair (16 groups of at most 16 in the reduction)
+constexpr int DW_XU = CH_Z * CH_Y * 2 * 4;    // input staging units: (halo row, x octet, channel quad) = 288
+constexpr size_t DW_LDS = (size_t)(3 * 16 * DW_XS + 16 * DW_GS) * 2;
+static_assert(DW_LDS >= 256 * 16 * sizeof(float), "the bias reduction reuses the staging area");
+
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+struct DwRegs {
+    v4s x[2][10];   // input units: 10 voxels (x octet + 2) x 4 channels
+    v4s gq[8];      // gradient unit: 8 voxels x 4 channels
+};
+
 __global__ __launch_bounds__(256) void k_conv_dw(ConvGeo g, const uint16_t *__restrict__ X,
-                                                 const uint16_t *__restrict__ G, int nvb_chunk,
-                                                 float *__restrict__ partials)
+                                                 const uint16_t *__restrict__ G, int npairs,
+                                                 int bricks_per_chunk, float *__restrict__ partials)
 {
-    __shared__ float red[4][16][16];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int cib_n = (g.cin + 15) / 16, cob_n = g.cout / 16;
-    const int tile = blockIdx.x;
-    const int tap = tile / (cib_n * cob_n), cib = (tile / cob_n) % cib_n, cob = tile % cob_n;
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const int ci = cib * 16 + (lane & 15), co = cob * 16 + (lane & 15);
-    const int kq = 4 * (lane >> 4);
-    const int64_t nvb = (g.V + 15) / 16;
-    const int64_t vb_begin = (int64_t)blockIdx.y * nvb_chunk;
-    const int64_t vb_end = vb_begin + nvb_chunk < nvb ? vb_begin + nvb_chunk : nvb;
-    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int64_t vb = vb_begin + wave; vb < vb_end; vb += 4) {
-        v4s a, b;
+    extern __shared__ __align__(16) unsigned char dl[];
+    uint16_t *xs = (uint16_t *)dl;                  // [3 dx][16 ci][DW_XS]
+    uint16_t *gs = xs + 3 * 16 * DW_XS;             // [16 co][DW_GS]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int pair = blockIdx.x % npairs, chunk = blockIdx.x / npairs;
+    const int cob_n = g.cout / 16, cib = pair / cob_n, cob = pair % cob_n;
+    const int ntx = (g.nx + CT_X - 1) / CT_X, nty = (g.ny + CT_Y - 1) / CT_Y, ntz = (g.nz + CT_Z - 1) / CT_Z;
+    const int nbricks = ntx * nty * ntz;
+    const int b_begin = chunk * bricks_per_chunk;
+    const int b_end = b_begin + bricks_per_chunk < nbricks ? b_begin + bricks_per_chunk : nbricks;
+    const int m = lane & 15, kx = 8 * ((lane >> 4) & 1), krow = lane >> 5;
+    // gradient unit of threads 0..127: channel quad gq_q, x octet gq_o, row gq_r (y = r & 3, z = r >> 2)
+    const int gq_q = tid & 3, gq_o = (tid >> 2) & 1, gq_r = (tid >> 3) & 15;
+    v4f acc[7];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t v = vb * 16 + kq + i;
-            a[i] = 0;
-            b[i] = 0;
-            if (v < g.V) {
-                const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
-                const int64_t u = src_voxel(g, x, y, z, dx, dy, dz);
-                if (u >= 0 && ci < g.cin) a[i] = (short)X[u * g.cin + ci];
-                b[i] = (short)G[v * g.cout + co];
+    for (int j = 0; j < 7; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    float bq[4] = {0.f, 0.f, 0.f, 0.f};   // bias sums of channels 4 gq_q .. + 3
+    DwRegs R;
+    auto load = [&](int b) {
+        const int x0 = (b % ntx) * CT_X, y0 = ((b / ntx) % nty) * CT_Y, z0 = (b / (ntx * nty)) * CT_Z;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int u = tid + 256 * k;
+            const int q = u & 3, o = (u >> 2) & 1, r = u >> 3;
+            const int hy = r % CH_Y, hz = r / CH_Y;
+            const int c0 = cib * 16 + 4 * q;
+            const bool ok = u < DW_XU && c0 < g.cin;
+#pragma unroll
+            for (int i = 0; i < 10; ++i) {
+                R.x[k][i] = v4s{0, 0, 0, 0};
+                if (ok) {
+                    const int64_t sv = src_voxel(g, x0, y0, z0, 8 * o + i - 1, hy - 1, hz - 1);
+                    if (sv >= 0) R.x[k][i] = *(const v4s *)(X + sv * g.cin + c0);
+                }
             }
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
+        const int y = y0 + (gq_r & 3), z = z0 + (gq_r >> 2);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) red[wave][4 * (lane >> 4) + i][lane & 15] = acc[i];
-    __syncthreads();
-    if (threadIdx.x < 256) {
-        const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
-        const float s = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
-        const int cir = cib * 16 + r, coc = cob * 16 + c;
-        if (cir < g.cin)
-            partials[(int64_t)blockIdx.y * 27 * g.cin * g.cout + ((int64_t)tap * g.cin + cir) * g.cout + coc] = s;
+        for (int i = 0; i < 8; ++i) {
+            const int x = x0 + 8 * gq_o + i;
+            R.gq[i] = v4s{0, 0, 0, 0};
+            if (tid < 128 && x < g.nx && y < g.ny && z < g.nz)
+                R.gq[i] = *(const v4s *)(G + (x + (int64_t)g.nx * (y + (int64_t)g.ny * z)) * g.cout + cob * 16 + 4 * gq_q);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int u = tid + 256 * k;
+            if (u >= DW_XU) continue;
+            const int q = u & 3, o = (u >> 2) & 1, r = u >> 3;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    v8s row;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) row[i] = R.x[k][dx + i][j];
+                    *(v8s *)(xs + (size_t)(dx * 16 + 4 * q + j) * DW_XS + r * 16 + 8 * o) = row;
+                }
+        }
+        if (tid < 128) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v8s row;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    row[i] = R.gq[i][j];
+                    bq[j] += bf2f((uint16_t)R.gq[i][j]);
+                }
+                *(v8s *)(gs + (size_t)(4 * gq_q + j) * DW_GS + gq_r * 16 + 8 * gq_o) = row;
+            }
+        }
+    };
+    if (b_begin < b_end) load(b_begin);
+    for (int b = b_begin; b < b_end; ++b) {
+        __syncthreads();   // the previous brick's fragments have been read
+        store();
+        __syncthreads();
+        if (b + 1 < b_end) load(b + 1);
+        // k-step s: plane s / 2, rows 2 (s % 2) + krow, x from kx
+#pragma unroll 2
+        for (int s = 0; s < 8; ++s) {
+            const int z = s >> 1, row = 2 * (s & 1) + krow;
+            const v8bf bf = __builtin_bit_cast(v8bf, *(const v8s *)(gs + (size_t)m * DW_GS + (z * CT_Y + row) * 16 + kx));
+#pragma unroll
+            for (int j = 0; j < 7; ++j) {
+                const int t = wave + 4 * j;
+                if (t < 27) {
+                    const int tdz = t / 9, tdy = (t / 3) % 3, tdx = t % 3;
+                    const v8bf af = __builtin_bit_cast(
+                        v8bf, *(const v8s *)(xs + (size_t)(tdx * 16 + m) * DW_XS + ((z + tdz) * CH_Y + row + tdy) * 16 + kx));
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // this chunk's partial: taps of this wave, then (ci block 0) the bias sums
+    float *part = partials + ((int64_t)chunk * npairs + pair) * DW_PART;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const int t = wave + 4 * j;
+        if (t < 27)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) part[t * 256 + (4 * (lane >> 4) + i) * 16 + m] = acc[j][i];
+    }
+    if (cib == 0) {
+        __syncthreads();
+        float *red = (float *)dl;   // [16 channels][256 threads]
+#pragma unroll
+        for (int c = 0; c < 16; ++c) red[c * 256 + tid] = (tid < 128 && c / 4 == gq_q) ? bq[c % 4] : 0.f;
+        __syncthreads();
+        if (tid < 16) {
+            float t = 0.f;
+            for (int q = 0; q < 256; ++q) t += red[tid * 256 + q];
+            part[27 * 256 + tid] = t;
+        }
     }
 }
+
+// grad_w += scale * (sum of the chunks' weight partials), grad_b likewise for
+// the bias sums, in a fixed order: a workgroup owns 16 float4 of one pair's
+// partial; thread t sums chunk group t / 16 (chunks t / 16, + 16, ...: up to
+// 16 loads in flight), then 16 threads add the 16 group sums in group order.
+__global__ __launch_bounds__(256) void k_dw_reduce(const float *__restrict__ partials, int npairs, int nchunks,
+                                                   int cin, int cout, float scale, float *__restrict__ grad_w,
+                                                   float *__restrict__ grad_b)
+{
+    __shared__ float4 gsum[16][16];
+    constexpr int NE4 = DW_PART / 4, SLICES = (NE4 + 15) / 16;
+    const int pair = blockIdx.x / SLICES, slice = blockIdx.x % SLICES;
+    const int cob_n = cout / 16, cib = pair / cob_n, cob = pair % cob_n;
+    const int gr = threadIdx.x >> 4, e4 = slice * 16 + (threadIdx.x & 15);
+    const int64_t stride = (int64_t)npairs * DW_PART;
+    float4 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int ch = gr + 16 * i;
+        v[i] = (e4 < NE4 && ch < nchunks) ? *(const float4 *)(partials + ch * stride + (int64_t)pair * DW_PART + 4 * e4)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float4 s4 = v[0];
+#pragma unroll
+    for (int i = 1; i < 16; ++i) { s4.x += v[i].x; s4.y += v[i].y; s4.z += v[i].z; s4.w += v[i].w; }
+    gsum[gr][threadIdx.x & 15] = s4;
+    __syncthreads();
+    if (threadIdx.x >= 16 || e4 >= NE4) return;
+    float4 t4 = gsum[0][threadIdx.x];
+    for (int q = 1; q < 16; ++q) {
+        const float4 u = gsum[q][threadIdx.x];
+        t4.x += u.x; t4.y += u.y; t4.z += u.z; t4.w += u.w;
+    }
+    const float sv[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = 4 * e4 + i;
+        if (e < 27 * 256) {
+            const int t = e >> 8, ci = cib * 16 + ((e >> 4) & 15), co = cob * 16 + (e & 15);
+            if (ci < cin) grad_w[((int64_t)t * cin + ci) * cout + co] += scale * sv[i];
+        } else if (cib == 0) {
+            grad_b[cob * 16 + (e - 27 * 256)] += scale * sv[i];
+        }
+    }
+}
+
 
 // sum over chunks (fixed order), added to the gradient
 __global__ void k_sum_chunks(const float *__restrict__ partials, int nchunk, int64_t n, float scale,
@@ -352,28 +509,6 @@ __global__ void k_sum_chunks(const float *__restrict__ partials, int nchunk, int
         float s = 0.f;
         for (int c = 0; c < nchunk; ++c) s += partials[(int64_t)c * n + e];
         grad[e] += scale * s;
-    }
-}
-
-// per-channel column sums of a [V][C] BF16 tensor (bias gradients): block b sums
-// rows [b*chunk, (b+1)*chunk) with 256/C rows in flight (coalesced rows), one
-// partial per (block, channel); the partials are summed in block order after.
-__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t *__restrict__ G, int64_t V, int C, int64_t chunk,
-                                                     float *__restrict__ partials)
-{
-    __shared__ float red[256];
-    const int rows = 256 / C, c = threadIdx.x % C, r0 = threadIdx.x / C;
-    const int64_t v_begin = (int64_t)blockIdx.x * chunk;
-    const int64_t v_end = v_begin + chunk < V ? v_begin + chunk : V;
-    float s = 0.f;
-    if (r0 < rows)
-        for (int64_t v = v_begin + r0; v < v_end; v += rows) s += bf2f(G[v * C + c]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < C) {
-        float t = 0.f;
-        for (int q = 0; q < rows; ++q) t += red[q * C + threadIdx.x];
-        partials[(int64_t)blockIdx.x * C + threadIdx.x] = t;
     }
 }
 
@@ -782,21 +917,20 @@ static rsv_status conv_bwd_weight(rsv_net *n, int l, int nx, int ny, int nz, int
 {
     rsv_ctx *c = n->c;
     ConvGeo g{nx, ny, nz, up, n->a.cin[l], n->a.cout[l], (int64_t)nx * ny * nz};
-    const int64_t nvb = (g.V + 15) / 16;
-    const int tiles = 27 * ((g.cin + 15) / 16) * (g.cout / 16);
-    int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(nvb / 64, std::max(1, 2048 / tiles)));
-    const int per = (int)((nvb + chunks - 1) / chunks);
-    chunks = (int)((nvb + per - 1) / per);
-    const int64_t nw = 27LL * g.cin * g.cout;
-    const int64_t bchunk = 2048;
-    const int bch = (int)((g.V + bchunk - 1) / bchunk);
-    rsv_status s = part_reserve(n, std::max<int64_t>(nw * chunks, (int64_t)bch * g.cout));
+    if (g.cout % 16 || g.cin > 64) return set_err(c, RSV_ERR_ARG, "channel count must be 16, 32 or 64");
+    const int npairs = ((g.cin + 15) / 16) * (g.cout / 16);
+    const int64_t nbricks = (int64_t)((nx + CT_X - 1) / CT_X) * ((ny + CT_Y - 1) / CT_Y) * ((nz + CT_Z - 1) / CT_Z);
+    // about 256 workgroups (two per CU fit the 63 KB of LDS) of at least two bricks
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>((nbricks + 1) / 2, std::max(1, 256 / npairs)));
+    const int per = (int)((nbricks + want - 1) / want);
+    const int nchunks = (int)((nbricks + per - 1) / per);
+    if (nchunks > DW_MAXCHUNK) return set_err(c, RSV_ERR_ARG, "weight gradient: too many voxel chunks");
+    rsv_status s = part_reserve(n, (int64_t)nchunks * npairs * DW_PART);
     if (s != RSV_OK) return s;
-    hipLaunchKernelGGL(k_conv_dw, dim3(tiles, chunks), dim3(256), 0, c->stream, g, X, G, per, n->part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(nw)), dim3(256), 0, c->stream, (const float *)n->part, chunks, nw, scale, grad_w);
-    // bias: the partials buffer is reused after the weight sums (same stream)
-    hipLaunchKernelGGL(k_colsum_bf16, dim3(bch), dim3(256), 0, c->stream, G, g.V, g.cout, bchunk, n->part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, c->stream, (const float *)n->part, bch, (int64_t)g.cout, scale, grad_b);
+    hipLaunchKernelGGL(k_conv_dw, dim3(nchunks * npairs), dim3(256), DW_LDS, c->stream, g, X, G, npairs, per, n->part);
+    constexpr int slices = (DW_PART / 4 + 15) / 16;
+    hipLaunchKernelGGL(k_dw_reduce, dim3(npairs * slices), dim3(256), 0, c->stream, (const float *)n->part, npairs, nchunks,
+                       g.cin, g.cout, scale, grad_w, grad_b);
     RSV_LAUNCH(c);
     return RSV_OK;
 }
