@@ -117,8 +117,8 @@ def log(*a):
 # per workload: the forms of one timed step (the first is the headline) and
 # the forms run once after the timed steps
 WORKLOAD_FORMS = {
-    "C5": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64,gmres_ras64_iluk1,gmres_ras64_ilut,"
-           "gmres_cpr_fpf,gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0,gmres_cpr_fpf_bilu0_fp32"),
+    "C5": ("gmres_bilu0,gmres_bilu0_fp32", "gmres_bilu0_dcgs2,bicgstab_bilu0,gmres_ras64,gmres_ras64_iluk1,"
+           "gmres_ras64_ilut,gmres_cpr_fpf,gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0,gmres_cpr_fpf_bilu0_fp32"),
     "C3": ("gmres_bilu0,gmres_bilu0_fp32", "gmres_ras64"),
     "C2": ("gmres_ras64,bicgstab_bilu0,gmres_bilu0,gmres_bilu0_fp32,gmres_ras64_fp32,gmres_ras64_dcgs2,"
            "gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64,gmres_ras64_iluk1,gmres_cpr_fpf,"
