@@ -48,6 +48,9 @@ def algorithmic_bytes(nx, ny, nz):
         "ilu_bwd": 72 * (nl + c) + 16 * N,      # U blocks + D^-1, y in, z out
         "ilu_apply": 72 * nnzb + 32 * N,
         "spmv_plain": 72 * nnzb + 16 * N,
+        # FP32 factors: FP32 blocks and intermediate y, FP64 r in and z out
+        "ilu_fwd_fp32": 36 * nl + 12 * N,
+        "ilu_bwd_fp32": 36 * (nl + c) + 12 * N,
     }
 
 
@@ -107,7 +110,8 @@ def ras_algorithmic_bytes(nx, ny, nz, parts, ov):
                 nl += int((inside[1:] & inside[:-1]).sum() + (inside[:, 1:] & inside[:, :-1]).sum()
                           + (inside[:, :, 1:] & inside[:, :, :-1]).sum())
     N = 3 * c
-    return {"ilu_fwd": 72 * nl + 16 * N, "ilu_bwd": 72 * (nl + c) + 16 * N, "cells": c, "pairs": nl}
+    return {"ilu_fwd": 72 * nl + 16 * N, "ilu_bwd": 72 * (nl + c) + 16 * N, "cells": c, "pairs": nl,
+            "ilu_fwd_fp32": 36 * nl + 12 * N, "ilu_bwd_fp32": 36 * (nl + c) + 12 * N}
 
 
 def log(*a):
@@ -574,11 +578,15 @@ def main():
             # residual launches per solve that do read b are counted the same
             ab["spmv"] = ab_global["spmv_plain"]
         pk = forms_all[form][1]
+        if pk.get("precision") == rsv.FP32 and pk.get("type") in (rsv.PC_BILU0, rsv.PC_CPR) and \
+                pk.get("cpr_stage", rsv.PC_BILU0) == rsv.PC_BILU0:
+            ab["ilu_fwd"], ab["ilu_bwd"] = ab_global["ilu_fwd_fp32"], ab_global["ilu_bwd_fp32"]
         if pk.get("type") == rsv.PC_RAS or (pk.get("type") == rsv.PC_CPR and pk.get("cpr_stage") == rsv.PC_RAS):
             # the sweeps of this form are the local RAS sweeps
             ab_ras = ras_algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz, (pk["ras_px"], pk["ras_py"], pk["ras_pz"]),
                                            pk["ras_overlap"])
-            ab["ilu_fwd"], ab["ilu_bwd"] = ab_ras["ilu_fwd"], ab_ras["ilu_bwd"]
+            sfx = "_fp32" if pk.get("precision") == rsv.FP32 else ""
+            ab["ilu_fwd"], ab["ilu_bwd"] = ab_ras["ilu_fwd" + sfx], ab_ras["ilu_bwd" + sfx]
         tab = {k: {"avg_us": 1e3 * kms[k] / kcnt[k], "launches": kcnt[k], "total_ms": kms[k],
                    "GBps": (ab[k] / (kms[k] / kcnt[k] * 1e-3) / 1e9) if k in ab and k != "ilu_apply" else None}
                for k in rsv.K_NAMES if kcnt[k] > 0}
