@@ -172,75 +172,130 @@ constexpr int CH_N = CH_X * CH_Y * CH_Z;   // 648 halo voxels
 
 inline size_t conv_lds_bytes(int cin, int KB, int NB) { return (size_t)CH_N * cin * 2 + (size_t)KB * NB * 64 * sizeof(v4s); }
 
-template <int NB, bool OUT_BF16>
+// Global -> LDS copy of n 16-byte words by the workgroup, eight loads in
+// flight per thread before their stores.
+__device__ inline void stage_words(const v4s *__restrict__ src, v4s *dst, int n)
+{
+    for (int e0 = 0; e0 < n; e0 += 8 * 256) {
+        v4s v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = e0 + i * 256 + (int)threadIdx.x;
+            if (e < n) v[i] = src[e];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = e0 + i * 256 + (int)threadIdx.x;
+            if (e < n) dst[e] = v[i];
+        }
+    }
+}
+
+// LDS-tiled variant for inputs of CIN = 4, 16 or 32 channels.  A workgroup
+// stages the packed weights in LDS once and then walks bricks of 16 (x) x 4
+// (y) x 4 (z) output voxels (brick b, b + gridDim.x, ...): the brick's
+// 18 x 6 x 6 input halo (zero outside the grid, nearest-up-sampled when `up`)
+// goes to LDS from registers that were loaded during the previous brick's
+// MFMAs, so every MFMA operand comes from LDS and no load waits on the
+// critical path.  Wave w owns output plane z0 + w; its voxel block mb is the
+// x-run at y0 + mb.
+template <int NB, bool OUT_BF16, int CIN>
 __global__ __launch_bounds__(256) void k_conv_lds(ConvGeo g, const uint16_t *__restrict__ X, const v4s *__restrict__ Wf,
                                                   int KB, const float *__restrict__ bias,
                                                   const uint16_t *__restrict__ skip, int relu, void *__restrict__ out)
 {
+    constexpr int C4 = CIN / 4, NI = (CH_N * C4 + 255) / 256;   // halo words (4 channels) per thread
     extern __shared__ __align__(16) unsigned char cl[];
     v4s *wl = (v4s *)cl;                                        // [KB][NB][64]
-    uint16_t *xl = (uint16_t *)(cl + (size_t)KB * NB * 64 * sizeof(v4s));   // [648][cin]
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ntx = (g.nx + CT_X - 1) / CT_X, nty = (g.ny + CT_Y - 1) / CT_Y;
-    const int b = blockIdx.x;
-    const int x0 = (b % ntx) * CT_X, y0 = ((b / ntx) % nty) * CT_Y, z0 = (b / (ntx * nty)) * CT_Z;
-    const int cin = g.cin, c4 = cin / 4;
-    // stage the weights and the halo
-    for (int e = threadIdx.x; e < KB * NB * 64; e += 256) wl[e] = Wf[e];
-    for (int e = threadIdx.x; e < CH_N * c4; e += 256) {
-        const int h = e / c4, q = e - h * c4;
-        const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
-        const int64_t u = src_voxel(g, x0, y0, z0, hx - 1, hy - 1, hz - 1);
-        v4s val = v4s{0, 0, 0, 0};
-        if (u >= 0) val = *(const v4s *)(X + u * cin + 4 * q);
-        *(v4s *)(xl + (size_t)h * cin + 4 * q) = val;
-    }
-    __syncthreads();
-    const int m = lane & 15, kq = 4 * (lane >> 4);
-    v4f acc[CT_Y][NB];
+    uint16_t *xl = (uint16_t *)(cl + (size_t)KB * NB * 64 * sizeof(v4s));   // [648][CIN]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ntx = (g.nx + CT_X - 1) / CT_X, nty = (g.ny + CT_Y - 1) / CT_Y, ntz = (g.nz + CT_Z - 1) / CT_Z;
+    const int nbricks = ntx * nty * ntz;
+    stage_words(Wf, wl, KB * NB * 64);
+    v4s hv[NI];
+    auto load = [&](int b) {
+        const int x0 = (b % ntx) * CT_X, y0 = ((b / ntx) % nty) * CT_Y, z0 = (b / (ntx * nty)) * CT_Z;
 #pragma unroll
-    for (int mb = 0; mb < CT_Y; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
-    const int K = 27 * cin;
-    for (int kb = 0; kb < KB; ++kb) {
-        const int k = kb * 16 + kq;
-        const bool kin = k < K;
-        const int tap = kin ? k / cin : 0, ci = k - tap * cin;
-        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo offsets (0..2)
-        v4s a[CT_Y];
-#pragma unroll
-        for (int mb = 0; mb < CT_Y; ++mb) {
-            const int h = ((wave + dz) * CH_Y + (mb + dy)) * CH_X + (m + dx);
-            a[mb] = kin ? *(const v4s *)(xl + (size_t)h * cin + ci) : v4s{0, 0, 0, 0};
+        for (int i = 0; i < NI; ++i) {
+            const int e = tid + 256 * i;
+            const int h = e / C4, q = e - h * C4;
+            const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
+            hv[i] = v4s{0, 0, 0, 0};
+            if (e < CH_N * C4) {
+                const int64_t u = src_voxel(g, x0, y0, z0, hx - 1, hy - 1, hz - 1);
+                if (u >= 0) hv[i] = *(const v4s *)(X + u * CIN + 4 * q);
+            }
         }
+    };
+    const int m = lane & 15, kq = 4 * (lane >> 4);
+    const int n = lane & 15, mr = 4 * (lane >> 4);
+    const int K = 27 * CIN;
+    if (blockIdx.x < nbricks) load(blockIdx.x);
+    for (int b = blockIdx.x; b < nbricks; b += gridDim.x) {
+        const int x0 = (b % ntx) * CT_X, y0 = ((b / ntx) % nty) * CT_Y, z0 = (b / (ntx * nty)) * CT_Z;
+        __syncthreads();   // the previous brick's operands have been read (and the weights written)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const v4s bf = wl[(kb * NB + nb) * 64 + lane];
+        for (int i = 0; i < NI; ++i) {
+            const int e = tid + 256 * i;
+            if (e < CH_N * C4) *(v4s *)(xl + (size_t)e * 4) = hv[i];   // [h][CIN] = word e
+        }
+        __syncthreads();
+        if (b + (int)gridDim.x < nbricks) load(b + gridDim.x);
+        v4f acc[CT_Y][NB];
+#pragma unroll
+        for (int mb = 0; mb < CT_Y; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int kb = 0; kb < KB; ++kb) {
+            const int k = kb * 16 + kq;
+            const bool kin = k < K;
+            const int tap = kin ? k / CIN : 0, ci = k - tap * CIN;
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo offsets (0..2)
+            v4s a[CT_Y];
+#pragma unroll
+            for (int mb = 0; mb < CT_Y; ++mb) {
+                const int h = ((wave + dz) * CH_Y + (mb + dy)) * CH_X + (m + dx);
+                a[mb] = kin ? *(const v4s *)(xl + (size_t)h * CIN + ci) : v4s{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const v4s bf = wl[(kb * NB + nb) * 64 + lane];
+#pragma unroll
+                for (int mb = 0; mb < CT_Y; ++mb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], bf, acc[mb][nb], 0, 0, 0);
+            }
+        }
+        // epilogue: the skip inputs are loaded together, then bias, skip, ReLU, store
+        const int z = z0 + wave;
+        float sk[NB][CT_Y][4];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int mb = 0; mb < CT_Y; ++mb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], bf, acc[mb][nb], 0, 0, 0);
-        }
-    }
-    const int n = lane & 15, mr = 4 * (lane >> 4);
-    const int z = z0 + wave;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int co = nb * 16 + n;
-        const float bb = bias ? bias[co] : 0.f;
+                for (int i = 0; i < 4; ++i) {
+                    const int x = x0 + mr + i, y = y0 + mb;
+                    sk[nb][mb][i] = 0.f;
+                    if (skip && x < g.nx && y < g.ny && z < g.nz)
+                        sk[nb][mb][i] = bf2f(skip[(x + (int64_t)g.nx * (y + (int64_t)g.ny * z)) * g.cout + nb * 16 + n]);
+                }
 #pragma unroll
-        for (int mb = 0; mb < CT_Y; ++mb) {
-            const int y = y0 + mb;
+        for (int nb = 0; nb < NB; ++nb) {
+            const int co = nb * 16 + n;
+            const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = x0 + mr + i;
-                if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
-                const int64_t vo = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
-                float val = acc[mb][nb][i] + bb;
-                if (skip) val += bf2f(skip[vo * g.cout + co]);
-                if (relu) val = val > 0.f ? val : 0.f;
-                if (OUT_BF16) ((uint16_t *)out)[vo * g.cout + co] = f2bf(val);
-                else ((float *)out)[vo * g.cout + co] = val;
+            for (int mb = 0; mb < CT_Y; ++mb) {
+                const int y = y0 + mb;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int x = x0 + mr + i;
+                    if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+                    const int64_t vo = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+                    float val = acc[mb][nb][i] + bb + sk[nb][mb][i];
+                    if (relu) val = val > 0.f ? val : 0.f;
+                    if (OUT_BF16) ((uint16_t *)out)[vo * g.cout + co] = f2bf(val);
+                    else ((float *)out)[vo * g.cout + co] = val;
+                }
             }
         }
     }
@@ -255,25 +310,35 @@ hipError_t launch_conv(hipStream_t st, const ConvGeo &g, const uint16_t *X, cons
                        const uint16_t *skip, int relu, void *out)
 {
     const int NB = (g.cout + 15) / 16;
-    if (g.cin <= 32 && conv_lds_bytes(g.cin, KB, NB) <= CONV_LDS_MAX && g.V >= 4096) {
-        static bool attr[2][5] = {};
+    if ((g.cin == 4 || g.cin == 16 || g.cin == 32) && conv_lds_bytes(g.cin, KB, NB) <= CONV_LDS_MAX && g.V >= 4096) {
+        static bool attr[2][5][3] = {};
         const size_t sh = conv_lds_bytes(g.cin, KB, NB);
-        const int64_t nblk_ = (int64_t)((g.nx + CT_X - 1) / CT_X) * ((g.ny + CT_Y - 1) / CT_Y) * ((g.nz + CT_Z - 1) / CT_Z);
-#define RSV_CONVL(nb)                                                                                                     \
-    do {                                                                                                              \
-        if (!attr[OUT_BF16][nb]) {                                                                                    \
-            hipError_t e_ = hipFuncSetAttribute((const void *)k_conv_lds<nb, OUT_BF16>,                               \
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)CONV_LDS_MAX);       \
-            if (e_ != hipSuccess) return e_;                                                                          \
-            attr[OUT_BF16][nb] = true;                                                                                \
-        }                                                                                                             \
-        hipLaunchKernelGGL((k_conv_lds<nb, OUT_BF16>), dim3((unsigned)nblk_), dim3(256), sh, st, g, X, Wf, KB, bias, \
-                           skip, relu, out);                                                                          \
+        const int64_t nbricks = (int64_t)((g.nx + CT_X - 1) / CT_X) * ((g.ny + CT_Y - 1) / CT_Y) * ((g.nz + CT_Z - 1) / CT_Z);
+        // a few workgroups per CU, each walking many bricks with its weights staged once
+        const unsigned nwg = (unsigned)std::min<int64_t>(nbricks, 1024);
+        const int ci = g.cin == 4 ? 0 : (g.cin == 16 ? 1 : 2);
+#define RSV_CONVL(nb, cin)                                                                                                \
+    do {                                                                                                                  \
+        if (!attr[OUT_BF16][nb][ci]) {                                                                                    \
+            hipError_t e_ = hipFuncSetAttribute((const void *)k_conv_lds<nb, OUT_BF16, cin>,                              \
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)CONV_LDS_MAX);           \
+            if (e_ != hipSuccess) return e_;                                                                              \
+            attr[OUT_BF16][nb][ci] = true;                                                                                \
+        }                                                                                                                 \
+        hipLaunchKernelGGL((k_conv_lds<nb, OUT_BF16, cin>), dim3(nwg), dim3(256), sh, st, g, X, Wf, KB, bias, skip, relu, \
+                           out);                                                                                          \
     } while (0)
-        if (NB == 1) RSV_CONVL(1);
-        else if (NB == 2) RSV_CONVL(2);
-        else if (NB == 4) RSV_CONVL(4);
-        else return hipErrorInvalidValue;
+#define RSV_CONVL_NB(cin)                          \
+    do {                                           \
+        if (NB == 1) RSV_CONVL(1, cin);            \
+        else if (NB == 2) RSV_CONVL(2, cin);       \
+        else if (NB == 4) RSV_CONVL(4, cin);       \
+        else return hipErrorInvalidValue;          \
+    } while (0)
+        if (g.cin == 4) RSV_CONVL_NB(4);
+        else if (g.cin == 16) RSV_CONVL_NB(16);
+        else RSV_CONVL_NB(32);
+#undef RSV_CONVL_NB
 #undef RSV_CONVL
         return hipGetLastError();
     }
