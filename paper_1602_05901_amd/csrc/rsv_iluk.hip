@@ -134,6 +134,79 @@ __global__ __launch_bounds__(KT) void k_iluk_factor(IlukDev d, int32_t *flags)
     }
 }
 
+// One row of the forward sweep, y_i = r_i - sum L_ij y_j: the blocks and y
+// values of up to four entries are loaded before their products are
+// subtracted (in entry order).
+__device__ inline void iluk_fwd_row(const IlukDev &d, const double *__restrict__ r, int32_t i)
+{
+    const int64_t sl = d.gslot[i];
+    double v0 = r[vidx(sl, 0)], v1 = r[vidx(sl, 1)], v2 = r[vidx(sl, 2)];
+    const int64_t pe = d.lend[i];
+    for (int64_t p0 = d.lptr[i]; p0 < pe; p0 += 4) {
+        double L[4][9], y[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (p0 + q >= pe) continue;
+            const double *Lp = d.lval + 9 * (p0 + q), *yk = d.y + 3 * (int64_t)d.lcol[p0 + q];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) L[q][e] = Lp[e];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) y[q][e] = yk[e];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (p0 + q >= pe) continue;
+            v0 -= L[q][0] * y[q][0] + L[q][1] * y[q][1] + L[q][2] * y[q][2];
+            v1 -= L[q][3] * y[q][0] + L[q][4] * y[q][1] + L[q][5] * y[q][2];
+            v2 -= L[q][6] * y[q][0] + L[q][7] * y[q][1] + L[q][8] * y[q][2];
+        }
+    }
+    d.y[3 * (int64_t)i] = v0;
+    d.y[3 * (int64_t)i + 1] = v1;
+    d.y[3 * (int64_t)i + 2] = v2;
+}
+
+// One row of the backward sweep, z_i = U_ii^-1 (y_i - sum U_ij z_j) (z in
+// place of y), the owner also writing z_i into the tile-lane result.
+__device__ inline void iluk_bwd_row(const IlukDev &d, double *__restrict__ z, int32_t i)
+{
+    double v0 = d.y[3 * (int64_t)i], v1 = d.y[3 * (int64_t)i + 1], v2 = d.y[3 * (int64_t)i + 2];
+    const int64_t qe = d.uend[i];
+    for (int64_t q0 = d.uptr[i]; q0 < qe; q0 += 4) {
+        double U[4][9], w[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q0 + q >= qe) continue;
+            const double *Uq = d.uval + 9 * (q0 + q), *zj = d.y + 3 * (int64_t)d.ucol[q0 + q];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) U[q][e] = Uq[e];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) w[q][e] = zj[e];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q0 + q >= qe) continue;
+            v0 -= U[q][0] * w[q][0] + U[q][1] * w[q][1] + U[q][2] * w[q][2];
+            v1 -= U[q][3] * w[q][0] + U[q][4] * w[q][1] + U[q][5] * w[q][2];
+            v2 -= U[q][6] * w[q][0] + U[q][7] * w[q][1] + U[q][8] * w[q][2];
+        }
+    }
+    const double *Di = d.dinv + 9 * (int64_t)i;
+    const double w0 = Di[0] * v0 + Di[1] * v1 + Di[2] * v2;
+    const double w1 = Di[3] * v0 + Di[4] * v1 + Di[5] * v2;
+    const double w2 = Di[6] * v0 + Di[7] * v1 + Di[8] * v2;
+    d.y[3 * (int64_t)i] = w0;
+    d.y[3 * (int64_t)i + 1] = w1;
+    d.y[3 * (int64_t)i + 2] = w2;
+    if (d.own[i] & 1) {
+        const int64_t sl = d.gslot[i];
+        z[vidx(sl, 0)] = w0;
+        z[vidx(sl, 1)] = w1;
+        z[vidx(sl, 2)] = w2;
+    }
+}
+
+// Small subdomains: one workgroup per subdomain walks its levels.
 __global__ __launch_bounds__(KA) void k_iluk_apply(IlukDev d, const double *__restrict__ r, double *__restrict__ z)
 {
     const int s = blockIdx.x;
@@ -141,21 +214,7 @@ __global__ __launch_bounds__(KA) void k_iluk_apply(IlukDev d, const double *__re
         const int nlev = d.fl_cnt[s];
         const int64_t *fl = d.fl + d.fl_off[s];
         for (int lv = 0; lv < nlev; ++lv) {
-            for (int64_t t = fl[lv] + threadIdx.x; t < fl[lv + 1]; t += KA) {
-                const int32_t i = d.fo[t];
-                const int64_t sl = d.gslot[i];
-                double v0 = r[vidx(sl, 0)], v1 = r[vidx(sl, 1)], v2 = r[vidx(sl, 2)];
-                for (int64_t p = d.lptr[i]; p < d.lend[i]; ++p) {
-                    const double *L = d.lval + 9 * p, *yk = d.y + 3 * (int64_t)d.lcol[p];
-                    const double y0 = yk[0], y1 = yk[1], y2 = yk[2];
-                    v0 -= L[0] * y0 + L[1] * y1 + L[2] * y2;
-                    v1 -= L[3] * y0 + L[4] * y1 + L[5] * y2;
-                    v2 -= L[6] * y0 + L[7] * y1 + L[8] * y2;
-                }
-                d.y[3 * (int64_t)i] = v0;
-                d.y[3 * (int64_t)i + 1] = v1;
-                d.y[3 * (int64_t)i + 2] = v2;
-            }
+            for (int64_t t = fl[lv] + threadIdx.x; t < fl[lv + 1]; t += KA) iluk_fwd_row(d, r, d.fo[t]);
             __syncthreads();
         }
     }
@@ -163,33 +222,48 @@ __global__ __launch_bounds__(KA) void k_iluk_apply(IlukDev d, const double *__re
         const int nlev = d.bl_cnt[s];
         const int64_t *bl = d.bl + d.bl_off[s];
         for (int lv = 0; lv < nlev; ++lv) {
-            for (int64_t t = bl[lv] + threadIdx.x; t < bl[lv + 1]; t += KA) {
-                const int32_t i = d.bo[t];
-                double v0 = d.y[3 * (int64_t)i], v1 = d.y[3 * (int64_t)i + 1], v2 = d.y[3 * (int64_t)i + 2];
-                for (int64_t q = d.uptr[i]; q < d.uend[i]; ++q) {
-                    const double *U = d.uval + 9 * q, *zj = d.y + 3 * (int64_t)d.ucol[q];
-                    const double z0 = zj[0], z1 = zj[1], z2 = zj[2];
-                    v0 -= U[0] * z0 + U[1] * z1 + U[2] * z2;
-                    v1 -= U[3] * z0 + U[4] * z1 + U[5] * z2;
-                    v2 -= U[6] * z0 + U[7] * z1 + U[8] * z2;
-                }
-                const double *Di = d.dinv + 9 * (int64_t)i;
-                const double w0 = Di[0] * v0 + Di[1] * v1 + Di[2] * v2;
-                const double w1 = Di[3] * v0 + Di[4] * v1 + Di[5] * v2;
-                const double w2 = Di[6] * v0 + Di[7] * v1 + Di[8] * v2;
-                d.y[3 * (int64_t)i] = w0;
-                d.y[3 * (int64_t)i + 1] = w1;
-                d.y[3 * (int64_t)i + 2] = w2;
-                if (d.own[i] & 1) {
-                    const int64_t sl = d.gslot[i];
-                    z[vidx(sl, 0)] = w0;
-                    z[vidx(sl, 1)] = w1;
-                    z[vidx(sl, 2)] = w2;
-                }
-            }
+            for (int64_t t = bl[lv] + threadIdx.x; t < bl[lv + 1]; t += KA) iluk_bwd_row(d, z, d.bo[t]);
             __syncthreads();
         }
     }
+}
+
+// Large subdomains: one launch per level of every subdomain at once
+// (grid.y = subdomain, grid.x workgroups striding over the level's rows), so
+// the whole chip works on a level and the kernel boundary orders the levels.
+constexpr int LV_WG = 4;   // workgroups per subdomain and level
+__global__ __launch_bounds__(256) void k_iluk_fwd_level(IlukDev d, const double *__restrict__ r, int lv)
+{
+    const int s = blockIdx.y;
+    if (lv >= d.fl_cnt[s]) return;
+    const int64_t *fl = d.fl + d.fl_off[s];
+    for (int64_t t = fl[lv] + blockIdx.x * 256 + threadIdx.x; t < fl[lv + 1]; t += (int64_t)gridDim.x * 256)
+        iluk_fwd_row(d, r, d.fo[t]);
+}
+__global__ __launch_bounds__(256) void k_iluk_bwd_level(IlukDev d, double *__restrict__ z, int lv)
+{
+    const int s = blockIdx.y;
+    if (lv >= d.bl_cnt[s]) return;
+    const int64_t *bl = d.bl + d.bl_off[s];
+    for (int64_t t = bl[lv] + blockIdx.x * 256 + threadIdx.x; t < bl[lv + 1]; t += (int64_t)gridDim.x * 256)
+        iluk_bwd_row(d, z, d.bo[t]);
+}
+
+// The apply of either form: per-level launches when a level has at least 256
+// rows per subdomain on average, else one workgroup per subdomain.
+inline rsv_status iluk_apply(rsv_ctx *c, const IlukDev &d, int nsub, int nfl_max, int nbl_max, bool per_level,
+                             const double *r, double *z)
+{
+    if (!per_level) {
+        hipLaunchKernelGGL(k_iluk_apply, dim3(nsub), dim3(KA), 0, c->stream, d, r, z);
+        RSV_LAUNCH(c);
+        return RSV_OK;
+    }
+    const dim3 grid(LV_WG, nsub);
+    for (int lv = 0; lv < nfl_max; ++lv) hipLaunchKernelGGL(k_iluk_fwd_level, grid, dim3(256), 0, c->stream, d, r, lv);
+    for (int lv = 0; lv < nbl_max; ++lv) hipLaunchKernelGGL(k_iluk_bwd_level, grid, dim3(256), 0, c->stream, d, z, lv);
+    RSV_LAUNCH(c);
+    return RSV_OK;
 }
 
 // ---------------------------------------------------------------- ILUT(p, tol)
@@ -649,6 +723,8 @@ struct RasK final : PcImpl {
     rsv_matrix *M = nullptr;
     rsv_ctx *c = nullptr;
     int nsub = 0;
+    int nfl_max = 0, nbl_max = 0;   // most levels of a subdomain (forward, backward)
+    bool per_level = false;         // apply by per-level launches
     int64_t nrow = 0, nl = 0, nu = 0;
     std::vector<void *> mem;
     IlukDev d{};
@@ -681,9 +757,7 @@ struct RasK final : PcImpl {
     rsv_status apply(const double *r, double *z) override
     {
         ProfScope ps(c, RSV_K_RAS);
-        hipLaunchKernelGGL(k_iluk_apply, dim3(nsub), dim3(KA), 0, c->stream, d, r, z);
-        RSV_LAUNCH(c);
-        return RSV_OK;
+        return iluk_apply(c, d, nsub, nfl_max, nbl_max, per_level, r, z);
     }
 
     rsv_status setup(int px, int py, int pz, int ov, int level, int64_t *bad_cell)
@@ -819,6 +893,7 @@ struct RasK final : PcImpl {
                 std::vector<int64_t> &bounds = pass ? bl : fl;
                 (pass ? bl_off : fl_off)[s] = (int32_t)bounds.size();
                 (pass ? bl_cnt : fl_cnt)[s] = nlv;
+                (pass ? nbl_max : nfl_max) = std::max(pass ? nbl_max : nfl_max, nlv);
                 for (int q = 0; q <= nlv; ++q) bounds.push_back(pos + cnt[q]);
                 std::vector<int32_t> &ord = pass ? bo : fo;
                 std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
@@ -827,6 +902,7 @@ struct RasK final : PcImpl {
             pos += m;
         }
         P.clear();
+        per_level = nsub > 0 && nrow / nsub >= 256 * (int64_t)std::max(nfl_max, nbl_max);
         int32_t *dgslot, *down, *dlcol, *ducol, *dfo, *dbo, *dfloff, *dbloff, *dflcnt, *dblcnt;
         int64_t *dlptr, *duptr, *dlsrc, *dusrc, *ddbase, *dfl, *dbl;
         double *dlval, *duval, *ddval, *ddinv, *dy;
@@ -875,6 +951,8 @@ struct RasT final : PcImpl {
     rsv_matrix *M = nullptr;
     rsv_ctx *c = nullptr;
     int nsub = 0;
+    int nfl_max = 0, nbl_max = 0;   // most levels of a subdomain (forward, backward)
+    bool per_level = false;         // apply by per-level launches
     int64_t nrow = 0, capl = 0, capu = 0;
     std::vector<void *> mem;
     IlukDev d{};
@@ -906,9 +984,7 @@ struct RasT final : PcImpl {
     rsv_status apply(const double *r, double *z) override
     {
         ProfScope ps(c, RSV_K_RAS);
-        hipLaunchKernelGGL(k_iluk_apply, dim3(nsub), dim3(KA), 0, c->stream, d, r, z);
-        RSV_LAUNCH(c);
-        return RSV_OK;
+        return iluk_apply(c, d, nsub, nfl_max, nbl_max, per_level, r, z);
     }
 
     rsv_status setup(int px, int py, int pz, int ov, int p, double tol, int64_t *bad_cell)
@@ -1020,6 +1096,13 @@ struct RasT final : PcImpl {
         RSV_HIP(c, hipMemcpy(nk.data(), dnk, (size_t)nsub * sizeof(int64_t), hipMemcpyDeviceToHost));
         nkept = 0;
         for (int64_t v : nk) nkept += v;
+        // the device-built schedules' level counts choose the apply
+        std::vector<int32_t> nfc(nsub), nbc(nsub);
+        RSV_HIP(c, hipMemcpy(nfc.data(), d.fl_cnt, (size_t)nsub * sizeof(int32_t), hipMemcpyDeviceToHost));
+        RSV_HIP(c, hipMemcpy(nbc.data(), d.bl_cnt, (size_t)nsub * sizeof(int32_t), hipMemcpyDeviceToHost));
+        nfl_max = *std::max_element(nfc.begin(), nfc.end());
+        nbl_max = *std::max_element(nbc.begin(), nbc.end());
+        per_level = nrow / nsub >= 256 * (int64_t)std::max(nfl_max, nbl_max);
         return RSV_OK;
     }
 };

@@ -75,6 +75,23 @@ def test_bilu_k_apply(rsv, ctx, dims, k):
     M.close(); A.close(); g.close()
 
 
+def test_bilu_1_apply_large_subdomain(rsv, ctx):
+    """The whole 64x64x32 grid as one subdomain: 131k rows, at least 256 per
+    level on average, so the apply runs one launch per level (the path of
+    large RAS subdomains); the same bar as the small grids."""
+    dims = (64, 64, 32)
+    cfg, B, Ao, g = sysm(rsv, ctx, dims, 7)
+    A = rsv.Matrix(g, dev(B))
+    M = rsv.Precond(A, type=rsv.PC_BILU0, iluk_level=1)
+    n = 3 * cfg.ncell
+    r = I.test_vector(8, n)
+    z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    M.apply(dev(r), z)
+    M.apply(dev(r), z)   # a second apply over the same schedules
+    check_apply(z.cpu().numpy(), O.ILU(Ao, level=1).apply(r))
+    M.close(); A.close(); g.close()
+
+
 @pytest.mark.parametrize("dims,parts,ov", [((20, 20, 10), (2, 2, 2), 1), ((13, 9, 5), (3, 2, 1), 1),
                                            ((16, 16, 8), (4, 4, 4), 1), ((12, 10, 6), (2, 2, 2), 2),
                                            ((12, 10, 6), (2, 3, 1), 0), ((10, 1, 1), (3, 1, 1), 1),

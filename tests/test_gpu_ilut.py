@@ -96,6 +96,22 @@ def test_whole_grid_ilut_apply(rsv, ctx, dims, p, tol, shift):
     A.close(); g.close()
 
 
+def test_ilut_apply_large_subdomain(rsv, ctx):
+    """The whole 64x64x32 grid as one subdomain: at least 256 rows per level
+    on average, so the apply runs one launch per level."""
+    dims = (64, 64, 32)
+    cfg, B, Ao, g = sysm(rsv, ctx, dims, 13, 2.0)
+    A = rsv.Matrix(g, dev(B))
+    n = 3 * cfg.ncell
+    r = I.test_vector(14, n)
+    z = apply_gpu(rsv, A, n, r, type=rsv.PC_BILU0)
+    ref = O.ILU(Ao, ilut=(-1, 1e-3)).apply(r)
+    err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+    log("  error", err)
+    assert err <= bar_of(2.0, ref, r)
+    A.close(); g.close()
+
+
 @pytest.mark.parametrize("dims,parts,ov", [((20, 20, 10), (2, 2, 2), 1), ((13, 9, 5), (3, 2, 1), 1),
                                            ((17, 3, 19), (2, 1, 3), 2), ((9, 16, 33), (1, 2, 4), 0),
                                            ((32, 32, 16), (4, 4, 4), 1)])
