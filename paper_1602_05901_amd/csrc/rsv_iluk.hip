@@ -714,10 +714,21 @@ Omega omega_of(const Geo &G, int s, int px, int py, int pz, int ov)
 struct SubPlan {
     std::vector<int64_t> cells;                  // global natural cell index, ascending
     std::vector<int32_t> owned;
-    std::vector<std::vector<int32_t>> lcol, ucol; // local columns, ascending
+    std::vector<int64_t> lptr, uptr;             // per local row: its range in lcol / ucol (m + 1)
+    std::vector<int32_t> lcol, ucol;             // local columns, ascending within a row
     std::vector<int32_t> flev, blev;
     int nfl = 0, nbl = 0;
 };
+
+// Runs f(s) for s = 0 .. n-1 on up to 16 host threads.
+template <class F> void for_each_subdomain(int n, F f)
+{
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t] { for (int s = t; s < n; s += nth) f(s); });
+    for (auto &x : th) x.join();
+}
 
 struct RasK final : PcImpl {
     rsv_matrix *M = nullptr;
@@ -773,9 +784,10 @@ struct RasK final : PcImpl {
             sp.owned = std::move(om.owned);
             const int64_t m = (int64_t)sp.cells.size();
             auto at = [&](int64_t i, int64_t j, int64_t k) -> int32_t { return om.at(i, j, k); };
-            sp.lcol.assign(m, {});
-            sp.ucol.assign(m, {});
-            std::vector<std::vector<int32_t>> ulev(m);
+            // rows in order, appended to flat arrays; ulev holds each U entry's fill level
+            sp.lptr.assign(m + 1, 0);
+            sp.uptr.assign(m + 1, 0);
+            std::vector<int32_t> ulev;
             std::vector<int32_t> lev(m, -1), row;
             for (int64_t r = 0; r < m; ++r) {
                 const int64_t cc = sp.cells[r];
@@ -788,9 +800,9 @@ struct RasK final : PcImpl {
                 std::sort(row.begin(), row.end());
                 for (size_t t = 0; t < row.size() && row[t] < r; ++t) {
                     const int32_t mm = row[t];
-                    for (size_t q = 0; q < sp.ucol[mm].size(); ++q) {
-                        const int32_t jj = sp.ucol[mm][q];
-                        const int32_t l = lev[mm] + ulev[mm][q] + 1;
+                    for (int64_t q = sp.uptr[mm]; q < sp.uptr[mm + 1]; ++q) {
+                        const int32_t jj = sp.ucol[q];
+                        const int32_t l = lev[mm] + ulev[q] + 1;
                         if (l > level) continue;
                         if (lev[jj] < 0) {
                             row.insert(std::upper_bound(row.begin() + t + 1, row.end(), jj), jj);
@@ -801,40 +813,49 @@ struct RasK final : PcImpl {
                     }
                 }
                 for (int32_t col : row) {
-                    if (col < r) sp.lcol[r].push_back(col);
-                    else if (col > r) { sp.ucol[r].push_back(col); ulev[r].push_back(lev[col]); }
+                    if (col < r) sp.lcol.push_back(col);
+                    else if (col > r) { sp.ucol.push_back(col); ulev.push_back(lev[col]); }
                     lev[col] = -1;
                 }
+                sp.lptr[r + 1] = (int64_t)sp.lcol.size();
+                sp.uptr[r + 1] = (int64_t)sp.ucol.size();
             }
             sp.flev.assign(m, 0);
             sp.blev.assign(m, 0);
             for (int64_t r = 0; r < m; ++r) {
                 int32_t v = 0;
-                for (int32_t k2 : sp.lcol[r]) v = std::max(v, sp.flev[k2] + 1);
+                for (int64_t q = sp.lptr[r]; q < sp.lptr[r + 1]; ++q) v = std::max(v, sp.flev[sp.lcol[q]] + 1);
                 sp.flev[r] = v;
                 sp.nfl = std::max(sp.nfl, v + 1);
             }
             for (int64_t r = m - 1; r >= 0; --r) {
                 int32_t v = 0;
-                for (int32_t j2 : sp.ucol[r]) v = std::max(v, sp.blev[j2] + 1);
+                for (int64_t q = sp.uptr[r]; q < sp.uptr[r + 1]; ++q) v = std::max(v, sp.blev[sp.ucol[q]] + 1);
                 sp.blev[r] = v;
                 sp.nbl = std::max(sp.nbl, v + 1);
             }
         };
-        {
-            const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-            std::vector<std::thread> th;
-            for (int t = 0; t < nth; ++t)
-                th.emplace_back([&, t] { for (int s = t; s < nsub; s += nth) plan(s); });
-            for (auto &x : th) x.join();
-        }
+        for_each_subdomain(nsub, plan);
         // concatenate: rows of subdomain s start at base[s]
         std::vector<int64_t> base(nsub + 1, 0);
         for (int s = 0; s < nsub; ++s) base[s + 1] = base[s] + (int64_t)P[s].cells.size();
         nrow = base[nsub];
         if (nrow >= ((int64_t)1 << 31)) return set_err(c, RSV_ERR_ARG, "RAS: more than 2^31 subdomain cells");
-        std::vector<int32_t> gslot(nrow), own(nrow), lcol, ucol, fo(nrow), bo(nrow);
-        std::vector<int64_t> lptr(nrow + 1), uptr(nrow + 1), lsrc, usrc, dbase(nrow), fl, bl;
+        // per subdomain: its first L / U entry and its first level boundary
+        std::vector<int64_t> lbase(nsub + 1, 0), ubase(nsub + 1, 0), fbase(nsub + 1, 0), bbase(nsub + 1, 0);
+        for (int s = 0; s < nsub; ++s) {
+            lbase[s + 1] = lbase[s] + (int64_t)P[s].lcol.size();
+            ubase[s + 1] = ubase[s] + (int64_t)P[s].ucol.size();
+            fbase[s + 1] = fbase[s] + P[s].nfl + 1;
+            bbase[s + 1] = bbase[s] + P[s].nbl + 1;
+            nfl_max = std::max(nfl_max, P[s].nfl);
+            nbl_max = std::max(nbl_max, P[s].nbl);
+        }
+        nl = lbase[nsub];
+        nu = ubase[nsub];
+        std::vector<int32_t> gslot(nrow), own(nrow), lcol(nl), ucol(nu), fo(nrow), bo(nrow);
+        std::vector<int64_t> lptr(nrow + 1), uptr(nrow + 1), lsrc(nl), usrc(nu), dbase(nrow), fl(fbase[nsub]),
+            bl(bbase[nsub]);
         std::vector<int32_t> fl_off(nsub), bl_off(nsub), fl_cnt(nsub), bl_cnt(nsub);
         auto abase = [&](int64_t cell, int slotdir) -> int64_t {   // A entry of block (cell, stencil slot) at element 0
             const int i = (int)(cell % nx), j = (int)((cell / nx) % ny), k = (int)(cell / (nx * ny));
@@ -851,7 +872,7 @@ struct RasK final : PcImpl {
             if (di == 0 && dj == 0 && dk == 1) return 6;
             return -1;
         };
-        for (int s = 0; s < nsub; ++s) {
+        for_each_subdomain(nsub, [&](int s) {
             const SubPlan &sp = P[s];
             const int64_t m = (int64_t)sp.cells.size();
             for (int64_t r = 0; r < m; ++r) {
@@ -861,46 +882,40 @@ struct RasK final : PcImpl {
                 // the owner bit, and the cell's row for error reports
                 own[g] = (int32_t)((row_of(G, i, j, k) << 1) | (sp.owned[r] ? 1 : 0));
                 dbase[g] = abase(cc, 3);
-                lptr[g] = (int64_t)lcol.size();
-                for (int32_t col : sp.lcol[r]) {
-                    lcol.push_back((int32_t)(base[s] + col));
+                lptr[g] = lbase[s] + sp.lptr[r];
+                for (int64_t q = sp.lptr[r]; q < sp.lptr[r + 1]; ++q) {
+                    const int32_t col = sp.lcol[q];
+                    lcol[lbase[s] + q] = (int32_t)(base[s] + col);
                     const int dir = stencil_dir(cc, sp.cells[col]);
-                    lsrc.push_back(dir >= 0 ? abase(cc, dir) : -1);
+                    lsrc[lbase[s] + q] = dir >= 0 ? abase(cc, dir) : -1;
                 }
-                uptr[g] = (int64_t)ucol.size();
-                for (int32_t col : sp.ucol[r]) {
-                    ucol.push_back((int32_t)(base[s] + col));
+                uptr[g] = ubase[s] + sp.uptr[r];
+                for (int64_t q = sp.uptr[r]; q < sp.uptr[r + 1]; ++q) {
+                    const int32_t col = sp.ucol[q];
+                    ucol[ubase[s] + q] = (int32_t)(base[s] + col);
                     const int dir = stencil_dir(cc, sp.cells[col]);
-                    usrc.push_back(dir >= 0 ? abase(cc, dir) : -1);
+                    usrc[ubase[s] + q] = dir >= 0 ? abase(cc, dir) : -1;
                 }
             }
-        }
-        lptr[nrow] = (int64_t)lcol.size();
-        uptr[nrow] = (int64_t)ucol.size();
-        nl = (int64_t)lcol.size();
-        nu = (int64_t)ucol.size();
-        // level schedules: rows of a subdomain bucketed by level
-        int64_t pos = 0;
-        for (int s = 0; s < nsub; ++s) {
-            const SubPlan &sp = P[s];
-            const int64_t m = (int64_t)sp.cells.size();
+            // level schedules: the subdomain's rows bucketed by level
             for (int pass = 0; pass < 2; ++pass) {
                 const std::vector<int32_t> &lv = pass ? sp.blev : sp.flev;
                 const int nlv = pass ? sp.nbl : sp.nfl;
                 std::vector<int64_t> cnt(nlv + 1, 0);
                 for (int64_t r = 0; r < m; ++r) cnt[lv[r] + 1]++;
                 for (int q = 0; q < nlv; ++q) cnt[q + 1] += cnt[q];
-                std::vector<int64_t> &bounds = pass ? bl : fl;
-                (pass ? bl_off : fl_off)[s] = (int32_t)bounds.size();
+                const int64_t b0 = pass ? bbase[s] : fbase[s];
+                (pass ? bl_off : fl_off)[s] = (int32_t)b0;
                 (pass ? bl_cnt : fl_cnt)[s] = nlv;
-                (pass ? nbl_max : nfl_max) = std::max(pass ? nbl_max : nfl_max, nlv);
-                for (int q = 0; q <= nlv; ++q) bounds.push_back(pos + cnt[q]);
+                std::vector<int64_t> &bounds = pass ? bl : fl;
+                for (int q = 0; q <= nlv; ++q) bounds[b0 + q] = base[s] + cnt[q];
                 std::vector<int32_t> &ord = pass ? bo : fo;
                 std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-                for (int64_t r = 0; r < m; ++r) ord[pos + fill[lv[r]]++] = (int32_t)(base[s] + r);
+                for (int64_t r = 0; r < m; ++r) ord[base[s] + fill[lv[r]]++] = (int32_t)(base[s] + r);
             }
-            pos += m;
-        }
+        });
+        lptr[nrow] = nl;
+        uptr[nrow] = nu;
         P.clear();
         per_level = nsub > 0 && nrow / nsub >= 256 * (int64_t)std::max(nfl_max, nbl_max);
         int32_t *dgslot, *down, *dlcol, *ducol, *dfo, *dbo, *dfloff, *dbloff, *dflcnt, *dblcnt;
@@ -994,13 +1009,7 @@ struct RasT final : PcImpl {
         nsub = px * py * pz;
         capl = capu = (p < 0) ? 3 : p;
         std::vector<Omega> O(nsub);
-        {
-            const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-            std::vector<std::thread> th;
-            for (int t = 0; t < nth; ++t)
-                th.emplace_back([&, t] { for (int s = t; s < nsub; s += nth) O[s] = omega_of(G, s, px, py, pz, ov); });
-            for (auto &x : th) x.join();
-        }
+        for_each_subdomain(nsub, [&](int s) { O[s] = omega_of(G, s, px, py, pz, ov); });
         std::vector<int64_t> base(nsub + 1, 0);
         for (int s = 0; s < nsub; ++s) base[s + 1] = base[s] + (int64_t)O[s].cells.size();
         nrow = base[nsub];
