@@ -56,17 +56,21 @@ def algorithmic_bytes(nx, ny, nz):
 
 def cpr_fpf_algorithmic_bytes(nx, ny, nz, fp32=False, coarse=128, pre=1, post=1):
     """Bytes the CPR-FPF kernels of one apply must move, the stage R's sweeps
-    excluded (they are counted with the sweeps): the two residual products
-    (stored blocks of A, x, f and the weights or r, the pressure vector), one
+    excluded (they are counted with the sweeps): the restricted residual
+    (stored blocks of A, x, f and the weights, the pressure vector out), one
     multigrid V-cycle (every level's stored coefficients, b and x per colour
-    sweep pair and per restriction, the coarsest level's inverse) and the
-    final combination (z read and written, t, e)."""
+    sweep pair and per restriction, the coarsest level's inverse), the
+    pressure correction folded into z (z_p read and written, e), the second
+    residual (blocks, x, f, r out) and the final combination (z read and
+    written, t)."""
     c = nx * ny * nz
     N = 3 * c
     ab = algorithmic_bytes(nx, ny, nz)
     wa = 36 if fp32 else 72
     wc = 4 if fp32 else 8
-    resid = wa * ab["nnzb"] + 24 * N + 8 * c
+    resid0 = wa * ab["nnzb"] + 24 * N + 8 * c
+    resid1 = wa * ab["nnzb"] + 24 * N
+    prolong = 24 * c
     dims = [(nx, ny, nz)]
     while dims[-1][0] * dims[-1][1] * dims[-1][2] > coarse:
         dims.append(tuple((v + 1) // 2 if v > 1 else 1 for v in dims[-1]))
@@ -80,9 +84,9 @@ def cpr_fpf_algorithmic_bytes(nx, ny, nz, fp32=False, coarse=128, pre=1, post=1)
         nc = dims[l + 1][0] * dims[l + 1][1] * dims[l + 1][2]
         sweep = wc * nzl + 24 * n
         mg += pre * sweep + (wc * nzl + 16 * n + 8 * nc) + post * sweep + 8 * nc
-    combine = 24 * N + 8 * c
-    return {"resid": resid, "mg": mg, "combine": combine, "apply": 2 * resid + mg + combine,
-            "levels": len(dims)}
+    combine = 24 * N
+    return {"resid": resid0 + resid1, "mg": mg, "prolong": prolong, "combine": combine,
+            "apply": resid0 + resid1 + prolong + mg + combine, "levels": len(dims)}
 
 
 def ras_algorithmic_bytes(nx, ny, nz, parts, ov):
@@ -596,10 +600,11 @@ def main():
             tab["ras"].update({"algorithmic_bytes_per_apply": apply_bytes[form], "GBps": gb,
                                "frac": round(gb / HBM_PEAK_GBS, 4)})
         if pk.get("type") == rsv.PC_CPR and kcnt["cpr"] > 0:
-            # CPR-FPF records four timed scopes per apply: the restricted
-            # residual, the V-cycle, the residual and the combination
+            # CPR-FPF records five timed scopes per apply: the restricted
+            # residual, the V-cycle, the correction of z, the residual and the
+            # combination
             cb = cpr_fpf_algorithmic_bytes(cfg.nx, cfg.ny, cfg.nz, fp32=pk.get("precision") == rsv.FP32)
-            napply = kcnt["cpr"] // 4
+            napply = kcnt["cpr"] // 5
             ms_apply = kms["cpr"] / max(napply, 1)
             tab["cpr"].update({"applies": napply, "ms_per_apply": ms_apply,
                                "algorithmic_bytes_per_apply": cb["apply"], "mg_levels": cb["levels"],

@@ -559,6 +559,18 @@ struct CprImpl : PcImpl {
         return RSV_OK;
     }
 
+    // z_p += e: the pressure correction folded into z before the residual at
+    // z + Pi_p e, which then reads no e (the same sums: x_p + e is formed in
+    // FP64 either way)
+    rsv_status prolong(double *z)
+    {
+        const Geo &g = A->g->geo;
+        ProfScope ps(c, RSV_K_CPR);
+        hipLaunchKernelGGL(k_cpr_prolong, dim3(nblk(g.nslot)), dim3(CB), 0, c->stream, g, z, (const double *)lev[0].x);
+        RSV_LAUNCH(c);
+        return RSV_OK;
+    }
+
     rsv_status combine(double *z, const double *e, int has_z)
     {
         const Geo &g = A->g->geo;
@@ -579,12 +591,7 @@ struct CprImpl : PcImpl {
             if ((s = R->apply(f, z)) != RSV_OK) return s;
             if ((s = resid(0, z, nullptr, f)) != RSV_OK) return s;
             if ((s = pressure()) != RSV_OK) return s;
-            {
-                ProfScope ps(c, RSV_K_CPR);
-                hipLaunchKernelGGL(k_cpr_prolong, dim3(nblk(g.nslot)), dim3(CB), 0, c->stream, g, z, e);
-                RSV_LAUNCH(c);
-            }
-            return RSV_OK;
+            return prolong(z);
         case RSV_CPR_PF:
             {
                 ProfScope ps(c, RSV_K_CPR);
@@ -600,9 +607,10 @@ struct CprImpl : PcImpl {
             if ((s = R->apply(f, z)) != RSV_OK) return s;
             if ((s = resid(0, z, nullptr, f)) != RSV_OK) return s;
             if ((s = pressure()) != RSV_OK) return s;
-            if ((s = resid(1, z, e, f)) != RSV_OK) return s;
+            if ((s = prolong(z)) != RSV_OK) return s;
+            if ((s = resid(1, z, nullptr, f)) != RSV_OK) return s;
             if ((s = R->apply(r, t)) != RSV_OK) return s;
-            return combine(z, e, 1);
+            return combine(z, nullptr, 1);
         case RSV_CPR_FFPF:
             if ((s = R->apply(f, z)) != RSV_OK) return s;
             if ((s = resid(1, z, nullptr, f)) != RSV_OK) return s;
@@ -610,9 +618,10 @@ struct CprImpl : PcImpl {
             if ((s = combine(z, nullptr, 1)) != RSV_OK) return s;
             if ((s = resid(0, z, nullptr, f)) != RSV_OK) return s;
             if ((s = pressure()) != RSV_OK) return s;
-            if ((s = resid(1, z, e, f)) != RSV_OK) return s;
+            if ((s = prolong(z)) != RSV_OK) return s;
+            if ((s = resid(1, z, nullptr, f)) != RSV_OK) return s;
             if ((s = R->apply(r, t)) != RSV_OK) return s;
-            return combine(z, e, 1);
+            return combine(z, nullptr, 1);
         default: return set_err(c, RSV_ERR_ARG, "bad CPR variant");
         }
     }
