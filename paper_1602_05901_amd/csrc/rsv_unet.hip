@@ -24,6 +24,8 @@
 #include <new>
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -64,8 +66,9 @@ struct Arch {
         }
         np = off;
     }
-    int kb(int l) const { return (27 * cin[l] + 15) / 16; }        // K blocks, forward
-    int kbt(int l) const { return (27 * cout[l] + 15) / 16; }      // K blocks, backward data
+    // K blocks (of 32 for inputs with a multiple of 8 channels, else 16): forward, backward data
+    int kb(int l) const { return (27 * cin[l] + (cin[l] % 8 ? 15 : 31)) / (cin[l] % 8 ? 16 : 32); }
+    int kbt(int l) const { return (27 * cout[l] + (cout[l] % 8 ? 15 : 31)) / (cout[l] % 8 ? 16 : 32); }
 };
 
 struct ConvGeo {
@@ -87,23 +90,40 @@ __device__ inline int64_t src_voxel(const ConvGeo &g, int x, int y, int z, int d
 }
 
 // ---------------------------------------------------------------- convolution as implicit GEMM
+// K per MFMA: 32 (v_mfma_f32_16x16x32_bf16, 8 k per lane) when the input has a
+// multiple of 8 channels, so that a lane's 8 consecutive k are 8 channels of
+// one tap; else 16 (v_mfma_f32_16x16x16_bf16, 4 k per lane).
+__host__ __device__ constexpr int conv_kw(int cin) { return cin % 8 == 0 ? 32 : 16; }
+__host__ __device__ constexpr int conv_kblocks(int cin) { return (27 * cin + conv_kw(cin) - 1) / conv_kw(cin); }
+// bytes of one lane's packed weight fragment
+__host__ __device__ constexpr int conv_frag_bytes(int cin) { return conv_kw(cin) / 2; }
+template <bool K32> struct Frag { using T = v4s; static constexpr int KW = 16; };
+template <> struct Frag<true> { using T = v8s; static constexpr int KW = 32; };
+__device__ inline v4f mfma_k(v4s a, v4s b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+__device__ inline v4f mfma_k(v8s a, v8s b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+
 // One wavefront: 16*MB output voxels x (16*NB) output channels.  GEMM row m =
-// voxel, column n = output channel, k = tap*cin + ci.  Operand fragments of
-// v_mfma_f32_16x16x16_bf16: lane l holds A[m = l%16][k = 4*(l/16) .. +3] and
-// B[k = 4*(l/16) .. +3][n = l%16]; the result holds D[m = 4*(l/16) + i][n = l%16].
-// Weights are pre-packed so that B fragments are one 8-byte load per lane; an A
-// fragment (16 consecutive voxels x 16 k) is one contiguous 512-byte row of
-// the channels-last input when the tap keeps the voxels inside the grid row.
-// Each B fragment feeds MB products and each A fragment NB.
-template <int MB, int NB, bool OUT_BF16>
-__global__ __launch_bounds__(256) void k_conv(ConvGeo g, const uint16_t *__restrict__ X, const v4s *__restrict__ Wf,
+// voxel, column n = output channel, k = tap*cin + ci.  Operand fragments
+// (KW = 16 or 32, w = KW / 4 k per lane): lane l holds A[m = l%16][k = w*(l/16)
+// .. + w-1] and B[k = w*(l/16) .. + w-1][n = l%16]; the result holds
+// D[m = 4*(l/16) + i][n = l%16].  Weights are pre-packed so that B fragments
+// are one load per lane; an A fragment's lane reads w consecutive channels of
+// one voxel.  Each B fragment feeds MB products and each A fragment NB.
+template <int MB, int NB, bool OUT_BF16, bool K32>
+__global__ __launch_bounds__(256) void k_conv(ConvGeo g, const uint16_t *__restrict__ X, const void *__restrict__ Wfv,
                                               int KB, const float *__restrict__ bias,
                                               const uint16_t *__restrict__ skip, int relu, void *__restrict__ out)
 {
+    using FT = typename Frag<K32>::T;
+    constexpr int KW = Frag<K32>::KW;
+    const FT *Wf = (const FT *)Wfv;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t v0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MB);
     if (v0 >= g.V) return;
-    const int m = lane & 15, kq = 4 * (lane >> 4);
+    const int m = lane & 15, kq = (KW / 4) * (lane >> 4);
     int px[MB], py[MB], pz[MB];
     bool live[MB];   // the last tile of a level may be partial
 #pragma unroll
@@ -121,25 +141,24 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const uint16_t *__restr
         for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
     const int K = 27 * g.cin;
     for (int kb = 0; kb < KB; ++kb) {
-        const int k = kb * 16 + kq;
+        const int k = kb * KW + kq;
         const bool kin = k < K;
         const int tap = kin ? k / g.cin : 0, ci = k - tap * g.cin;
         const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        v4s a[MB];
+        FT a[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-            a[mb] = v4s{0, 0, 0, 0};
+            a[mb] = FT{};
             if (kin && live[mb]) {
                 const int64_t u = src_voxel(g, px[mb], py[mb], pz[mb], dx, dy, dz);
-                if (u >= 0) a[mb] = *(const v4s *)(X + u * g.cin + ci);
+                if (u >= 0) a[mb] = *(const FT *)(X + u * g.cin + ci);
             }
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const v4s b = Wf[((int64_t)kb * NB + nb) * 64 + lane];
+            const FT b = Wf[((int64_t)kb * NB + nb) * 64 + lane];
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], b, acc[mb][nb], 0, 0, 0);
+            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma_k(a[mb], b, acc[mb][nb]);
         }
     }
     const int n = lane & 15, mr = 4 * (lane >> 4);
@@ -170,7 +189,10 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const uint16_t *__restr
 constexpr int CT_X = 16, CT_Y = 4, CT_Z = 4, CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2;
 constexpr int CH_N = CH_X * CH_Y * CH_Z;   // 648 halo voxels
 
-inline size_t conv_lds_bytes(int cin, int KB, int NB) { return (size_t)CH_N * cin * 2 + (size_t)KB * NB * 64 * sizeof(v4s); }
+inline size_t conv_lds_bytes(int cin, int KB, int NB)
+{
+    return (size_t)CH_N * cin * 2 + (size_t)KB * NB * 64 * conv_frag_bytes(cin);
+}
 
 // Global -> LDS copy of n 16-byte words by the workgroup, eight loads in
 // flight per thread before their stores.
@@ -200,18 +222,21 @@ __device__ inline void stage_words(const v4s *__restrict__ src, v4s *dst, int n)
 // critical path.  Wave w owns output plane z0 + w; its voxel block mb is the
 // x-run at y0 + mb.
 template <int NB, bool OUT_BF16, int CIN>
-__global__ __launch_bounds__(256) void k_conv_lds(ConvGeo g, const uint16_t *__restrict__ X, const v4s *__restrict__ Wf,
+__global__ __launch_bounds__(256) void k_conv_lds(ConvGeo g, const uint16_t *__restrict__ X, const void *__restrict__ Wfv,
                                                   int KB, const float *__restrict__ bias,
                                                   const uint16_t *__restrict__ skip, int relu, void *__restrict__ out)
 {
+    constexpr bool K32 = CIN % 8 == 0;
+    using FT = typename Frag<K32>::T;
+    constexpr int KW = Frag<K32>::KW;
     constexpr int C4 = CIN / 4, NI = (CH_N * C4 + 255) / 256;   // halo words (4 channels) per thread
     extern __shared__ __align__(16) unsigned char cl[];
-    v4s *wl = (v4s *)cl;                                        // [KB][NB][64]
-    uint16_t *xl = (uint16_t *)(cl + (size_t)KB * NB * 64 * sizeof(v4s));   // [648][CIN]
+    FT *wl = (FT *)cl;                                          // [KB][NB][64]
+    uint16_t *xl = (uint16_t *)(cl + (size_t)KB * NB * 64 * sizeof(FT));   // [648][CIN]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ntx = (g.nx + CT_X - 1) / CT_X, nty = (g.ny + CT_Y - 1) / CT_Y, ntz = (g.nz + CT_Z - 1) / CT_Z;
     const int nbricks = ntx * nty * ntz;
-    stage_words(Wf, wl, KB * NB * 64);
+    stage_words((const v4s *)Wfv, (v4s *)wl, KB * NB * 64 * (int)(sizeof(FT) / sizeof(v4s)));
     v4s hv[NI];
     auto load = [&](int b) {
         const int x0 = (b % ntx) * CT_X, y0 = ((b / ntx) % nty) * CT_Y, z0 = (b / (ntx * nty)) * CT_Z;
@@ -227,7 +252,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvGeo g, const uint16_t *__r
             }
         }
     };
-    const int m = lane & 15, kq = 4 * (lane >> 4);
+    const int m = lane & 15, kq = (KW / 4) * (lane >> 4);
     const int n = lane & 15, mr = 4 * (lane >> 4);
     const int K = 27 * CIN;
     if (blockIdx.x < nbricks) load(blockIdx.x);
@@ -247,22 +272,21 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvGeo g, const uint16_t *__r
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = v4f{0.f, 0.f, 0.f, 0.f};
         for (int kb = 0; kb < KB; ++kb) {
-            const int k = kb * 16 + kq;
+            const int k = kb * KW + kq;
             const bool kin = k < K;
             const int tap = kin ? k / CIN : 0, ci = k - tap * CIN;
             const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo offsets (0..2)
-            v4s a[CT_Y];
+            FT a[CT_Y];
 #pragma unroll
             for (int mb = 0; mb < CT_Y; ++mb) {
                 const int h = ((wave + dz) * CH_Y + (mb + dy)) * CH_X + (m + dx);
-                a[mb] = kin ? *(const v4s *)(xl + (size_t)h * CIN + ci) : v4s{0, 0, 0, 0};
+                a[mb] = kin ? *(const FT *)(xl + (size_t)h * CIN + ci) : FT{};
             }
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const v4s bf = wl[(kb * NB + nb) * 64 + lane];
+                const FT bf = wl[(kb * NB + nb) * 64 + lane];
 #pragma unroll
-                for (int mb = 0; mb < CT_Y; ++mb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], bf, acc[mb][nb], 0, 0, 0);
+                for (int mb = 0; mb < CT_Y; ++mb) acc[mb][nb] = mfma_k(a[mb], bf, acc[mb][nb]);
             }
         }
         // epilogue: the skip inputs are loaded together, then bias, skip, ReLU, store
@@ -306,7 +330,7 @@ constexpr size_t CONV_LDS_MAX = 96 * 1024;
 // launch of k_conv: NB = cout / 16 column blocks; 4 voxel blocks per wave on
 // large levels (weight fragments reused four times), 1 on small ones (more waves)
 template <bool OUT_BF16>
-hipError_t launch_conv(hipStream_t st, const ConvGeo &g, const uint16_t *X, const v4s *Wf, int KB, const float *bias,
+hipError_t launch_conv(hipStream_t st, const ConvGeo &g, const uint16_t *X, const void *Wf, int KB, const float *bias,
                        const uint16_t *skip, int relu, void *out)
 {
     const int NB = (g.cout + 15) / 16;
@@ -345,7 +369,13 @@ hipError_t launch_conv(hipStream_t st, const ConvGeo &g, const uint16_t *X, cons
     const int MB = g.V >= 131072 ? 4 : 1;
     const int64_t waves = (g.V + 16 * MB - 1) / (16 * MB);
     const dim3 grid((unsigned)((waves + 3) / 4)), blk(256);
-#define RSV_CONV(mb, nb) hipLaunchKernelGGL((k_conv<mb, nb, OUT_BF16>), grid, blk, 0, st, g, X, Wf, KB, bias, skip, relu, out)
+#define RSV_CONV(mb, nb)                                                                                                \
+    do {                                                                                                                \
+        if (g.cin % 8 == 0)                                                                                             \
+            hipLaunchKernelGGL((k_conv<mb, nb, OUT_BF16, true>), grid, blk, 0, st, g, X, Wf, KB, bias, skip, relu, out);  \
+        else                                                                                                            \
+            hipLaunchKernelGGL((k_conv<mb, nb, OUT_BF16, false>), grid, blk, 0, st, g, X, Wf, KB, bias, skip, relu, out); \
+    } while (0)
     if (MB == 4) {
         if (NB == 1) RSV_CONV(4, 1);
         else if (NB == 2) RSV_CONV(4, 2);
@@ -387,9 +417,6 @@ constexpr int DW_MAXCHUNK = 256;              // chunks per pair (16 groups of a
 constexpr int DW_XU = CH_Z * CH_Y * 2 * 4;    // input staging units: (halo row, x octet, channel quad) = 288
 constexpr size_t DW_LDS = (size_t)(3 * 16 * DW_XS + 16 * DW_GS) * 2;
 static_assert(DW_LDS >= 256 * 16 * sizeof(float), "the bias reduction reuses the staging area");
-
-typedef short v8s __attribute__((ext_vector_type(8)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 struct DwRegs {
     v4s x[2][10];   // input units: 10 voxels (x octet + 2) x 4 channels
@@ -806,32 +833,32 @@ __global__ void k_adam(int64_t n, float *__restrict__ p, const float *__restrict
     }
 }
 
-// pack W[tap][ci][co] (FP32) into B fragments: forward (k = tap*cin + ci, n = co)
-// or transposed for the data gradient (k = tap'*cout + co with tap' = 26 - tap, n = ci)
-__global__ void k_pack(const float *__restrict__ W, int cin, int cout, int transposed, int KB, int NB,
-                       v4s *__restrict__ Wf)
+// pack W[tap][ci][co] (FP32) into B fragments of kw k per block (kw / 4 per
+// lane): forward (k = tap*cin + ci, n = co) or transposed for the data
+// gradient (k = tap'*cout + co with tap' = 26 - tap, n = ci)
+__global__ void k_pack(const float *__restrict__ W, int cin, int cout, int transposed, int KB, int NB, int kw,
+                       short *__restrict__ Wf)
 {
     const int64_t n = (int64_t)KB * NB * 64;
+    const int w = kw / 4;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
         const int lane = (int)(e % 64);
         const int nb = (int)((e / 64) % NB);
         const int kb = (int)(e / (64 * NB));
         const int col = nb * 16 + (lane & 15);
-        v4s frag;
-        for (int i = 0; i < 4; ++i) {
-            const int k = kb * 16 + 4 * (lane >> 4) + i;
-            float w = 0.f;
+        for (int i = 0; i < w; ++i) {
+            const int k = kb * kw + w * (lane >> 4) + i;
+            float wv = 0.f;
             if (!transposed) {
-                if (k < 27 * cin && col < cout) w = W[(int64_t)k * cout + col];   // k = tap*cin + ci
+                if (k < 27 * cin && col < cout) wv = W[(int64_t)k * cout + col];   // k = tap*cin + ci
             } else {
                 if (k < 27 * cout && col < cin) {
                     const int tp = k / cout, co = k - tp * cout;
-                    w = W[((int64_t)(26 - tp) * cin + col) * cout + co];
+                    wv = W[((int64_t)(26 - tp) * cin + col) * cout + co];
                 }
             }
-            frag[i] = (short)f2bf(w);
+            Wf[e * w + i] = (short)f2bf(wv);
         }
-        Wf[e] = frag;
     }
 }
 
@@ -903,10 +930,11 @@ static rsv_status net_pack(rsv_net *n)
     for (int l = 0; l < 10; ++l) {
         const int NB = n->a.cout[l] / 16, NBt = (n->a.cin[l] + 15) / 16;
         hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)n->a.kb(l) * NB * 64)), dim3(256), 0, c->stream, n->P + n->a.woff[l],
-                           n->a.cin[l], n->a.cout[l], 0, n->a.kb(l), NB, n->wf[l]);
+                           n->a.cin[l], n->a.cout[l], 0, n->a.kb(l), NB, conv_kw(n->a.cin[l]), (short *)n->wf[l]);
         if (l > 0)
             hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)n->a.kbt(l) * NBt * 64)), dim3(256), 0, c->stream,
-                               n->P + n->a.woff[l], n->a.cin[l], n->a.cout[l], 1, n->a.kbt(l), NBt, n->wt[l]);
+                               n->P + n->a.woff[l], n->a.cin[l], n->a.cout[l], 1, n->a.kbt(l), NBt, conv_kw(n->a.cout[l]),
+                               (short *)n->wt[l]);
     }
     RSV_LAUNCH(c);
     n->packed = true;
@@ -1223,9 +1251,10 @@ rsv_status rsv_net_create(rsv_ctx *c, const rsv_net_arch *arch, uint64_t seed, r
     if (s == RSV_OK) s = dev_alloc(c, (void **)&n->Vv, pb);
     if (s == RSV_OK) s = dev_alloc(c, (void **)&n->d_sc, 8 * sizeof(double));
     for (int l = 0; l < 10 && s == RSV_OK; ++l) {
-        s = dev_alloc(c, (void **)&n->wf[l], (size_t)n->a.kb(l) * (n->a.cout[l] / 16) * 64 * sizeof(v4s));
+        s = dev_alloc(c, (void **)&n->wf[l], (size_t)n->a.kb(l) * (n->a.cout[l] / 16) * 64 * conv_frag_bytes(n->a.cin[l]));
         if (s == RSV_OK)
-            s = dev_alloc(c, (void **)&n->wt[l], (size_t)n->a.kbt(l) * ((n->a.cin[l] + 15) / 16) * 64 * sizeof(v4s));
+            s = dev_alloc(c, (void **)&n->wt[l],
+                          (size_t)n->a.kbt(l) * ((n->a.cin[l] + 15) / 16) * 64 * conv_frag_bytes(n->a.cout[l]));
     }
     if (s != RSV_OK) { delete n; return s; }
     // He-uniform init; the final layer is scaled by 0.1 so an untrained net starts small
@@ -1411,11 +1440,12 @@ rsv_status rsv_conv3d(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32_t ci
     if (!c || !x || !w || !y) return set_err(c, RSV_ERR_ARG, "NULL argument");
     if (cin % 4 || cin < 4 || cin > 64 || (cout != 16 && cout != 32 && cout != 64) || nx < 1 || ny < 1 || nz < 1)
         return set_err(c, RSV_ERR_ARG, "conv3d needs cin a multiple of 4 up to 64, cout 16/32/64, positive dims");
-    const int KB = (27 * cin + 15) / 16, NB = cout / 16;
-    v4s *wf = nullptr;
-    rsv_status s = dev_alloc(c, (void **)&wf, (size_t)KB * NB * 64 * sizeof(v4s));
+    const int KB = conv_kblocks(cin), NB = cout / 16;
+    short *wf = nullptr;
+    rsv_status s = dev_alloc(c, (void **)&wf, (size_t)KB * NB * 64 * conv_frag_bytes(cin));
     if (s != RSV_OK) return s;
-    hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)KB * NB * 64)), dim3(256), 0, c->stream, w, cin, cout, 0, KB, NB, wf);
+    hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)KB * NB * 64)), dim3(256), 0, c->stream, w, cin, cout, 0, KB, NB,
+                       conv_kw(cin), wf);
     ConvGeo g{nx, ny, nz, 0, cin, cout, (int64_t)nx * ny * nz};
     hipError_t e = launch_conv<false>(c->stream, g, x, wf, KB, b, nullptr, 0, y);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1437,14 +1467,14 @@ rsv_status rsv_conv3d_bwd(rsv_ctx *c, int32_t nx, int32_t ny, int32_t nz, int32_
     tmp.a.init(16, 16, 16);
     tmp.a.cin[1] = cin;
     tmp.a.cout[1] = cout;
-    const int KBt = (27 * cout + 15) / 16, NBt = (cin + 15) / 16;
+    const int KBt = conv_kblocks(cout), NBt = (cin + 15) / 16;
     rsv_status s = RSV_OK;
     ConvGeo g{nx, ny, nz, 0, cin, cout, (int64_t)nx * ny * nz};
     if (dx) {
-        s = dev_alloc(c, (void **)&tmp.wt[1], (size_t)KBt * NBt * 64 * sizeof(v4s));
+        s = dev_alloc(c, (void **)&tmp.wt[1], (size_t)KBt * NBt * 64 * conv_frag_bytes(cout));
         if (s == RSV_OK) {
             hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)KBt * NBt * 64)), dim3(256), 0, c->stream, w, cin, cout, 1, KBt,
-                               NBt, tmp.wt[1]);
+                               NBt, conv_kw(cout), (short *)tmp.wt[1]);
             s = conv_bwd_data(&tmp, 1, nx, ny, nz, dy, dx);
         }
     }
