@@ -258,8 +258,11 @@ rsv_status launch_copy(rsv_ctx *c, int64_t n, const double *x, double *y);
 rsv_status launch_scale_dev(rsv_ctx *c, int64_t n, double *x, int k_norm2);   // x /= sqrt(sc[k]) (0 -> 0)
 rsv_status launch_axpby(rsv_ctx *c, int64_t n, double a, const double *x, double b, double *y); // y = a x + b y
 rsv_status launch_mdot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, const double *w, int k0);
+// CGS2's second pass: dots of V_i with w - V c (c = scalars kc..), w unchanged
 rsv_status launch_upd_dot(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0);
-rsv_status launch_upd_norm(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc, int k0);
+// CGS2's third pass: w <- (w - V c1) - V c2 (scalars kc1.., kc2..) and w . w
+rsv_status launch_upd_norm(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, double *w, int kc1, int kc2,
+                           int k0);
 rsv_status launch_combine(rsv_ctx *c, int64_t n, const double *V, int64_t ldv, int K, int ky, double *u, int accumulate);
 // Fixed per-device scratch of the entry points that allocate nothing
 // (RSV_NOALLOC_SCRATCH_BYTES in rsv.h), in doubles.

@@ -239,7 +239,7 @@ static rsv_status gmres(Solve &S, PcImpl *P, PcImpl *FB, double theta, int m, in
                 if (e == RSV_OK) e = mat_spmv(S.M, SPMV_NORM, zt, w, nullptr, 0, 0, SC_W0);
                 if (e == RSV_OK) e = launch_mdot(c, n, V, n, j + 1, w, SC_H1);
                 if (e == RSV_OK) e = launch_upd_dot(c, n, V, n, j + 1, w, SC_H1, SC_H2);
-                if (e == RSV_OK) e = launch_upd_norm(c, n, V, n, j + 1, w, SC_H2, SC_HN);
+                if (e == RSV_OK) e = launch_upd_norm(c, n, V, n, j + 1, w, SC_H1, SC_H2, SC_HN);
                 if (e == RSV_OK) e = launch_scale_dev(c, n, w, SC_HN);
                 if (e == RSV_OK) e = scal_to_host_async(c, j & 1, 0, SC_H2 + j + 1);
                 return e;
@@ -287,7 +287,7 @@ static rsv_status gmres(Solve &S, PcImpl *P, PcImpl *FB, double theta, int m, in
                 s = mat_spmv(S.M, SPMV_NORM, z, w, nullptr, 0, 0, SC_W0);
                 if (s == RSV_OK) s = launch_mdot(c, n, V, n, j + 1, w, SC_H1);
                 if (s == RSV_OK) s = launch_upd_dot(c, n, V, n, j + 1, w, SC_H1, SC_H2);
-                if (s == RSV_OK) s = launch_upd_norm(c, n, V, n, j + 1, w, SC_H2, SC_HN);
+                if (s == RSV_OK) s = launch_upd_norm(c, n, V, n, j + 1, w, SC_H1, SC_H2, SC_HN);
                 if (s == RSV_OK) s = launch_scale_dev(c, n, w, SC_HN);
                 if (s == RSV_OK) s = scal_to_host(c, 0, SC_H2 + j + 1);
                 if (s != RSV_OK) return s;
