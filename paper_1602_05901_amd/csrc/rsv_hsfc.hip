@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_scan_tile(const uint32_t *__restrict__ 
     t[threadIdx.x] = s;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {   // inclusive scan of the thread totals
-        const uint32_t a = (threadIdx.x >= off) ? t[threadIdx.x - off] : 0u;
+        const uint32_t a = ((int)threadIdx.x >= off) ? t[threadIdx.x - off] : 0u;
         __syncthreads();
         t[threadIdx.x] += a;
         __syncthreads();

@@ -263,9 +263,6 @@ __device__ inline void face_st(uint64_t *p, uint64_t v)
 __device__ inline uint32_t half_bits(double v, int h) { return (uint32_t)((uint64_t)__double_as_longlong(v) >> (32 * h)); }
 __device__ inline uint32_t half_bits(float v, int) { return __float_as_uint(v); }
 
-__device__ inline double shfl_d(double v, int src) { return __shfl(v, src, 64); }
-__device__ inline float shfl_d(float v, int src) { return __shfl(v, src, 64); }
-
 // Spin-loop guard: checks the clock and the shared error flag only every 256th
 // call (the flag read is a device-scope load, which waits for every memory
 // operation the wave still has in flight).

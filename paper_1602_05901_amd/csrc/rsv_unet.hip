@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvGeo g, const uint16_t *__r
     const int m = lane & 15, kq = (KW / 4) * (lane >> 4);
     const int n = lane & 15, mr = 4 * (lane >> 4);
     const int K = 27 * CIN;
-    if (blockIdx.x < nbricks) load(blockIdx.x);
+    if ((int)blockIdx.x < nbricks) load(blockIdx.x);
     for (int b = blockIdx.x; b < nbricks; b += gridDim.x) {
         const int x0 = (b % ntx) * CT_X, y0 = ((b / ntx) % nty) * CT_Y, z0 = (b / (ntx * nty)) * CT_Z;
         __syncthreads();   // the previous brick's operands have been read (and the weights written)
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(256) void k_final_dw(int64_t V, int C, int64_t chun
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * nw + q] = red[0];
@@ -800,7 +800,7 @@ __global__ __launch_bounds__(256) void k_loss(Geo geo, const float *__restrict__
     r1[threadIdx.x] = b;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) { r0[threadIdx.x] += r0[threadIdx.x + w]; r1[threadIdx.x] += r1[threadIdx.x + w]; }
+        if ((int)threadIdx.x < w) { r0[threadIdx.x] += r0[threadIdx.x + w]; r1[threadIdx.x] += r1[threadIdx.x + w]; }
         __syncthreads();
     }
     if (threadIdx.x == 0) { partials[2 * blockIdx.x] = r0[0]; partials[2 * blockIdx.x + 1] = r1[0]; }
