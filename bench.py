@@ -327,8 +327,8 @@ def poisson_measure(rsv, ctx, dims, parts, its=90, reps=3, cpu=True):
         kern["spmv"]["GBps"] = spmv_bytes / (kern["spmv"]["avg_us"] * 1e-6) / 1e9
     ras_bytes = M.apply_bytes
     if "ras" in kern and ras_bytes > 0:
-        # one apply moves every Omega_s entry's ids and coefficients once and
-        # five vector passes over the entries (the library's own count)
+        # the library's own count of one apply: per Omega_s cell its factors
+        # and three vector passes, per grid cell the result, per x-chunk its ids
         gbps = ras_bytes / (kern["ras"]["avg_us"] * 1e-6) / 1e9
         kern["ras"].update({"algorithmic_bytes": ras_bytes, "GBps": round(gbps, 1),
                             "frac": round(gbps / HBM_PEAK_GBS, 4)})
