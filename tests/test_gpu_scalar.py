@@ -87,8 +87,9 @@ def test_scalar_spmv_per_entry(rsv, ctx, dims, sigma):
     T.close()
 
 
-def test_scalar_top_down_numbering(rsv, ctx):
-    dims = (6, 5, 4)
+@pytest.mark.parametrize("dims,parts", [((6, 5, 4), (2, 2, 2)), ((37, 9, 6), (2, 1, 2))])
+def test_scalar_top_down_numbering(rsv, ctx, dims, parts):
+    # the second grid puts several 8-cell x-chunks in a row of every subdomain
     nx, ny, nz = dims
     cfg, C, Ao = system(dims, 1.0, 3)
     c = np.arange(cfg.ncell)
@@ -105,13 +106,13 @@ def test_scalar_top_down_numbering(rsv, ctx):
     y = torch.zeros(cfg.ncell, dtype=torch.float64, device="cuda")
     A.spmv(dev(xt), y)
     assert np.allclose(y.cpu().numpy()[perm], Ao.spmv(x), rtol=1e-13, atol=1e-13)
-    M = rsv.Precond(A, type=rsv.PC_RAS, ras_px=2, ras_py=2, ras_pz=2, ras_overlap=1)
+    M = rsv.Precond(A, type=rsv.PC_RAS, ras_px=parts[0], ras_py=parts[1], ras_pz=parts[2], ras_overlap=1)
     r = I.test_vector(10, cfg.ncell)
     rt = np.empty_like(r)
     rt[perm] = r
     z = torch.zeros_like(y)
     M.apply(dev(rt), z)
-    ref = S.RAS(Ao, dims, (2, 2, 2), 1).apply(r)
+    ref = S.RAS(Ao, dims, parts, 1).apply(r)
     assert np.max(np.abs(z.cpu().numpy()[perm] - ref)) <= 1e-12 * np.max(np.abs(ref))
     M.close(); A.close(); g.close()
 
