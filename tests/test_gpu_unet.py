@@ -97,7 +97,10 @@ def net_params(seed, ch=(16, 32, 64), bias=0.05):
 # (four voxel blocks per wave; the second with a partial last block)
 CONV_CASES = [((8, 8, 4), 4, 16), ((8, 8, 4), 16, 16), ((6, 5, 3), 16, 32), ((4, 4, 4), 32, 64),
               ((4, 4, 2), 64, 32), ((5, 3, 7), 64, 64), ((16, 16, 8), 16, 16), ((3, 1, 1), 4, 32),
-              ((64, 64, 32), 4, 16), ((65, 45, 45), 16, 32)]
+              ((64, 64, 32), 4, 16), ((65, 45, 45), 16, 32),
+              # 8 and 24 input channels (8 per lane of a 16x16x32 MFMA), 12 (4 per lane of a
+              # 16x16x16 MFMA), 32 on a grid large enough for the LDS-staged kernel
+              ((9, 7, 5), 8, 16), ((10, 9, 8), 24, 64), ((7, 6, 5), 12, 32), ((20, 18, 16), 32, 16)]
 
 
 @pytest.mark.parametrize("dims,cin,cout", CONV_CASES)
