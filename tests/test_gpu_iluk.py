@@ -119,6 +119,25 @@ def test_ras_iluk_apply(rsv, ctx, dims, parts, ov, k, shift):
     M.close(); A.close(); g.close()
 
 
+def test_ras_iluk_apply_large_subdomains(rsv, ctx):
+    """Two RAS subdomains of 49x64x32 cells: over 256 rows per level on
+    average, so the apply runs one launch per level for both subdomains at
+    once (grid.y = subdomain); two applies over the same schedules."""
+    dims, parts = (96, 64, 32), (2, 1, 1)
+    cfg, B, Ao, g = sysm(rsv, ctx, dims, 9)
+    A = rsv.Matrix(g, dev(B))
+    M = rsv.Precond(A, type=rsv.PC_RAS, ras_px=parts[0], ras_py=parts[1], ras_pz=parts[2], ras_overlap=1,
+                    iluk_level=1)
+    n = 3 * cfg.ncell
+    r = I.test_vector(10, n)
+    z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    M.apply(dev(r), z)
+    M.apply(dev(r), z)
+    ref = O.RAS(Ao, dims, parts, 1, level=1).apply(r)
+    assert np.max(np.abs(z.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+    M.close(); A.close(); g.close()
+
+
 def test_ras_iluk_top_down_numbering(rsv, ctx):
     dims = (10, 9, 6)
     nx, ny, nz = dims

@@ -112,6 +112,23 @@ def test_ilut_apply_large_subdomain(rsv, ctx):
     A.close(); g.close()
 
 
+def test_ras_ilut_apply_large_subdomains(rsv, ctx):
+    """Two RAS subdomains of 49x64x32 cells with ILUT(-1, 1e-3) local
+    factors: the size at which the apply takes one launch per level."""
+    dims, parts = (96, 64, 32), (2, 1, 1)
+    cfg, B, Ao, g = sysm(rsv, ctx, dims, 15, 2.0)
+    A = rsv.Matrix(g, dev(B))
+    n = 3 * cfg.ncell
+    r = I.test_vector(16, n)
+    z = apply_gpu(rsv, A, n, r, type=rsv.PC_RAS, ras_px=parts[0], ras_py=parts[1], ras_pz=parts[2],
+                  ras_overlap=1, ilut_p=-1, ilut_tol=1e-3)
+    ref = O.RAS(Ao, dims, parts, 1, ilut=(-1, 1e-3)).apply(r)
+    err = np.max(np.abs(z - ref)) / np.max(np.abs(ref))
+    log("  error", err)
+    assert err <= bar_of(2.0, ref, r)
+    A.close(); g.close()
+
+
 @pytest.mark.parametrize("dims,parts,ov", [((20, 20, 10), (2, 2, 2), 1), ((13, 9, 5), (3, 2, 1), 1),
                                            ((17, 3, 19), (2, 1, 3), 2), ((9, 16, 33), (1, 2, 4), 0),
                                            ((32, 32, 16), (4, 4, 4), 1)])
