@@ -749,6 +749,24 @@ def test_gmres_dcgs2_fp32_factors(rsv, ctx):
     check_solve(st, ref, xg, relres, hist_rtol=1e-5)
 
 
+@pytest.mark.parametrize("restart", [60, 45])
+def test_gmres_cgs2_long_cycles(rsv, ctx, restart):
+    """CGS2 with 45 and 60 basis vectors per cycle: the widest multi-vector
+    kernel instances (up to 64 vectors, both coefficient sets of the third
+    pass held at once), against the oracle's CGS2 GMRES of the same length."""
+    cfg = cfg_of((6, 5, 4), seed=17)
+    S = Sys(rsv, ctx, cfg)
+    n = 3 * cfg.ncell
+    b = dev(I.test_vector(18, n))
+    bo = b.cpu().numpy()
+    x = torch.zeros_like(b)
+    st = rsv.solve(S.A, None, b, x, method=rsv.GMRES, restart=restart, tol=1e-10, maxit=2000, record_history=1)
+    ref = O.gmres(S.Ao, bo, pc=None, m=restart, tol=1e-10, maxit=2000, hist=True)
+    assert st["status"] == 0 and abs(st["its"] - ref["its"]) <= max(2, 0.05 * ref["its"])
+    assert np.linalg.norm(bo - S.Ao.spmv(x.cpu().numpy())) / np.linalg.norm(bo) <= 1e-10
+    assert np.allclose(st["hist"][:40], ref["hist"][:40], rtol=1e-8, atol=0)
+
+
 def test_gmres_dcgs2_unpreconditioned_and_edges(rsv, ctx):
     """No preconditioner (many steps per cycle, slow decay), b = 0, maxit
     exhaustion at a step inside a cycle, the exact preconditioner (the second
