@@ -234,7 +234,9 @@ __global__ __launch_bounds__(BS) void k_factors_to_rows(Geo g, const double *__r
 // s + 7.  FP64 values are split into 32-bit halves, each stored with the
 // 32-bit call epoch in the upper half of a 64-bit word (FP32 values: one
 // word), so a word is valid exactly when its tag equals the current epoch --
-// no fences between tiles, no clearing between calls.  Word (p*W + h)*8 + e
+// no fences between tiles, no clearing between calls (the buffers are cleared
+// once, when allocated: memory another object wrote, possibly under another
+// context's epochs, could otherwise hold a word with a matching tag).  Word (p*W + h)*8 + e
 // of a row holds half h of component p of entry e.  The compute wave writes
 // a whole face row with one store instruction (for the same reason, the
 // number of store instructions, not their width, sets their cost): lane q
@@ -737,6 +739,12 @@ inline size_t sweep_lds_bytes(int dir, int D)
     return (size_t)D * sweep_slot_bytes<T>(dir) + 64 * sizeof(int32_t);
 }
 
+// zero n 64-bit words
+__global__ __launch_bounds__(256) void k_zero_words(int64_t n, uint64_t *__restrict__ p)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0ull;
+}
+
 // ---------------------------------------------------------------- the preconditioner object
 
 struct Bilu0 : PcImpl {
@@ -750,6 +758,7 @@ struct Bilu0 : PcImpl {
     float *zt32 = nullptr;                       // FP32 z for the per-plane path
     double *zt64 = nullptr;
     uint64_t *faceX = nullptr, *faceY = nullptr;
+    int64_t face_words = 0;                      // words per face buffer
     int32_t *tile_order = nullptr;
     int64_t nbytes = 0;
     int btx = 0, bty = 0;                        // tiles per box (0: the whole grid)
@@ -841,7 +850,8 @@ struct Bilu0 : PcImpl {
         }
         if (pipelined) {
             const int W = fp32 ? 1 : 2;
-            const size_t fb = (size_t)NT * (g.nz + 7) * 24 * W * sizeof(uint64_t);
+            face_words = (int64_t)NT * (g.nz + 7) * 24 * W;
+            const size_t fb = (size_t)face_words * sizeof(uint64_t);
             // the sweeps keep a multi-slot ring in LDS: allow the full LDS per workgroup
             RSV_HIP(c, hipFuncSetAttribute((const void *)k_sweep<0, double, NLoad<0, double>::v>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max));
             RSV_HIP(c, hipFuncSetAttribute((const void *)k_sweep<1, double, NLoad<1, double>::v>, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max));
@@ -851,6 +861,11 @@ struct Bilu0 : PcImpl {
             if (s == RSV_OK) s = alloc((void **)&faceY, fb);
             if (s == RSV_OK) s = alloc((void **)&tile_order, (size_t)NT * sizeof(int32_t));
             if (s != RSV_OK) return s;
+            // no word may carry a tag before its first write (epochs are never 0)
+            const int nzb = (int)std::min<int64_t>((face_words + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_zero_words, dim3(nzb), dim3(256), 0, c->stream, face_words, faceX);
+            hipLaunchKernelGGL(k_zero_words, dim3(nzb), dim3(256), 0, c->stream, face_words, faceY);
+            RSV_LAUNCH(c);
             std::vector<int32_t> ord(NT);
             for (int t = 0; t < NT; ++t) ord[t] = t;
             // topological order: by anti-diagonal of the tile inside its box
