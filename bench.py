@@ -367,6 +367,52 @@ def poisson_measure(rsv, ctx, dims, parts, its=90, reps=3, cpu=True):
     return out
 
 
+# (grid, input channels, output channels) of the network's layers at the
+# 512x512x128 workload: level 0 full resolution, level 1 half, level 2 quarter
+CONV_LAYERS = [((512, 512, 128), 4, 16), ((512, 512, 128), 16, 16), ((512, 512, 128), 32, 16),
+               ((256, 256, 64), 16, 32), ((256, 256, 64), 32, 32), ((128, 128, 32), 32, 64),
+               ((128, 128, 32), 64, 64), ((256, 256, 64), 64, 32)]
+
+
+def conv_layers(rsv, torch, reps=5):
+    """Time single layers (`rsv_conv3d`: BF16 in, FP32 out, bias, weight
+    packing included): one untimed launch, then the mean of `reps`; prints
+    one JSON line."""
+    ctx = rsv.Context(0)
+    out = []
+    for dims, cin, cout in CONV_LAYERS:
+        V = dims[0] * dims[1] * dims[2]
+        gen = torch.Generator(device="cuda").manual_seed(cin * 100 + cout)
+        # BF16 bit patterns of finite values in [0, 0.5)
+        x = torch.randint(0, 0x3F00, (V * cin,), dtype=torch.int16, device="cuda", generator=gen)
+        w = torch.randn(27 * cin * cout, dtype=torch.float32, device="cuda", generator=gen) * 0.1
+        b = torch.zeros(cout, dtype=torch.float32, device="cuda")
+        y = torch.zeros(V * cout, dtype=torch.float32, device="cuda")
+        rsv.conv3d(ctx, dims, cin, cout, x, w, b, y)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            rsv.conv3d(ctx, dims, cin, cout, x, w, b, y)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / reps * 1e3
+        flop = 2 * 27 * cin * cout * V
+        out.append({"grid": list(dims), "cin": cin, "cout": cout, "ms": round(ms, 4),
+                    "TFLOPs": round(flop / ms / 1e9, 1), "of_bf16_peak": round(flop / ms / 1e9 / 2500.0, 4)})
+        log(f"conv {dims} {cin}->{cout}: {ms:.3f} ms")
+        del x, y
+    print(json.dumps({"conv_layers": out}), flush=True)
+    ctx.close()
+
+
+def copy_probe(torch, dev):
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy probe: 1073741824 bytes read, 1073741824 bytes written")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -389,6 +435,8 @@ def main():
                     help="grid:subdomains of the scalar Poisson run after the solves (empty: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with one device-to-device copy of 1 GiB (calibrates HBM byte counters)")
+    ap.add_argument("--conv-layers", action="store_true",
+                    help="only time single 3x3x3 convolution layers at the learned form's sizes and print them")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path",
@@ -403,6 +451,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.conv_layers:
+        conv_layers(rsv, torch)
+        if args.copy_probe:
+            copy_probe(torch, dev)
+        return
     wl = args.workload.upper()
     cfg = I.preset(wl, seed=args.seed)
     dforms, dextra = WORKLOAD_FORMS.get(wl, ("gmres_bilu0", ""))
@@ -751,12 +804,7 @@ def main():
     }
     print(json.dumps(line), flush=True)
     if args.copy_probe:
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy probe: 1073741824 bytes read, 1073741824 bytes written")
+        copy_probe(torch, dev)
     if not args.poisson:
         A.close()
     g.close(); ctx.close()
