@@ -132,7 +132,9 @@ WORKLOAD_FORMS = {
            "gmres_bilu0_dcgs2,gmres_ras64_fp32_dcgs2,bicgstab_ras64,gmres_ras64_iluk1,gmres_cpr_fpf,"
            "gmres_cpr_fpf_bilu0,bicgstab_cpr_fpf_bilu0,gmres_cpr_fpf_fp32,gmres_cpr_fpf_bilu0_fp32,gmres_ras64_ilut", ""),
     "C4": ("gmres_bilu0,gmres_bilu0_fp32", ""),
-    "C1": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0,gmres_ras64"),
+    # (RAS over 4x4x4 boxes of 5x5x2 cells stagnates on the literal C1 matrix,
+    # in the oracle as on the GPU: relative residual 2.8e-4 after 3000 steps)
+    "C1": ("gmres_bilu0,gmres_bilu0_fp32", "bicgstab_bilu0"),
 }
 
 
