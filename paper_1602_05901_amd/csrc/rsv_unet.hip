@@ -189,9 +189,12 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeo g, const uint16_t *__restr
 constexpr int CT_X = 16, CT_Y = 4, CT_Z = 4, CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2;
 constexpr int CH_N = CH_X * CH_Y * CH_Z;   // 648 halo voxels
 
+// the epilogue of one or two output blocks stages each wave's results in the
+// halo area ([64 voxels][16 NB + 1] floats per wave), made larger if needed
+__host__ __device__ constexpr size_t conv_stage_bytes(int nb) { return nb <= 2 ? (size_t)4 * 64 * (16 * nb + 1) * 4 : 0; }
 inline size_t conv_lds_bytes(int cin, int KB, int NB)
 {
-    return (size_t)CH_N * cin * 2 + (size_t)KB * NB * 64 * conv_frag_bytes(cin);
+    return std::max((size_t)CH_N * cin * 2, conv_stage_bytes(NB)) + (size_t)KB * NB * 64 * conv_frag_bytes(cin);
 }
 
 // Global -> LDS copy of n 16-byte words by the workgroup, eight loads in
@@ -289,36 +292,89 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvGeo g, const uint16_t *__r
                 for (int mb = 0; mb < CT_Y; ++mb) acc[mb][nb] = mfma_k(a[mb], bf, acc[mb][nb]);
             }
         }
-        // epilogue: the skip inputs are loaded together, then bias, skip, ReLU, store
-        const int z = z0 + wave;
-        float sk[NB][CT_Y][4];
+        if constexpr (NB <= 2) {
+            // epilogue through LDS (16 or 32 output channels): each wave puts
+            // its 64 voxels x 16 NB channels into the halo area, which no wave
+            // reads any more, then lane v takes voxel v whole (x = v % 16,
+            // y = v / 16), adds bias and skip, applies the ReLU and stores the
+            // voxel with 16-byte accesses instead of one channel per lane and store
+            constexpr int C = 16 * NB, SC = C + 1;          // channels; staging row (one word of padding)
+            float *stg = (float *)xl + wave * (64 * SC);
+            __syncthreads();   // every wave is done with the halo
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
+            for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int mb = 0; mb < CT_Y; ++mb)
+                for (int mb = 0; mb < CT_Y; ++mb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int x = x0 + mr + i, y = y0 + mb;
-                    sk[nb][mb][i] = 0.f;
-                    if (skip && x < g.nx && y < g.ny && z < g.nz)
-                        sk[nb][mb][i] = bf2f(skip[(x + (int64_t)g.nx * (y + (int64_t)g.ny * z)) * g.cout + nb * 16 + n]);
+                    for (int i = 0; i < 4; ++i) stg[(mb * 16 + mr + i) * SC + nb * 16 + n] = acc[mb][nb][i];
+            __syncthreads();
+            const int x = x0 + (lane & 15), y = y0 + (lane >> 4), z = z0 + wave;
+            if (x < g.nx && y < g.ny && z < g.nz) {
+                const int64_t vo = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+                float v[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) v[c] = stg[lane * SC + c] + (bias ? bias[c] : 0.f);
+                if (skip) {
+                    const uint4 *sp = (const uint4 *)(skip + vo * C);
+#pragma unroll
+                    for (int q = 0; q < C / 8; ++q) {
+                        const uint4 sq = sp[q];
+                        const uint32_t sw[4] = {sq.x, sq.y, sq.z, sq.w};
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) v[8 * q + c] += bf2f((uint16_t)(sw[c >> 1] >> (16 * (c & 1))));
+                    }
                 }
+                if (relu)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int co = nb * 16 + n;
-            const float bb = bias ? bias[co] : 0.f;
+                    for (int c = 0; c < C; ++c) v[c] = v[c] > 0.f ? v[c] : 0.f;
+                if (OUT_BF16) {
+                    uint4 *op = (uint4 *)((uint16_t *)out + vo * C);
 #pragma unroll
-            for (int mb = 0; mb < CT_Y; ++mb) {
-                const int y = y0 + mb;
+                    for (int q = 0; q < C / 8; ++q) {
+                        uint32_t pw[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int x = x0 + mr + i;
-                    if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
-                    const int64_t vo = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
-                    float val = acc[mb][nb][i] + bb + sk[nb][mb][i];
-                    if (relu) val = val > 0.f ? val : 0.f;
-                    if (OUT_BF16) ((uint16_t *)out)[vo * g.cout + co] = f2bf(val);
-                    else ((float *)out)[vo * g.cout + co] = val;
+                        for (int h = 0; h < 4; ++h)
+                            pw[h] = (uint32_t)f2bf(v[8 * q + 2 * h]) | ((uint32_t)f2bf(v[8 * q + 2 * h + 1]) << 16);
+                        op[q] = uint4{pw[0], pw[1], pw[2], pw[3]};
+                    }
+                } else {
+                    float4 *op = (float4 *)((float *)out + vo * C);
+#pragma unroll
+                    for (int q = 0; q < C / 4; ++q) op[q] = float4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+                }
+            }
+        } else {
+            // epilogue: the skip inputs are loaded together, then bias, skip, ReLU, store
+            const int z = z0 + wave;
+            float sk[NB][CT_Y][4];
+    #pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+    #pragma unroll
+                for (int mb = 0; mb < CT_Y; ++mb)
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int x = x0 + mr + i, y = y0 + mb;
+                        sk[nb][mb][i] = 0.f;
+                        if (skip && x < g.nx && y < g.ny && z < g.nz)
+                            sk[nb][mb][i] = bf2f(skip[(x + (int64_t)g.nx * (y + (int64_t)g.ny * z)) * g.cout + nb * 16 + n]);
+                    }
+    #pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int co = nb * 16 + n;
+                const float bb = bias ? bias[co] : 0.f;
+    #pragma unroll
+                for (int mb = 0; mb < CT_Y; ++mb) {
+                    const int y = y0 + mb;
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int x = x0 + mr + i;
+                        if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+                        const int64_t vo = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+                        float val = acc[mb][nb][i] + bb + sk[nb][mb][i];
+                        if (relu) val = val > 0.f ? val : 0.f;
+                        if (OUT_BF16) ((uint16_t *)out)[vo * g.cout + co] = f2bf(val);
+                        else ((float *)out)[vo * g.cout + co] = val;
+                    }
                 }
             }
         }
